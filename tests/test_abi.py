@@ -1,0 +1,85 @@
+"""The C-ABI library loads and exports every symbol include/rn.h declares.
+
+No device work here: only calls that fail argument checks before touching a
+GPU, plus the host-only partitioner entry point.
+"""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "rn.h")
+
+
+@pytest.fixture(scope="module")
+def rn():
+    from paper_1607_07696_amd import rn
+    rn.load_library()
+    return rn
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rn_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree(rn):
+    decl = declared_functions()
+    assert decl == sorted(rn.EXPORTS)
+
+
+def test_every_declared_symbol_is_exported(rn):
+    lib = rn.load_library()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_pair_layout_matches_header(rn):
+    assert rn.PAIR_DTYPE.itemsize == 12
+
+
+def test_graph_load_rejects_malformed_csr_before_device(rn):
+    lib = rn.load_library()
+    h = C.c_void_p()
+    rp = np.array([0, 1, 3], dtype=np.int32)
+    col = np.array([1, 0, 5], dtype=np.int32)   # 5 is out of range
+    w = np.array([1, 1, 1], dtype=np.uint32)
+    i32 = C.POINTER(C.c_int32)
+    st = lib.rn_graph_load(2, 3, rp.ctypes.data_as(i32), col.ctypes.data_as(i32),
+                           w.ctypes.data_as(C.POINTER(C.c_uint32)), C.byref(h))
+    assert st == rn.RN_ERR_ARG and not h.value
+    assert b"col" in lib.rn_last_error()
+    rp_bad = np.array([0, 2, 1], dtype=np.int32)
+    st = lib.rn_graph_load(2, 1, rp_bad.ctypes.data_as(i32), col.ctypes.data_as(i32),
+                           w.ctypes.data_as(C.POINTER(C.c_uint32)), C.byref(h))
+    assert st == rn.RN_ERR_ARG
+    st = lib.rn_graph_load(0, 0, rp.ctypes.data_as(i32), None, None, C.byref(h))
+    assert st == rn.RN_ERR_ARG
+
+
+def test_join_calls_reject_null_handle(rn):
+    lib = rn.load_library()
+    n = C.c_int64(7)
+    st = lib.rn_dist_join(None, None, 1, None, 1, 5, None, 0, C.byref(n), None)
+    assert st == rn.RN_ERR_ARG and n.value == 0
+    st = lib.rn_kcp_join(None, None, 1, None, 1, 5, None, 0, C.byref(n), None)
+    assert st == rn.RN_ERR_ARG
+    assert lib.rn_set_tuning(None, 0, 11) == rn.RN_ERR_ARG
+    assert lib.rn_graph_num_vertices(None) == 0
+    lib.rn_graph_free(None)
+
+
+def test_partition_host_argument_checks(rn, rg):
+    g = rg.road_graph(8, 0)
+    with pytest.raises(rn.RnError):
+        rn.partition_host(g.row_ptr, g.col, g.w, alpha=1.5)
+    with pytest.raises(rn.RnError):
+        rn.partition_host(g.row_ptr, g.col, g.w, max_leaf=0)
+
+
+def test_version(rn):
+    assert rn.load_library().rn_version().startswith(b"rn ")
