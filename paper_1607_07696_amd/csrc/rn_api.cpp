@@ -73,14 +73,14 @@ struct rn_graph {
     int hash_log2 = 11;
 
     // query buffers (grown on demand)
-    uint32_t *d_qblock = nullptr;  // QueryCtl | S bitmap | R bitmap, cleared as one
+    uint32_t *d_qblock = nullptr;  // QueryCtl | S bitmap | R bitmap | sort histograms, cleared as one
     size_t qblock_words = 0;
     int32_t *d_src = nullptr;
     uint32_t *d_ovf[kTiers] = {};
     size_t src_cap = 0;
     rn_pair *d_pairs[2] = {};
     unsigned long long pair_cap = 0;
-    uint32_t *d_hist = nullptr;
+    uint32_t *d_stage = nullptr;   // source-listing block sums
     uint32_t *d_gslots = nullptr;  // global-memory tier state (global_slot_words(V) per slot)
     uint32_t n_gslots = 0;
     QueryCtl *h_ctl = nullptr;     // pinned read-back of the control block
@@ -91,11 +91,13 @@ struct rn_graph {
     hipEvent_t ev[EV_COUNT] = {};
     rn_stats stats{};
 
-    size_t bitmap_words() const { return (static_cast<size_t>(V) + 31) / 32; }
+    // bitmap sizes rounded to 256-byte multiples keep every region 16-byte aligned
+    size_t bitmap_words() const { return ((static_cast<size_t>(V) + 31) / 32 + 63) / 64 * 64; }
     size_t ctl_words() const { return (sizeof(QueryCtl) + 255) / 256 * 64; }
     QueryCtl *d_ctl() const { return reinterpret_cast<QueryCtl *>(d_qblock); }
     uint32_t *d_sbits() const { return d_qblock + ctl_words(); }
     uint32_t *d_rbits() const { return d_qblock + ctl_words() + bitmap_words(); }
+    uint32_t *d_hist() const { return d_qblock + ctl_words() + 2 * bitmap_words(); }
 };
 
 namespace {
@@ -118,7 +120,7 @@ void release_buffers(rn_graph *g) {
     for (auto &p : g->d_ovf) dev_free(p);
     dev_free(g->d_pairs[0]);
     dev_free(g->d_pairs[1]);
-    dev_free(g->d_hist);
+    dev_free(g->d_stage);
     dev_free(g->d_gslots);
     g->n_gslots = 0;
     g->qblock_words = 0;
@@ -127,7 +129,7 @@ void release_buffers(rn_graph *g) {
 }
 
 rn_status ensure_query_buffers(rn_graph *g, int32_t nR) {
-    const size_t qwords = g->ctl_words() + 2 * g->bitmap_words();
+    const size_t qwords = g->ctl_words() + 2 * g->bitmap_words() + sort_hist_words();
     if (g->qblock_words < qwords) {
         dev_free(g->d_qblock);
         RN_HIP(dev_alloc(&g->d_qblock, qwords), "allocating query bitmaps");
@@ -141,7 +143,7 @@ rn_status ensure_query_buffers(rn_graph *g, int32_t nR) {
         for (auto &p : g->d_ovf) RN_HIP(dev_alloc(&p, cap), "allocating the re-run lists");
         g->src_cap = cap;
     }
-    if (!g->d_hist) RN_HIP(dev_alloc(&g->d_hist, sort_hist_words()), "allocating sort histograms");
+    if (!g->d_stage) RN_HIP(dev_alloc(&g->d_stage, stage_scratch_words(g->V)), "allocating staging scratch");
     if (!g->d_gslots) {
         // up to 64 concurrent global-tier searches, within 8 GiB
         const size_t words = global_slot_words(g->V);
@@ -429,7 +431,7 @@ rn_status run_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, 
         record(g, EV_START, stream);
         RN_HIP(launch_fill_u32(g->d_qblock, g->qblock_words, 0u, stream), "clearing query state");
         RN_HIP(launch_stage(R, nR, S, nS, g->V, g->d_rank, g->d_order, g->d_rbits(), g->d_sbits(),
-                            g->d_src, ctl, stream),
+                            g->d_src, ctl, g->d_stage, stream),
                "staging the query");
         record(g, EV_STAGED, stream);
         for (int t = 0; t < ntiers; ++t) {
@@ -458,13 +460,10 @@ rn_status run_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, 
         }
         record(g, EV_RELAXED, stream);
         record(g, EV_SELECTED, stream);
-        rn_pair *sorted = nullptr;
-        RN_HIP(launch_sort_pairs(g->d_pairs[0], g->d_pairs[1], &ctl->npairs, g->pair_cap, bound, g->V,
-                                 g->d_hist, &sorted, stream),
+        RN_HIP(launch_sort_to_out(g->d_pairs[0], g->d_pairs[1], &ctl->npairs, g->pair_cap, bound, g->V,
+                                  g->d_hist(), out, static_cast<unsigned long long>(cap), ctl,
+                                  ntiers - 1, stream),
                "sorting pairs");
-        RN_HIP(launch_copy_out(sorted, out, ctl, static_cast<unsigned long long>(cap), g->pair_cap,
-                               ntiers - 1, stream),
-               "copying pairs out");
         record(g, EV_DONE, stream);
         RN_HIP(hipMemcpyAsync(g->h_ctl, ctl, sizeof(QueryCtl), hipMemcpyDeviceToHost, stream),
                "reading the query status");

@@ -76,7 +76,9 @@ inline size_t global_slot_words(int32_t V) {
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_stage(const int32_t *R, int32_t nR, const int32_t *S, int32_t nS, int32_t V,
                         const int32_t *rank, const int32_t *order, uint32_t *rbits,
-                        uint32_t *sbits, int32_t *src, QueryCtl *ctl, hipStream_t s);
+                        uint32_t *sbits, int32_t *src, QueryCtl *ctl, uint32_t *scratch,
+                        hipStream_t s);
+size_t stage_scratch_words(int32_t V);
 // Relaxation at table tier `tier` (log2 size hash_log2); grid chosen inside.
 hipError_t launch_join(const JoinArgs &a, int hash_log2, uint32_t max_sources, hipStream_t s);
 int join_tier_supported(int hash_log2);
@@ -84,10 +86,14 @@ int join_tier_supported(int hash_log2);
 // global_slot_words(V) words each.
 hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslots, int32_t V,
                               uint32_t max_sources, hipStream_t s);
-// Sort pairs[0 .. min(*n, cap)) by (dist, u, v); result in *out_buf (one of a, b).
-hipError_t launch_sort_pairs(rn_pair *a, rn_pair *b, const unsigned long long *n,
-                             unsigned long long cap, uint32_t max_dist, int32_t V,
-                             uint32_t *hist, rn_pair **out_buf, hipStream_t s);
+// Sort pairs[0 .. min(*n, cap)) by (dist, u, v) (scratch: another buffer of
+// cap pairs) and write them to out when the query succeeded and the result
+// fits (no argument error, no search left over, *n <= user_cap, *n <= cap).
+// hist: sort_hist_words() words, zero on entry.  max_dist bounds every dist.
+hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned long long *n,
+                              unsigned long long cap, uint32_t max_dist, int32_t V, uint32_t *hist,
+                              rn_pair *out, unsigned long long user_cap, const QueryCtl *ctl,
+                              int last_tier, hipStream_t s);
 size_t sort_hist_words();
 // Copy sorted pairs to the caller when the query succeeded and fits.
 hipError_t launch_copy_out(const rn_pair *src, rn_pair *dst, const QueryCtl *ctl,

@@ -25,7 +25,7 @@ namespace {
 
 constexpr uint32_t kEmpty = 0x7FFFFFFFu;  // empty table key (never a vertex id)
 constexpr uint32_t kPend = 0x80000000u;   // key flag: the vertex is in the pending list
-constexpr uint32_t kWin = 256;            // arcs expanded per window (4 per lane)
+constexpr uint32_t kWin = 256;            // frontier arcs expanded per window (4 per lane)
 
 // ------------------------------------------------------------------ wave helpers
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63u; }
@@ -37,20 +37,41 @@ __device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
 
 __device__ __forceinline__ uint32_t popc(uint64_t m) { return static_cast<uint32_t>(__popcll(m)); }
 
-__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v = min(v, static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), o)));
-    return v;
+// Cross-lane move through DPP: lanes without a source (or masked off) get `identity`.
+// Controls used: row_shr:n = 0x110 + n, row_bcast:15 = 0x142, row_bcast:31 = 0x143.
+template <int CTRL, int ROW_MASK = 0xf, int BANK_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp(uint32_t v, uint32_t identity) {
+    return static_cast<uint32_t>(__builtin_amdgcn_update_dpp(static_cast<int>(identity), static_cast<int>(v),
+                                                             CTRL, ROW_MASK, BANK_MASK, false));
 }
 
+__device__ __forceinline__ uint32_t readlane(uint32_t v, int lane) {
+    return static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(v), lane));
+}
+
+// Inclusive prefix sum over the 64 lanes: sums within 16-lane rows (shifts by
+// 1, 2, 3, then 4 and 8 on the upper banks), then row totals carried across
+// rows with the two row broadcasts.
 __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
-    const uint32_t lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t t = static_cast<uint32_t>(__shfl_up(static_cast<int>(v), o));
-        if (lane >= static_cast<uint32_t>(o)) v += t;
-    }
-    return v;
+    uint32_t s = v + dpp<0x111>(v, 0u);
+    s += dpp<0x112>(v, 0u);
+    s += dpp<0x113>(v, 0u);
+    s += dpp<0x114, 0xf, 0xe>(s, 0u);
+    s += dpp<0x118, 0xf, 0xc>(s, 0u);
+    s += dpp<0x142, 0xa, 0xf>(s, 0u);
+    s += dpp<0x143, 0xc, 0xf>(s, 0u);
+    return s;
+}
+
+// Minimum over the 64 lanes, returned to every lane.
+__device__ __forceinline__ uint32_t wave_min(uint32_t v) {
+    v = min(v, dpp<0x111>(v, kInf));
+    v = min(v, dpp<0x112>(v, kInf));
+    v = min(v, dpp<0x114>(v, kInf));
+    v = min(v, dpp<0x118>(v, kInf));
+    v = min(v, dpp<0x142, 0xa, 0xf>(v, kInf));
+    v = min(v, dpp<0x143, 0xc, 0xf>(v, kInf));
+    return readlane(v, 63);
 }
 
 // Make this wave's LDS writes visible to its other lanes before they read.
@@ -78,8 +99,8 @@ __device__ __forceinline__ void lds_store(uint32_t *p, uint32_t v) {
 }
 
 // ------------------------------------------------------------------ per-source search state
-// PC bounds the pending set and the frontier of one bucket; the table holds
-// every vertex reached within the bound.
+// H: distance-table slots (open addressing, linear probing, filled to at most
+// 3/4).  PC: capacity of each vertex list (pending set, frontier).
 template <int HB>
 struct Tier {
     static constexpr int H = 1 << HB;
@@ -91,72 +112,20 @@ template <int HB>
 struct SearchLds {
     static constexpr int H = Tier<HB>::H;
     static constexpr int PC = Tier<HB>::PC;
-    uint32_t key[H];    // vertex id | kPend, or kEmpty
-    uint32_t dist[H];   // tentative distance (kInf when empty)
-    uint32_t pslot[PC]; // pending list: table slot, arc range
-    int32_t pbeg[PC];
-    int32_t pend[PC];
-    int32_t fbeg[PC];   // frontier of the current phase: arc range and distance
-    int32_t fend[PC];   //   (reused as the emission staging area at the end)
-    uint32_t fd[PC];
-    uint8_t own[kWin];  // window arc -> owning frontier lane
+    uint32_t key[H];            // vertex id | kPend, or kEmpty
+    uint32_t dist[H];           // tentative distance (kInf when empty)
+    uint32_t slot[2][PC + 1];   // two vertex lists: table slot and arc range;
+    int32_t beg[2][PC + 1];     //   entry PC of each is a write sink for lanes
+    int32_t end[2][PC + 1];     //   that have nothing to store
+    uint8_t own[kWin];          // window arc -> owning frontier lane
 };
 
 struct WaveState {
-    uint32_t np;    // pending count
+    uint32_t np;    // entries in the pending list
     uint32_t nins;  // table entries in use
-    uint32_t imin;  // per-lane min of improved distances this phase
+    uint32_t imin;  // per-lane min of the distances improved this phase
     bool ovf;       // the search outgrew this tier
 };
-
-// Relax one arc per lane (act lanes), then append newly pending vertices.
-// Must be called by all 64 lanes; st.ovf is wave-uniform afterwards.
-template <int HB>
-__device__ __forceinline__ void relax_append(SearchLds<HB> &L, WaveState &st, bool act, int32_t y,
-                                             uint32_t nd, int32_t yb, int32_t ye) {
-    constexpr int H = Tier<HB>::H;
-    constexpr int PC = Tier<HB>::PC;
-    bool ins = false, app = false, lost = false;
-    uint32_t h = 0;
-    if (act) {
-        h = slot_hash<HB>(static_cast<uint32_t>(y));
-        bool found = false;
-        for (int probe = 0; probe < H; ++probe) {
-            uint32_t k = lds_load(&L.key[h]);
-            if ((k & ~kPend) == static_cast<uint32_t>(y)) { found = true; break; }
-            if (k == kEmpty) {
-                uint32_t old = atomicCAS(&L.key[h], kEmpty, static_cast<uint32_t>(y));
-                if (old == kEmpty) { ins = true; found = true; break; }
-                if ((old & ~kPend) == static_cast<uint32_t>(y)) { found = true; break; }
-            }
-            h = (h + 1) & (H - 1);
-        }
-        if (found) {
-            uint32_t old = atomicMin(&L.dist[h], nd);
-            if (nd < old) {
-                st.imin = min(st.imin, nd);
-                uint32_t ko = atomicOr(&L.key[h], kPend);
-                app = (ko & kPend) == 0;
-            }
-        } else {
-            lost = true;
-        }
-    }
-    const uint64_t mI = __ballot(ins), mA = __ballot(app), mL = __ballot(lost);
-    st.nins += popc(mI);
-    const uint32_t na = popc(mA);
-    if (mL != 0 || st.nins > (3u * H) / 4u || st.np + na > static_cast<uint32_t>(PC)) {
-        st.ovf = true;
-        return;
-    }
-    if (app) {
-        const uint32_t r = st.np + mbcnt(mA);
-        L.pslot[r] = h;
-        L.pbeg[r] = yb;
-        L.pend[r] = ye;
-    }
-    st.np += na;
-}
 
 __device__ __forceinline__ uint32_t current_bound(const JoinArgs &a) {
     if (!a.kcp) return a.theta;
@@ -164,24 +133,147 @@ __device__ __forceinline__ uint32_t current_bound(const JoinArgs &a) {
     return min(t, a.theta);
 }
 
-// Write this wave's staged pairs (L.fbeg = v, L.fd = dist) for source u.
+// Relax NJ window arcs per lane (slot j holds window arc j*64 + lane) and
+// append targets that became pending to list P.  Each step (first probe,
+// claim, min, pending flag) is issued for all NJ slots before any result is
+// used, so the slots' LDS latencies overlap; idle lanes issue no-op atomics
+// instead of branching.  Called by all 64 lanes; st.ovf is wave-uniform
+// afterwards.
+template <int HB, int NJ>
+__device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, uint32_t P,
+                                             const ArcRec *r, const uint32_t *nd, uint32_t bound) {
+    constexpr uint32_t H = Tier<HB>::H;
+    constexpr uint32_t PC = Tier<HB>::PC;
+    // slot states: 0 idle, 1 slot holds y, 2 slot claimed for y, 3 keep probing, 4 home slot empty
+    uint32_t h[NJ], k[NJ], stt[NJ], old[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) h[j] = slot_hash<HB>(static_cast<uint32_t>(r[j].y));
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) k[j] = lds_load(&L.key[h[j]]);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const uint32_t y = static_cast<uint32_t>(r[j].y);
+        stt[j] = nd[j] > bound ? 0u : ((k[j] & ~kPend) == y ? 1u : (k[j] == kEmpty ? 4u : 3u));
+    }
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+        old[j] = atomicCAS(&L.key[h[j]], stt[j] == 4u ? kEmpty : 0xFFFFFFFFu, static_cast<uint32_t>(r[j].y));
+    bool probe = false;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const uint32_t y = static_cast<uint32_t>(r[j].y);
+        if (stt[j] == 4u) stt[j] = old[j] == kEmpty ? 2u : ((old[j] & ~kPend) == y ? 1u : 3u);
+        probe |= stt[j] == 3u;
+    }
+    bool lost = false;
+    if (__ballot(probe) != 0) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            if (stt[j] == 3u) {  // linear probing past an occupied home slot
+                const uint32_t y = static_cast<uint32_t>(r[j].y);
+                uint32_t hh = h[j];
+                for (uint32_t q = 1; q < H; ++q) {
+                    hh = (hh + 1) & (H - 1);
+                    const uint32_t kk = lds_load(&L.key[hh]);
+                    if ((kk & ~kPend) == y) { stt[j] = 1u; break; }
+                    if (kk == kEmpty) {
+                        const uint32_t o = atomicCAS(&L.key[hh], kEmpty, y);
+                        if (o == kEmpty) { stt[j] = 2u; break; }
+                        if ((o & ~kPend) == y) { stt[j] = 1u; break; }
+                    }
+                }
+                if (stt[j] == 3u) lost = true;
+                h[j] = hh;
+            }
+        }
+    }
+    uint32_t v[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        v[j] = (stt[j] == 1u || stt[j] == 2u) ? nd[j] : kInf;
+        old[j] = atomicMin(&L.dist[h[j]], v[j]);
+    }
+    bool imp[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        imp[j] = v[j] < old[j];
+        old[j] = atomicOr(&L.key[h[j]], imp[j] ? kPend : 0u);
+    }
+    uint64_t mA[NJ];
+    uint32_t nadd = 0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const bool app = imp[j] && (old[j] & kPend) == 0;
+        st.imin = min(st.imin, imp[j] ? nd[j] : kInf);
+        st.nins += popc(__ballot(stt[j] == 2u));
+        mA[j] = __ballot(app);
+        nadd += popc(mA[j]);
+    }
+    if (__ballot(lost) != 0 || st.nins > (3u * H) / 4u || st.np + nadd > PC) {
+        st.ovf = true;
+        return;
+    }
+    uint32_t base = st.np;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const bool app = (mA[j] >> lane_id()) & 1u;
+        const uint32_t idx = app ? base + mbcnt(mA[j]) : PC;
+        L.slot[P][idx] = h[j];
+        L.beg[P][idx] = r[j].ybeg;
+        L.end[P][idx] = r[j].yend;
+        base += popc(mA[j]);
+    }
+    st.np = base;
+}
+
+// Load window arcs j*64 + lane (j < NJ) of the flattened frontier arc list
+// and relax them.  Every load is issued before any is used; lanes past the
+// window's end load arc 0 and stay idle.
+template <int HB, int NJ>
+__device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, uint32_t P,
+                                            const ArcRec *__restrict__ arcs, uint32_t cnt, uint32_t wb,
+                                            int32_t b, uint32_t excl, uint32_t d, uint32_t bound) {
+    const uint32_t lane = lane_id();
+    int32_t idx[NJ];
+    uint32_t od[NJ];
+    bool act[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const uint32_t t = j * 64 + lane;
+        act[j] = t < cnt;
+        const uint32_t o = L.own[act[j] ? t : 0u];
+        const int32_t ob = __shfl(b, static_cast<int>(o));
+        const uint32_t ox = static_cast<uint32_t>(__shfl(static_cast<int>(excl), static_cast<int>(o)));
+        od[j] = static_cast<uint32_t>(__shfl(static_cast<int>(d), static_cast<int>(o)));
+        idx[j] = act[j] ? ob + static_cast<int32_t>(wb + t - ox) : 0;
+    }
+    ArcRec r[NJ];
+    uint32_t nd[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) r[j] = arcs[idx[j]];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) nd[j] = act[j] ? sat_add(od[j], r[j].w) : kInf;
+    wave_sync();  // own[] fully read before the next window rewrites it
+    relax_window<HB, NJ>(L, st, P, r, nd, bound);
+}
+
+// Write this wave's staged pairs (L.beg[0] = v, L.end[0] = dist) for source u.
 template <int HB>
 __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a, int32_t u,
                                             uint32_t &nst) {
     if (nst == 0) return;
     unsigned long long base = 0;
     if (lane_id() == 0) base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(nst));
-    const uint32_t lo = static_cast<uint32_t>(__shfl(static_cast<int>(base & 0xFFFFFFFFull), 0));
-    const uint32_t hi = static_cast<uint32_t>(__shfl(static_cast<int>(base >> 32), 0));
-    base = (static_cast<unsigned long long>(hi) << 32) | lo;
+    base = (static_cast<unsigned long long>(readlane(static_cast<uint32_t>(base >> 32), 0)) << 32) |
+           readlane(static_cast<uint32_t>(base), 0);
     wave_sync();
     for (uint32_t i = lane_id(); i < nst; i += 64) {
         const unsigned long long idx = base + i;
         if (idx < a.pair_cap) {
             rn_pair p;
             p.u = u;
-            p.v = L.fbeg[i];
-            p.dist = L.fd[i];
+            p.v = L.beg[0][i];
+            p.dist = static_cast<uint32_t>(L.end[0][i]);
             a.pairs[idx] = p;
         }
     }
@@ -190,16 +282,19 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
 }
 
 // Bounded search from u.  Bucket b holds tentative distances in
-// [b*delta, (b+1)*delta); each phase takes every pending vertex of the lowest
-// non-empty bucket, expands its arcs and relaxes their targets.  With
-// delta <= the smallest arc weight each vertex is expanded once, at its final
-// distance (Dijkstra order by buckets); a larger delta trades re-expansions for
-// fewer phases, and delta = 0 expands the whole pending set every phase.  The
-// search ends when nothing is pending; every table entry then holds its exact
-// distance, and entries in S become pairs.
+// [b*delta, (b+1)*delta); each phase expands every pending vertex of the
+// lowest non-empty bucket and relaxes its arcs.  With delta <= the smallest
+// arc weight each vertex is expanded once, at its final distance (Dijkstra
+// order by buckets); a larger delta trades re-expansions for fewer phases, and
+// delta = 0 expands the whole pending set every phase (the pending list simply
+// becomes the next frontier).  A vertex's distance is read when its frontier
+// chunk is expanded, so improvements made earlier in the same phase are used
+// at once.  The search ends when nothing is pending; every table entry then
+// holds its exact distance, and entries in S become pairs.
 template <int HB>
 __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
     constexpr int H = Tier<HB>::H;
+    constexpr int PC = Tier<HB>::PC;
     constexpr int U = Tier<HB>::U;
     const uint32_t lane = lane_id();
     const int32_t ub = a.row_ptr[u];
@@ -208,111 +303,94 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
         const uint32_t h0 = slot_hash<HB>(static_cast<uint32_t>(u));   // table is empty
         lds_store(&L.key[h0], static_cast<uint32_t>(u) | kPend);
         L.dist[h0] = 0;
-        L.pslot[0] = h0;
-        L.pbeg[0] = ub;
-        L.pend[0] = ue;
+        L.slot[0][0] = h0;
+        L.beg[0][0] = ub;
+        L.end[0][0] = ue;
     }
     wave_sync();
     WaveState st;
     st.np = 1;
     st.nins = 1;
     st.ovf = false;
+    uint32_t P = 0;      // list receiving appends (the pending list)
     uint32_t pmin = 0;
     uint32_t bound = a.theta;
 
     while (st.np > 0) {
         bound = current_bound(a);
-        uint32_t thr = kInf;
-        if (a.delta != 0) {
-            const uint64_t t = (static_cast<uint64_t>(pmin / a.delta) + 1ull) * a.delta;
-            thr = t > kInf ? kInf : static_cast<uint32_t>(t);
+        uint32_t F, nf;
+        uint32_t kmin = kInf;
+        if (a.delta == 0) {
+            F = P;
+            nf = st.np;
+            P ^= 1u;
+            st.np = 0;
+        } else {
+            const uint64_t t64 = (static_cast<uint64_t>(pmin / a.delta) + 1ull) * a.delta;
+            const uint32_t thr = t64 > kInf ? kInf : static_cast<uint32_t>(t64);
+            F = P ^ 1u;
+            nf = 0;
+            uint32_t nk = 0;
+            for (uint32_t base = 0; base < st.np; base += 64) {
+                const uint32_t i = base + lane;
+                const bool valid = i < st.np;
+                const uint32_t ic = valid ? i : 0u;
+                const uint32_t s = L.slot[P][ic];
+                const int32_t b = L.beg[P][ic];
+                const int32_t e = L.end[P][ic];
+                const uint32_t d = L.dist[s];
+                const bool isF = valid && d < thr && d <= bound;
+                const bool isK = valid && d >= thr && d <= bound;
+                const bool drop = valid && d > bound;
+                const uint64_t mF = __ballot(isF), mK = __ballot(isK);
+                wave_sync();  // every lane has read its entry before the in-place compaction
+                atomicAnd(&L.key[s], drop ? ~kPend : 0xFFFFFFFFu);
+                const uint32_t fi = isF ? nf + mbcnt(mF) : static_cast<uint32_t>(PC);
+                L.slot[F][fi] = s;
+                L.beg[F][fi] = b;
+                L.end[F][fi] = e;
+                const uint32_t ki = isK ? nk + mbcnt(mK) : static_cast<uint32_t>(PC);
+                L.slot[P][ki] = s;
+                L.beg[P][ki] = b;
+                L.end[P][ki] = e;
+                kmin = min(kmin, isK ? d : kInf);
+                nf += popc(mF);
+                nk += popc(mK);
+            }
+            st.np = nk;
         }
-        // ---- split the pending list into this phase's frontier and the rest
-        uint32_t nf = 0, nk = 0, kmin = kInf;
-        for (uint32_t base = 0; base < st.np; base += 64) {
-            const uint32_t i = base + lane;
-            const bool valid = i < st.np;
-            uint32_t s = 0, d = kInf;
-            int32_t b = 0, e = 0;
-            if (valid) {
-                s = L.pslot[i];
-                b = L.pbeg[i];
-                e = L.pend[i];
-                d = L.dist[s];
-            }
-            const bool isF = valid && d < thr && d <= bound;
-            const bool isK = valid && d >= thr && d <= bound;
-            const uint64_t mF = __ballot(isF), mK = __ballot(isK);
-            wave_sync();  // every lane has read its entry before the in-place compaction
-            if (valid && !isK) atomicAnd(&L.key[s], ~kPend);
-            if (isF) {
-                const uint32_t r = nf + mbcnt(mF);
-                L.fbeg[r] = b;
-                L.fend[r] = e;
-                L.fd[r] = d;
-            }
-            if (isK) {
-                const uint32_t r = nk + mbcnt(mK);
-                L.pslot[r] = s;
-                L.pbeg[r] = b;
-                L.pend[r] = e;
-                kmin = min(kmin, d);
-            }
-            nf += popc(mF);
-            nk += popc(mK);
-        }
-        st.np = nk;
         st.imin = kInf;
         wave_sync();
         // ---- expand the frontier, kWin arcs at a time
         for (uint32_t fb = 0; fb < nf && !st.ovf; fb += 64) {
             const uint32_t f = fb + lane;
-            int32_t b = 0, e = 0;
-            uint32_t d = 0;
-            if (f < nf) {
-                b = L.fbeg[f];
-                e = L.fend[f];
-                d = L.fd[f];
-            }
-            const uint32_t deg = static_cast<uint32_t>(e - b);
+            const bool valid = f < nf;
+            const uint32_t fc = valid ? f : 0u;
+            const uint32_t s = L.slot[F][fc];
+            const int32_t b = L.beg[F][fc];
+            const int32_t e = L.end[F][fc];
+            const uint32_t d = L.dist[s];
+            atomicAnd(&L.key[s], valid ? ~kPend : 0xFFFFFFFFu);  // expanded now: no longer pending
+            const uint32_t deg = (valid && d <= bound) ? static_cast<uint32_t>(e - b) : 0u;
             const uint32_t incl = wave_incl_scan(deg);
             const uint32_t excl = incl - deg;
-            const uint32_t total = static_cast<uint32_t>(__shfl(static_cast<int>(incl), 63));
+            const uint32_t total = readlane(incl, 63);
             for (uint32_t wb = 0; wb < total && !st.ovf; wb += kWin) {
                 const uint32_t lo = max(excl, wb), hi = min(excl + deg, wb + kWin);
                 for (uint32_t p = lo; p < hi; ++p) L.own[p - wb] = static_cast<uint8_t>(lane);
                 wave_sync();
                 const uint32_t cnt = min(kWin, total - wb);
-                ArcRec r[kWin / 64];
-                uint32_t nd[kWin / 64];
-#pragma unroll
-                for (int j = 0; j < static_cast<int>(kWin / 64); ++j) {
-                    const uint32_t t = j * 64 + lane;
-                    const bool act = t < cnt;
-                    const uint32_t o = act ? L.own[t] : 0u;
-                    const int32_t ob = __shfl(b, static_cast<int>(o));
-                    const uint32_t ox = static_cast<uint32_t>(__shfl(static_cast<int>(excl), static_cast<int>(o)));
-                    const uint32_t od = static_cast<uint32_t>(__shfl(static_cast<int>(d), static_cast<int>(o)));
-                    nd[j] = kInf;
-                    r[j].y = 0;
-                    r[j].ybeg = 0;
-                    r[j].yend = 0;
-                    if (act) {
-                        r[j] = a.arcs[ob + static_cast<int32_t>(wb + t - ox)];
-                        nd[j] = sat_add(od, r[j].w);
-                    }
-                }
-                wave_sync();  // own[] fully read before the next window rewrites it
-#pragma unroll
-                for (int j = 0; j < static_cast<int>(kWin / 64); ++j) {
-                    relax_append<HB>(L, st, nd[j] <= bound, r[j].y, nd[j], r[j].ybeg, r[j].yend);
-                    if (st.ovf) break;
+                switch ((cnt + 63u) / 64u) {
+                    case 1: window_step<HB, 1>(L, st, P, a.arcs, cnt, wb, b, excl, d, bound); break;
+                    case 2: window_step<HB, 2>(L, st, P, a.arcs, cnt, wb, b, excl, d, bound); break;
+                    case 3: window_step<HB, 3>(L, st, P, a.arcs, cnt, wb, b, excl, d, bound); break;
+                    default: window_step<HB, 4>(L, st, P, a.arcs, cnt, wb, b, excl, d, bound); break;
                 }
                 wave_sync();
             }
         }
-        pmin = min(wave_min(kmin), wave_min(st.imin));
         if (st.ovf) break;
+        if (a.delta != 0) pmin = min(wave_min(kmin), wave_min(st.imin));
     }
 
     // ---- emit table entries in S, and clear the table for the next source
@@ -350,13 +428,11 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
             const uint32_t y = k[j] & ~kPend;
             const bool m = !st.ovf && k[j] != kEmpty && ((sb[j] >> (y & 31u)) & 1u) && d[j] <= bound;
             const uint64_t mM = __ballot(m);
-            if (m) {
-                const uint32_t r = nst + mbcnt(mM);
-                L.fbeg[r] = static_cast<int32_t>(y);
-                L.fd[r] = d[j];
-            }
+            const uint32_t idx = m ? nst + mbcnt(mM) : static_cast<uint32_t>(PC);
+            L.beg[0][idx] = static_cast<int32_t>(y);
+            L.end[0][idx] = static_cast<int32_t>(d[j]);
             nst += popc(mM);
-            if (nst + 64 > static_cast<uint32_t>(Tier<HB>::PC)) {
+            if (nst + 64 > static_cast<uint32_t>(PC)) {
                 wave_sync();
                 flush_pairs<HB>(L, a, u, nst);
             }
@@ -565,38 +641,204 @@ __global__ void k_overlap(const int32_t *R, int32_t nR, int32_t V, const uint32_
     if (u >= 0 && u < V && ((sbits[u >> 5] >> (u & 31)) & 1u)) atomicOr(&ctl->err, kErrOverlap);
 }
 
-// List the marked ranks in increasing order as vertex ids (one block).
-__global__ __launch_bounds__(1024) void k_compact(const uint32_t *rbits, uint32_t nwords,
-                                                  const int32_t *order, int32_t *src,
-                                                  QueryCtl *ctl) {
-    __shared__ uint32_t wsum[16];
+// Block-wide exclusive scan of one value per thread (blockDim.x = 1024); *total
+// receives the block sum.  Uses wsum[16] in LDS.
+__device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t *wsum, uint32_t *total) {
     const uint32_t tid = threadIdx.x;
-    const uint32_t per = (nwords + 1023u) / 1024u;
-    const uint32_t beg = min(nwords, tid * per), end = min(nwords, beg + per);
-    uint32_t c = 0;
-    for (uint32_t w = beg; w < end; ++w) c += __popc(rbits[w]);
-    const uint32_t incl = wave_incl_scan(c);
+    const uint32_t incl = wave_incl_scan(v);
     if ((tid & 63u) == 63u) wsum[tid >> 6] = incl;
     __syncthreads();
-    uint32_t off = 0;
-    for (uint32_t w = 0; w < (tid >> 6); ++w) off += wsum[w];
-    uint32_t pos = off + incl - c;
-    for (uint32_t w = beg; w < end; ++w) {
-        uint32_t bits = rbits[w];
-        while (bits) {
-            const uint32_t b = __ffs(bits) - 1u;
-            const int32_t r = static_cast<int32_t>(w * 32u + b);
-            src[pos++] = order ? order[r] : r;
-            bits &= bits - 1u;
-        }
+    uint32_t off = 0, all = 0;
+    for (uint32_t w = 0; w < 16; ++w) {
+        const uint32_t x = wsum[w];
+        off += w < (tid >> 6) ? x : 0u;
+        all += x;
     }
-    if (tid == 1023u) ctl->nsrc = pos;
+    __syncthreads();
+    *total = all;
+    return off + incl - v;
+}
+
+// Source listing, pass 1: marked ranks per 1024-word block of the rank bitmap.
+__global__ __launch_bounds__(1024) void k_rank_count(const uint32_t *rbits, uint32_t nwords,
+                                                     uint32_t *bsum) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t i = blockIdx.x * 1024u + threadIdx.x;
+    uint32_t total;
+    block_excl_scan_1024(i < nwords ? __popc(rbits[i]) : 0u, wsum, &total);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+// Source listing, pass 2: list the marked ranks in increasing order as vertex ids.
+__global__ __launch_bounds__(1024) void k_rank_emit(const uint32_t *rbits, uint32_t nwords,
+                                                    const uint32_t *bsum, const int32_t *order,
+                                                    int32_t *src, QueryCtl *ctl) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t tid = threadIdx.x;
+    uint32_t acc = 0;
+    for (uint32_t j = tid; j < blockIdx.x; j += 1024) acc += bsum[j];
+    uint32_t pre;
+    block_excl_scan_1024(acc, wsum, &pre);
+    const uint32_t i = blockIdx.x * 1024u + tid;
+    uint32_t bits = i < nwords ? rbits[i] : 0u;
+    uint32_t total;
+    uint32_t pos = pre + block_excl_scan_1024(__popc(bits), wsum, &total);
+    while (bits) {
+        const uint32_t b = __ffs(bits) - 1u;
+        const int32_t r = static_cast<int32_t>(i * 32u + b);
+        src[pos++] = order ? order[r] : r;
+        bits &= bits - 1u;
+    }
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) ctl->nsrc = pre + total;
 }
 
 // ------------------------------------------------------------------ radix sort
-constexpr uint32_t kSortBlocks = 256;
+// Pairs are ordered by the key (dist, u, v).  When dist and the two ids fit in
+// 64 bits the pairs are packed into uint64 keys dist:u:v (vb bits per id) and
+// sorted by one launch per 8-bit digit: each pass takes its block offsets from
+// a per-tile digit histogram, which the previous pass accumulated for the
+// tiles its items landed in.  Otherwise a two-launch-per-digit sort of the
+// 12-byte records is used.
+constexpr uint32_t kSortBlocks = 64;
+constexpr uint32_t kSortPassesMax = 8;
 
-// 8-bit digit at `bit` of the key (dist, u, v) packed as dist:u:v with vb bits per id.
+__device__ __forceinline__ void sort_tile(const unsigned long long *nptr, unsigned long long cap,
+                                          uint64_t &beg, uint64_t &end, uint64_t &tile) {
+    const uint64_t n = min(static_cast<uint64_t>(*nptr), static_cast<uint64_t>(cap));
+    tile = (n + gridDim.x - 1) / gridDim.x;
+    if (tile == 0) tile = 1;
+    beg = min(n, blockIdx.x * tile);
+    end = min(n, beg + tile);
+}
+
+// Stable within-block ranking of one 256-item chunk by an 8-bit digit:
+// returns the rank among earlier items with the same digit; wcnt[w][d]
+// receives wave w's count of digit d.  Ends with the block synchronised.
+__device__ __forceinline__ uint32_t chunk_rank(bool act, uint32_t dg, uint32_t (*wcnt)[256]) {
+    const uint32_t tid = threadIdx.x, wave = tid >> 6;
+    uint64_t peers = __ballot(act);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+        const bool set = (dg >> b) & 1u;
+        const uint64_t m = __ballot(act && set);
+        peers &= set ? m : ~m;
+    }
+    const uint32_t wrank = mbcnt(peers);
+    if (act && wrank == 0) wcnt[wave][dg] = popc(peers);
+    __syncthreads();
+    uint32_t off = 0;
+    for (uint32_t w = 0; w < wave; ++w) off += act ? wcnt[w][dg] : 0u;
+    return off + wrank;
+}
+
+// Exclusive scan over 256 threads (4 waves) through LDS scratch ws[4].
+__device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *ws) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t incl = wave_incl_scan(v);
+    if ((tid & 63u) == 63u) ws[tid >> 6] = incl;
+    __syncthreads();
+    uint32_t off = 0;
+    for (uint32_t w = 0; w < (tid >> 6); ++w) off += ws[w];
+    __syncthreads();
+    return off + incl - v;
+}
+
+// This block's first output position for each digit (thread d computes digit
+// d from its row of kSortBlocks counts, read as independent 16-byte loads).
+__device__ __forceinline__ uint32_t digit_base(const uint32_t *hist, uint32_t *ws) {
+    const uint32_t tid = threadIdx.x, blk = blockIdx.x;
+    const uint4 *row = reinterpret_cast<const uint4 *>(hist + tid * kSortBlocks);
+    uint4 v[kSortBlocks / 4];
+#pragma unroll
+    for (uint32_t q = 0; q < kSortBlocks / 4; ++q) v[q] = row[q];
+    uint32_t tot = 0, pre = 0;
+#pragma unroll
+    for (uint32_t q = 0; q < kSortBlocks / 4; ++q) {
+        const uint32_t b = 4 * q;
+        tot += v[q].x + v[q].y + v[q].z + v[q].w;
+        pre += (b < blk ? v[q].x : 0u) + (b + 1 < blk ? v[q].y : 0u) + (b + 2 < blk ? v[q].z : 0u) +
+               (b + 3 < blk ? v[q].w : 0u);
+    }
+    return block_excl_scan_256(tot, ws) + pre;
+}
+
+__device__ __forceinline__ uint64_t pack_pair(const rn_pair &p, uint32_t vb) {
+    return (static_cast<uint64_t>(p.dist) << (2u * vb)) |
+           (static_cast<uint64_t>(static_cast<uint32_t>(p.u)) << vb) | static_cast<uint32_t>(p.v);
+}
+
+__global__ __launch_bounds__(256) void k_sort_pack(const rn_pair *in, uint64_t *keys,
+                                                   const unsigned long long *nptr, unsigned long long cap,
+                                                   uint32_t vb, uint32_t *hist0) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t beg, end, tile;
+    sort_tile(nptr, cap, beg, end, tile);
+    for (uint64_t i = beg + threadIdx.x; i < end; i += 256) {
+        const uint64_t k = pack_pair(in[i], vb);
+        keys[i] = k;
+        atomicAdd(&h[k & 255u], 1u);
+    }
+    __syncthreads();
+    hist0[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// One digit pass.  hist: [256][gridDim] counts of this pass's digit per input
+// tile.  hist_next (or null): accumulates the next digit per output tile.
+// out_pairs (final pass only): receives the unpacked pairs, written only when
+// the query succeeded and its result fits.
+__global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *in, uint64_t *out, rn_pair *out_pairs,
+                                                   const unsigned long long *nptr, unsigned long long cap,
+                                                   uint32_t shift, uint32_t vb, const uint32_t *hist,
+                                                   uint32_t *hist_next, uint32_t next_shift,
+                                                   const QueryCtl *ctl, unsigned long long user_cap,
+                                                   int last_tier) {
+    __shared__ uint32_t base[256];
+    __shared__ uint32_t wcnt[4][256];
+    __shared__ uint32_t ws[4];
+    const uint32_t tid = threadIdx.x, nb = gridDim.x;
+    if (out_pairs) {
+        const unsigned long long n = *nptr;
+        if (ctl->err != 0 || n > user_cap || n > cap) return;
+        if (last_tier >= 0 && ctl->novf[last_tier] != 0) return;
+    }
+    base[tid] = digit_base(hist, ws);
+    uint64_t beg, end, tile;
+    sort_tile(nptr, cap, beg, end, tile);
+    const uint32_t mask = (1u << vb) - 1u;
+    for (uint64_t c = beg; c < end; c += 256) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+        const uint64_t i = c + tid;
+        const bool act = i < end;
+        const uint64_t k = act ? in[i] : 0ull;
+        const uint32_t dg = static_cast<uint32_t>(k >> shift) & 255u;
+        const uint32_t r = chunk_rank(act, dg, wcnt);
+        if (act) {
+            const uint32_t pos = base[dg] + r;
+            if (out_pairs) {
+                rn_pair p;
+                p.dist = static_cast<uint32_t>(k >> (2u * vb));
+                p.u = static_cast<int32_t>(static_cast<uint32_t>(k >> vb) & mask);
+                p.v = static_cast<int32_t>(static_cast<uint32_t>(k) & mask);
+                out_pairs[pos] = p;
+            } else {
+                out[pos] = k;
+            }
+            if (hist_next)
+                atomicAdd(&hist_next[(static_cast<uint32_t>(k >> next_shift) & 255u) * nb +
+                                     pos / static_cast<uint32_t>(tile)],
+                          1u);
+        }
+        __syncthreads();
+        base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
+        __syncthreads();
+    }
+}
+
+// ---- generic path: 12-byte records, any key width
 __device__ __forceinline__ uint32_t pair_digit(const rn_pair &p, uint32_t bit, uint32_t vb) {
     const uint32_t sh = 2u * vb;
     if (bit >= sh) return (p.dist >> (bit - sh)) & 255u;
@@ -607,57 +849,30 @@ __device__ __forceinline__ uint32_t pair_digit(const rn_pair &p, uint32_t bit, u
     return static_cast<uint32_t>(x) & 255u;
 }
 
-__device__ __forceinline__ void sort_tile(const unsigned long long *nptr, unsigned long long cap,
-                                          uint64_t &beg, uint64_t &end) {
-    const uint64_t n = min(static_cast<uint64_t>(*nptr), static_cast<uint64_t>(cap));
-    const uint64_t tile = (n + gridDim.x - 1) / gridDim.x;
-    beg = min(n, blockIdx.x * tile);
-    end = min(n, beg + tile);
-}
-
 __global__ __launch_bounds__(256) void k_radix_hist(const rn_pair *in, const unsigned long long *nptr,
                                                     unsigned long long cap, uint32_t bit,
                                                     uint32_t vb, uint32_t *hist) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
     __syncthreads();
-    uint64_t beg, end;
-    sort_tile(nptr, cap, beg, end);
+    uint64_t beg, end, tile;
+    sort_tile(nptr, cap, beg, end, tile);
     for (uint64_t i = beg + threadIdx.x; i < end; i += 256) atomicAdd(&h[pair_digit(in[i], bit, vb)], 1u);
     __syncthreads();
     hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of hist[256 * kSortBlocks] in place (one block).
-__global__ __launch_bounds__(1024) void k_radix_scan(uint32_t *hist) {
-    __shared__ uint32_t wsum[16];
-    constexpr uint32_t per = 256u * kSortBlocks / 1024u;
-    const uint32_t tid = threadIdx.x;
-    uint32_t c = 0;
-    for (uint32_t i = 0; i < per; ++i) c += hist[tid * per + i];
-    const uint32_t incl = wave_incl_scan(c);
-    if ((tid & 63u) == 63u) wsum[tid >> 6] = incl;
-    __syncthreads();
-    uint32_t run = incl - c;
-    for (uint32_t w = 0; w < (tid >> 6); ++w) run += wsum[w];
-    for (uint32_t i = 0; i < per; ++i) {
-        const uint32_t v = hist[tid * per + i];
-        hist[tid * per + i] = run;
-        run += v;
-    }
-}
-
-// Stable scatter by digit: items keep their input order within a digit.
 __global__ __launch_bounds__(256) void k_radix_scatter(const rn_pair *in, rn_pair *out,
                                                        const unsigned long long *nptr,
                                                        unsigned long long cap, uint32_t bit,
                                                        uint32_t vb, const uint32_t *hist) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
-    const uint32_t tid = threadIdx.x, wave = tid >> 6;
-    base[tid] = hist[tid * gridDim.x + blockIdx.x];
-    uint64_t beg, end;
-    sort_tile(nptr, cap, beg, end);
+    __shared__ uint32_t ws[4];
+    const uint32_t tid = threadIdx.x;
+    base[tid] = digit_base(hist, ws);
+    uint64_t beg, end, tile;
+    sort_tile(nptr, cap, beg, end, tile);
     for (uint64_t c = beg; c < end; c += 256) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
@@ -665,26 +880,10 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const rn_pair *in, rn_pai
         const uint64_t i = c + tid;
         const bool act = i < end;
         rn_pair p{0, 0, 0};
-        uint32_t dg = 0;
-        if (act) {
-            p = in[i];
-            dg = pair_digit(p, bit, vb);
-        }
-        uint64_t peers = __ballot(act);
-#pragma unroll
-        for (int b = 0; b < 8; ++b) {
-            const bool set = (dg >> b) & 1u;
-            const uint64_t m = __ballot(act && set);
-            peers &= set ? m : ~m;
-        }
-        const uint32_t wrank = mbcnt(peers);
-        if (act && wrank == 0) wcnt[wave][dg] = popc(peers);
-        __syncthreads();
-        if (act) {
-            uint32_t off = 0;
-            for (uint32_t w = 0; w < wave; ++w) off += wcnt[w][dg];
-            out[base[dg] + off + wrank] = p;
-        }
+        if (act) p = in[i];
+        const uint32_t dg = act ? pair_digit(p, bit, vb) : 0u;
+        const uint32_t r = chunk_rank(act, dg, wcnt);
+        if (act) out[base[dg] + r] = p;
         __syncthreads();
         base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
         __syncthreads();
@@ -744,16 +943,24 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
+size_t stage_scratch_words(int32_t V) {
+    const size_t nwords = (static_cast<size_t>(V) + 31) / 32;
+    return (nwords + 1023) / 1024 + 1;
+}
+
 hipError_t launch_stage(const int32_t *R, int32_t nR, const int32_t *S, int32_t nS, int32_t V,
                         const int32_t *rank, const int32_t *order, uint32_t *rbits,
-                        uint32_t *sbits, int32_t *src, QueryCtl *ctl, hipStream_t s) {
+                        uint32_t *sbits, int32_t *src, QueryCtl *ctl, uint32_t *scratch,
+                        hipStream_t s) {
     const int64_t n = static_cast<int64_t>(nR) + nS;
     hipLaunchKernelGGL(k_mark, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, s, R, nR, S,
                        nS, V, rank, rbits, sbits, ctl);
     hipLaunchKernelGGL(k_overlap, dim3(static_cast<uint32_t>((nR + 255) / 256)), dim3(256), 0, s, R, nR,
                        V, sbits, ctl);
     const uint32_t nwords = static_cast<uint32_t>((static_cast<int64_t>(V) + 31) / 32);
-    hipLaunchKernelGGL(k_compact, dim3(1), dim3(1024), 0, s, rbits, nwords, order, src, ctl);
+    const uint32_t nblk = (nwords + 1023u) / 1024u;
+    hipLaunchKernelGGL(k_rank_count, dim3(nblk), dim3(1024), 0, s, rbits, nwords, scratch);
+    hipLaunchKernelGGL(k_rank_emit, dim3(nblk), dim3(1024), 0, s, rbits, nwords, scratch, order, src, ctl);
     return hipGetLastError();
 }
 
@@ -780,25 +987,42 @@ hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslot
     return hipGetLastError();
 }
 
-size_t sort_hist_words() { return 256u * kSortBlocks; }
+size_t sort_hist_words() { return static_cast<size_t>(kSortPassesMax + 1) * 256u * kSortBlocks; }
 
-hipError_t launch_sort_pairs(rn_pair *a, rn_pair *b, const unsigned long long *n,
-                             unsigned long long cap, uint32_t max_dist, int32_t V, uint32_t *hist,
-                             rn_pair **out_buf, hipStream_t s) {
+hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned long long *n,
+                              unsigned long long cap, uint32_t max_dist, int32_t V, uint32_t *hist,
+                              rn_pair *out, unsigned long long user_cap, const QueryCtl *ctl,
+                              int last_tier, hipStream_t s) {
     const uint32_t vb = V > 1 ? bitlen(static_cast<uint64_t>(V - 1)) : 1u;
     const uint32_t bits = 2u * vb + bitlen(max_dist);
-    rn_pair *in = a, *out = b;
+    const uint32_t passes = (bits + 7u) / 8u;
+    if (bits <= 64 && cap < (1ull << 31)) {
+        uint64_t *ka = reinterpret_cast<uint64_t *>(scratch);
+        uint64_t *kb = reinterpret_cast<uint64_t *>(pairs);   // records are packed into ka first
+        const size_t hw = 256u * kSortBlocks;
+        hipLaunchKernelGGL(k_sort_pack, dim3(kSortBlocks), dim3(256), 0, s, pairs, ka, n, cap, vb, hist);
+        uint64_t *in = ka, *o = kb;
+        for (uint32_t p = 0; p < passes; ++p) {
+            const bool last = p + 1 == passes;
+            hipLaunchKernelGGL(k_sort_pass, dim3(kSortBlocks), dim3(256), 0, s, in, o, last ? out : nullptr,
+                               n, cap, 8u * p, vb, hist + p * hw, last ? nullptr : hist + (p + 1) * hw,
+                               8u * (p + 1), ctl, user_cap, last_tier);
+            uint64_t *t = in;
+            in = o;
+            o = t;
+        }
+        return hipGetLastError();
+    }
+    rn_pair *in = pairs, *o = scratch;
     for (uint32_t bit = 0; bit < bits; bit += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3(kSortBlocks), dim3(256), 0, s, in, n, cap, bit, vb, hist);
-        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, s, hist);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(kSortBlocks), dim3(256), 0, s, in, out, n, cap, bit,
-                           vb, hist);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(kSortBlocks), dim3(256), 0, s, in, o, n, cap, bit, vb,
+                           hist);
         rn_pair *t = in;
-        in = out;
-        out = t;
+        in = o;
+        o = t;
     }
-    *out_buf = in;
-    return hipGetLastError();
+    return launch_copy_out(in, out, ctl, user_cap, cap, last_tier, s);
 }
 
 hipError_t launch_copy_out(const rn_pair *src, rn_pair *dst, const QueryCtl *ctl,
