@@ -98,6 +98,8 @@ struct rn_graph {
     uint32_t *d_sbits() const { return d_qblock + ctl_words(); }
     uint32_t *d_rbits() const { return d_qblock + ctl_words() + bitmap_words(); }
     uint32_t *d_hist() const { return d_qblock + ctl_words() + 2 * bitmap_words(); }
+    uint32_t *d_seed_hist() const { return d_hist() + sort_hist_words(); }
+    uint32_t *d_cand_hist() const { return d_seed_hist() + kDistBins; }
 };
 
 namespace {
@@ -129,7 +131,7 @@ void release_buffers(rn_graph *g) {
 }
 
 rn_status ensure_query_buffers(rn_graph *g, int32_t nR) {
-    const size_t qwords = g->ctl_words() + 2 * g->bitmap_words() + sort_hist_words();
+    const size_t qwords = g->ctl_words() + 2 * g->bitmap_words() + sort_hist_words() + 2 * kDistBins;
     if (g->qblock_words < qwords) {
         dev_free(g->d_qblock);
         RN_HIP(dev_alloc(&g->d_qblock, qwords), "allocating query bitmaps");
@@ -190,11 +192,13 @@ float elapsed(rn_graph *g, int a, int b) {
     return ms;
 }
 
-// On-chip table tiers tried in order: the handle's first choice, then larger
-// ones; the global-memory tier follows them.
-int tier_list(const rn_graph *g, int *hb) {
+// On-chip table tiers tried in order: the handle's first choice (a small table
+// for k-closest pairs, whose searches are usually cut short by the bound),
+// then larger ones; the global-memory tier follows them.
+int tier_list(const rn_graph *g, bool kcp, int *hb) {
     int n = 0;
-    const int cand[kLdsTiers] = {g->hash_log2, std::min(g->hash_log2 + 2, 14), 14};
+    const int first = kcp ? 8 : g->hash_log2;
+    const int cand[kLdsTiers] = {first, std::min(std::max(first + 3, g->hash_log2), 14), 14};
     for (int c : cand)
         if (n == 0 || c > hb[n - 1]) hb[n++] = c;
     return n;
@@ -416,13 +420,11 @@ namespace {
 rn_status run_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS,
                    uint32_t bound, bool kcp, int32_t k, rn_pair *out, int64_t cap, int64_t *n_out,
                    hipStream_t stream) {
-    (void)k;
-    if (kcp) return fail(RN_ERR_ARG, "k-closest pairs not available in this build");
     RN_HIP(hipSetDevice(g->device), "selecting the device");
     rn_status st = ensure_query_buffers(g, nR);
     if (st != RN_OK) return st;
     int hb[kLdsTiers];
-    const int nlds = tier_list(g, hb);
+    const int nlds = tier_list(g, kcp, hb);
     const int ntiers = nlds + 1;
     QueryCtl *ctl = g->d_ctl();
     g->stats = rn_stats{};
@@ -434,6 +436,10 @@ rn_status run_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, 
                             g->d_src, ctl, g->d_stage, stream),
                "staging the query");
         record(g, EV_STAGED, stream);
+        if (kcp)
+            RN_HIP(launch_kcp_seed(g->d_src, &ctl->nsrc, static_cast<uint32_t>(nR), g->d_row_ptr, g->d_arcs,
+                                   g->d_sbits(), g->d_seed_hist(), static_cast<uint32_t>(k), ctl, stream),
+                   "seeding the k-closest-pairs bound");
         for (int t = 0; t < ntiers; ++t) {
             JoinArgs a;
             a.row_ptr = g->d_row_ptr;
@@ -450,6 +456,8 @@ rn_status run_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, 
             a.delta = g->delta;
             a.kcp = kcp ? 1 : 0;
             a.count_work = g->count_work ? 1 : 0;
+            a.k = static_cast<uint32_t>(k);
+            a.cand_hist = g->d_cand_hist();
             if (t < nlds)
                 RN_HIP(launch_join(a, hb[t], static_cast<uint32_t>(nR), stream), "launching the relaxation");
             else
@@ -459,11 +467,32 @@ rn_status run_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, 
             if (t == 0) record(g, EV_TIER0, stream);
         }
         record(g, EV_RELAXED, stream);
-        record(g, EV_SELECTED, stream);
-        RN_HIP(launch_sort_to_out(g->d_pairs[0], g->d_pairs[1], &ctl->npairs, g->pair_cap, bound, g->V,
-                                  g->d_hist(), out, static_cast<unsigned long long>(cap), ctl,
-                                  ntiers - 1, stream),
-               "sorting pairs");
+        if (!kcp) {
+            record(g, EV_SELECTED, stream);
+            RN_HIP(launch_sort_to_out(g->d_pairs[0], g->d_pairs[1], &ctl->npairs, g->pair_cap, bound, g->V,
+                                      g->d_hist(), out, static_cast<unsigned long long>(cap), ~0ull, ctl,
+                                      ntiers - 1, stream),
+                   "sorting pairs");
+        } else {
+            // the final bound fixes the sort key width: read it back first
+            RN_HIP(hipMemcpyAsync(g->h_ctl, ctl, sizeof(QueryCtl), hipMemcpyDeviceToHost, stream),
+                   "reading the query status");
+            RN_HIP(hipStreamSynchronize(stream), "waiting for the searches");
+            const QueryCtl c = *g->h_ctl;
+            if (c.err) return fail(RN_ERR_ARG, describe_err(c.err));
+            if (c.npairs > g->pair_cap) {
+                st = grow_pairs(g, c.npairs);
+                if (st != RN_OK) return st;
+                continue;
+            }
+            RN_HIP(launch_kcp_filter(g->d_pairs[0], g->pair_cap, g->d_pairs[1], ctl, stream),
+                   "filtering candidates");
+            record(g, EV_SELECTED, stream);
+            RN_HIP(launch_sort_to_out(g->d_pairs[1], g->d_pairs[0], &ctl->nsel, g->pair_cap, c.theta, g->V,
+                                      g->d_hist(), out, static_cast<unsigned long long>(cap),
+                                      static_cast<unsigned long long>(k), ctl, ntiers - 1, stream),
+                   "sorting pairs");
+        }
         record(g, EV_DONE, stream);
         RN_HIP(hipMemcpyAsync(g->h_ctl, ctl, sizeof(QueryCtl), hipMemcpyDeviceToHost, stream),
                "reading the query status");
@@ -488,9 +517,10 @@ rn_status run_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, 
         g->stats.retried = static_cast<int32_t>(c.novf[0]);
         g->stats.global_searches = static_cast<int32_t>(c.novf[nlds - 1]);
         g->stats.relax_launches = ntiers;
-        *n_out = static_cast<int64_t>(c.npairs);
-        if (c.npairs > static_cast<unsigned long long>(cap))
-            return fail(RN_ERR_CAPACITY, "output buffer too small");
+        const unsigned long long n =
+            kcp ? std::min<unsigned long long>(c.nsel, static_cast<unsigned long long>(k)) : c.npairs;
+        *n_out = static_cast<int64_t>(n);
+        if (n > static_cast<unsigned long long>(cap)) return fail(RN_ERR_CAPACITY, "output buffer too small");
         return RN_OK;
     }
     return fail(RN_ERR_NOMEM, "pair buffer did not settle");

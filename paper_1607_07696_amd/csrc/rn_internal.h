@@ -34,8 +34,13 @@ struct QueryCtl {
     uint32_t ncand;                 // k-closest pairs: bound-seeding candidate count
     unsigned long long arcs;        // work count: out-arcs of every settled (source, vertex)
     unsigned long long settled;     // work count: settled (source, vertex) pairs
-    uint32_t pad[2];
+    unsigned long long nsel;        // k-closest pairs: candidates kept by the final bound
 };
+
+// k-closest pairs: distances are counted in log-spaced bins (16 per octave:
+// exact below 16, then 16 steps per power of two); the upper edge of the bin
+// holding the k-th count bounds the k-th smallest distance from above.
+constexpr uint32_t kDistBins = 512;   // 464 used
 static_assert(sizeof(QueryCtl) % 4 == 0, "QueryCtl is cleared as 32-bit words");
 
 // One arc as the relaxation kernels read it: target, weight, and the target's
@@ -63,6 +68,8 @@ struct JoinArgs {
     uint32_t delta;             // bucket width (0 = one bucket)
     int32_t kcp;                // 1: bound is ctl->theta, read every phase
     int32_t count_work;         // 1: accumulate ctl->arcs / ctl->settled
+    uint32_t k;                 // k-closest pairs: k
+    uint32_t *cand_hist;        // k-closest pairs: kDistBins counts of emitted distances
 };
 
 // Per-source state of the global-memory tier, one slot per concurrent block:
@@ -90,14 +97,23 @@ hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslot
 // cap pairs) and write them to out when the query succeeded and the result
 // fits (no argument error, no search left over, *n <= user_cap, *n <= cap).
 // hist: sort_hist_words() words, zero on entry.  max_dist bounds every dist.
+// Only the first out_limit sorted pairs are written (all of them for a theta-join).
 hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned long long *n,
                               unsigned long long cap, uint32_t max_dist, int32_t V, uint32_t *hist,
-                              rn_pair *out, unsigned long long user_cap, const QueryCtl *ctl,
-                              int last_tier, hipStream_t s);
+                              rn_pair *out, unsigned long long user_cap, unsigned long long out_limit,
+                              const QueryCtl *ctl, int last_tier, hipStream_t s);
 size_t sort_hist_words();
+// k-closest pairs: seed the bound ctl->theta from the direct arcs between R and
+// S (seed_hist: kDistBins zeroed words), then, after the searches, keep the
+// emitted pairs within the final bound (into `kept`, count ctl->nsel).
+hipError_t launch_kcp_seed(const int32_t *src, const uint32_t *nsrc, uint32_t max_sources,
+                           const int32_t *row_ptr, const ArcRec *arcs, const uint32_t *sbits,
+                           uint32_t *seed_hist, uint32_t k, QueryCtl *ctl, hipStream_t s);
+hipError_t launch_kcp_filter(const rn_pair *pairs, unsigned long long cap, rn_pair *kept, QueryCtl *ctl,
+                             hipStream_t s);
 // Copy sorted pairs to the caller when the query succeeded and fits.
-hipError_t launch_copy_out(const rn_pair *src, rn_pair *dst, const QueryCtl *ctl,
-                           unsigned long long user_cap, unsigned long long limit,
-                           int last_tier, hipStream_t s);
+hipError_t launch_copy_out(const rn_pair *src, rn_pair *dst, const unsigned long long *n,
+                           const QueryCtl *ctl, unsigned long long user_cap, unsigned long long limit,
+                           unsigned long long out_limit, int last_tier, hipStream_t s);
 
 }  // namespace rn

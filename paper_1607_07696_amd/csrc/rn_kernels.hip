@@ -81,6 +81,45 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Log-spaced distance bins (k-closest pairs): exact below 16, then 16 bins
+// per power of two.
+__device__ __forceinline__ uint32_t dist_bin(uint32_t d) {
+    if (d < 16u) return d;
+    const uint32_t e = 31u - static_cast<uint32_t>(__clz(d));   // e >= 4
+    return 16u + (e - 4u) * 16u + ((d >> (e - 4u)) & 15u);
+}
+
+// Largest distance in bin b.
+__device__ __forceinline__ uint32_t bin_upper(uint32_t b) {
+    if (b < 16u) return b;
+    const uint32_t e = (b - 16u) / 16u + 4u, m = (b - 16u) % 16u;
+    const uint64_t u = ((16ull + m + 1ull) << (e - 4u)) - 1ull;
+    return u > kMaxDist ? kMaxDist : static_cast<uint32_t>(u);
+}
+
+// Upper edge of the bin where the cumulative count of hist[0..kDistBins)
+// reaches k (kMaxDist if the total is below k).  Called by a whole wave;
+// result wave-uniform.  Counts read late only make the edge larger, so a
+// stale read still yields an upper bound.
+__device__ __forceinline__ uint32_t wave_bound_from_hist(const uint32_t *hist, uint32_t k) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint4 *p = reinterpret_cast<const uint4 *>(hist + 8u * lane);
+    const uint4 x = p[0], y = p[1];
+    const uint32_t c[8] = {x.x, x.y, x.z, x.w, y.x, y.y, y.z, y.w};
+    uint32_t sum = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) sum += c[i];
+    const uint32_t incl = wave_incl_scan(sum);
+    if (readlane(incl, 63) < k) return kMaxDist;
+    uint32_t run = incl - sum, found = kInf;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        run += c[i];
+        if (found == kInf && run >= k) found = bin_upper(8u * lane + i);
+    }
+    return wave_min(found);
+}
+
 __device__ __forceinline__ uint32_t sat_add(uint32_t a, uint32_t b) {
     uint32_t s = a + b;
     return s < a ? kInf : s;
@@ -257,6 +296,16 @@ __device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, uin
     relax_window<HB, NJ>(L, st, P, r, nd, bound);
 }
 
+// k-closest pairs: once k pairs have been emitted, bound the k-th distance by
+// the emitted-distance histogram and lower the shared bound.  Whole wave.
+__device__ __forceinline__ void tighten_bound(const JoinArgs &a) {
+    const unsigned long long n =
+        __hip_atomic_load(&a.ctl->npairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (n < a.k) return;
+    const uint32_t b = wave_bound_from_hist(a.cand_hist, a.k);
+    if ((threadIdx.x & 63u) == 0) atomicMin(&a.ctl->theta, b);
+}
+
 // Write this wave's staged pairs (L.beg[0] = v, L.end[0] = dist) for source u.
 template <int HB>
 __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a, int32_t u,
@@ -395,7 +444,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
 
     // ---- emit table entries in S, and clear the table for the next source
     bound = current_bound(a);
-    uint32_t nst = 0;
+    uint32_t nst = 0, emitted = 0;
     unsigned long long warcs = 0;
     uint32_t wsettled = 0;
     for (uint32_t g0 = 0; g0 < static_cast<uint32_t>(H); g0 += 64 * U) {
@@ -428,6 +477,8 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
             const uint32_t y = k[j] & ~kPend;
             const bool m = !st.ovf && k[j] != kEmpty && ((sb[j] >> (y & 31u)) & 1u) && d[j] <= bound;
             const uint64_t mM = __ballot(m);
+            if (a.kcp && m) atomicAdd(&a.cand_hist[dist_bin(d[j])], 1u);
+            emitted += popc(mM);
             const uint32_t idx = m ? nst + mbcnt(mM) : static_cast<uint32_t>(PC);
             L.beg[0][idx] = static_cast<int32_t>(y);
             L.end[0][idx] = static_cast<int32_t>(d[j]);
@@ -440,6 +491,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
     }
     wave_sync();
     flush_pairs<HB>(L, a, u, nst);
+    if (a.kcp && emitted != 0) tighten_bound(a);
     if (a.count_work && !st.ovf) {
         for (int o = 32; o > 0; o >>= 1) {
             const uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(warcs & 0xFFFFFFFFull), o));
@@ -577,6 +629,7 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
                 }
             }
             const uint64_t mm = __ballot(m);
+            if (a.kcp && m) atomicAdd(&a.cand_hist[dist_bin(d)], 1u);
             if (mm != 0) {
                 unsigned long long base = 0;
                 if (lane == 0) base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(popc(mm)));
@@ -606,6 +659,7 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
             }
         }
         __syncthreads();
+        if (a.kcp && tid < 64) tighten_bound(a);
     }
 }
 
@@ -793,14 +847,14 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *in, uint64_t 
                                                    uint32_t shift, uint32_t vb, const uint32_t *hist,
                                                    uint32_t *hist_next, uint32_t next_shift,
                                                    const QueryCtl *ctl, unsigned long long user_cap,
-                                                   int last_tier) {
+                                                   unsigned long long out_limit, int last_tier) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t ws[4];
     const uint32_t tid = threadIdx.x, nb = gridDim.x;
     if (out_pairs) {
         const unsigned long long n = *nptr;
-        if (ctl->err != 0 || n > user_cap || n > cap) return;
+        if (ctl->err != 0 || n > cap || min(n, out_limit) > user_cap) return;
         if (last_tier >= 0 && ctl->novf[last_tier] != 0) return;
     }
     base[tid] = digit_base(hist, ws);
@@ -823,7 +877,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *in, uint64_t 
                 p.dist = static_cast<uint32_t>(k >> (2u * vb));
                 p.u = static_cast<int32_t>(static_cast<uint32_t>(k >> vb) & mask);
                 p.v = static_cast<int32_t>(static_cast<uint32_t>(k) & mask);
-                out_pairs[pos] = p;
+                if (pos < out_limit) out_pairs[pos] = p;
             } else {
                 out[pos] = k;
             }
@@ -890,14 +944,56 @@ __global__ __launch_bounds__(256) void k_radix_scatter(const rn_pair *in, rn_pai
     }
 }
 
-__global__ void k_copy_out(const rn_pair *src, rn_pair *dst, const QueryCtl *ctl,
-                           unsigned long long user_cap, unsigned long long limit, int last_tier) {
-    const unsigned long long n = ctl->npairs;
-    if (ctl->err != 0 || n > user_cap || n > limit) return;
+__global__ void k_copy_out(const rn_pair *src, rn_pair *dst, const unsigned long long *nptr,
+                           const QueryCtl *ctl, unsigned long long user_cap, unsigned long long limit,
+                           unsigned long long out_limit, int last_tier) {
+    const unsigned long long n = *nptr;
+    if (ctl->err != 0 || n > limit || min(n, out_limit) > user_cap) return;
     if (last_tier >= 0 && ctl->novf[last_tier] != 0) return;
+    const unsigned long long m = min(n, out_limit);
     for (unsigned long long i = blockIdx.x * static_cast<unsigned long long>(blockDim.x) + threadIdx.x;
-         i < n; i += static_cast<unsigned long long>(gridDim.x) * blockDim.x)
+         i < m; i += static_cast<unsigned long long>(gridDim.x) * blockDim.x)
         dst[i] = src[i];
+}
+
+// ------------------------------------------------------------------ k-closest pairs
+// Seed: every distinct (u, y) with u in R, y in S joined by an arc has
+// dist(u, y) <= the lightest such arc's weight, so the bin edge where k of
+// these weights are reached bounds the k-th smallest distance.  A pair with
+// parallel arcs is counted once, at its first lightest arc.
+__global__ void k_kcp_seed_hist(const int32_t *src, const uint32_t *nsrc, const int32_t *row_ptr,
+                                const ArcRec *arcs, const uint32_t *sbits, uint32_t *seed_hist) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *nsrc) return;
+    const int32_t u = src[i];
+    const int32_t b = row_ptr[u], e = row_ptr[u + 1];
+    for (int32_t x = b; x < e; ++x) {
+        const ArcRec r = arcs[x];
+        const uint32_t y = static_cast<uint32_t>(r.y);
+        if (!((sbits[y >> 5] >> (y & 31u)) & 1u)) continue;
+        bool first = true;
+        for (int32_t z = b; z < e && first; ++z) {
+            const ArcRec q = arcs[z];
+            if (q.y == r.y && (q.w < r.w || (q.w == r.w && z < x))) first = false;
+        }
+        if (first) atomicAdd(&seed_hist[dist_bin(r.w)], 1u);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_kcp_seed_bound(const uint32_t *seed_hist, uint32_t k, QueryCtl *ctl) {
+    const uint32_t b = wave_bound_from_hist(seed_hist, k);
+    if (threadIdx.x == 0) ctl->theta = b;
+}
+
+// Keep the emitted pairs within the final bound (order is restored by the sort).
+__global__ void k_kcp_filter(const rn_pair *pairs, unsigned long long cap, rn_pair *kept, QueryCtl *ctl) {
+    const unsigned long long n = min(ctl->npairs, cap);
+    const uint32_t bound = ctl->theta;
+    for (unsigned long long i = blockIdx.x * static_cast<unsigned long long>(blockDim.x) + threadIdx.x;
+         i < n; i += static_cast<unsigned long long>(gridDim.x) * blockDim.x) {
+        const rn_pair p = pairs[i];
+        if (p.dist <= bound) kept[atomicAdd(&ctl->nsel, 1ull)] = p;
+    }
 }
 
 inline uint32_t bitlen(uint64_t x) {
@@ -991,8 +1087,8 @@ size_t sort_hist_words() { return static_cast<size_t>(kSortPassesMax + 1) * 256u
 
 hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned long long *n,
                               unsigned long long cap, uint32_t max_dist, int32_t V, uint32_t *hist,
-                              rn_pair *out, unsigned long long user_cap, const QueryCtl *ctl,
-                              int last_tier, hipStream_t s) {
+                              rn_pair *out, unsigned long long user_cap, unsigned long long out_limit,
+                              const QueryCtl *ctl, int last_tier, hipStream_t s) {
     const uint32_t vb = V > 1 ? bitlen(static_cast<uint64_t>(V - 1)) : 1u;
     const uint32_t bits = 2u * vb + bitlen(max_dist);
     const uint32_t passes = (bits + 7u) / 8u;
@@ -1006,7 +1102,7 @@ hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned l
             const bool last = p + 1 == passes;
             hipLaunchKernelGGL(k_sort_pass, dim3(kSortBlocks), dim3(256), 0, s, in, o, last ? out : nullptr,
                                n, cap, 8u * p, vb, hist + p * hw, last ? nullptr : hist + (p + 1) * hw,
-                               8u * (p + 1), ctl, user_cap, last_tier);
+                               8u * (p + 1), ctl, user_cap, out_limit, last_tier);
             uint64_t *t = in;
             in = o;
             o = t;
@@ -1022,14 +1118,29 @@ hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned l
         in = o;
         o = t;
     }
-    return launch_copy_out(in, out, ctl, user_cap, cap, last_tier, s);
+    return launch_copy_out(in, out, n, ctl, user_cap, cap, out_limit, last_tier, s);
 }
 
-hipError_t launch_copy_out(const rn_pair *src, rn_pair *dst, const QueryCtl *ctl,
-                           unsigned long long user_cap, unsigned long long limit, int last_tier,
-                           hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_out, dim3(1024), dim3(256), 0, s, src, dst, ctl, user_cap, limit,
+hipError_t launch_copy_out(const rn_pair *src, rn_pair *dst, const unsigned long long *n,
+                           const QueryCtl *ctl, unsigned long long user_cap, unsigned long long limit,
+                           unsigned long long out_limit, int last_tier, hipStream_t s) {
+    hipLaunchKernelGGL(k_copy_out, dim3(1024), dim3(256), 0, s, src, dst, n, ctl, user_cap, limit, out_limit,
                        last_tier);
+    return hipGetLastError();
+}
+
+hipError_t launch_kcp_seed(const int32_t *src, const uint32_t *nsrc, uint32_t max_sources,
+                           const int32_t *row_ptr, const ArcRec *arcs, const uint32_t *sbits,
+                           uint32_t *seed_hist, uint32_t k, QueryCtl *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_kcp_seed_hist, dim3((max_sources + 255) / 256), dim3(256), 0, s, src, nsrc, row_ptr,
+                       arcs, sbits, seed_hist);
+    hipLaunchKernelGGL(k_kcp_seed_bound, dim3(1), dim3(64), 0, s, seed_hist, k, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_kcp_filter(const rn_pair *pairs, unsigned long long cap, rn_pair *kept, QueryCtl *ctl,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_kcp_filter, dim3(1024), dim3(256), 0, s, pairs, cap, kept, ctl);
     return hipGetLastError();
 }
 

@@ -1,0 +1,126 @@
+"""GPU k-closest-pairs parity: the HIP path against the CPU oracle, bit for bit.
+
+The answer is unique under the (dist, u, v) order, so results compare by exact
+equality of the pair arrays (tolerance 0).
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rnmod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1607_07696_amd import rn
+    rn.load_library()
+    return rn
+
+
+@pytest.fixture(scope="module")
+def g64(rg):
+    return rg.road_graph(64, 0)
+
+
+def gpu_kcp(rnmod, net, R, S, k):
+    return rnmod.pairs_to_numpy(net.kcp_join(R, S, k))
+
+
+def assert_same(got, want):
+    assert got.shape == want.shape, (got.shape, want.shape)
+    assert np.array_equal(got, want)
+
+
+def test_config1_kcp(rnmod, orc, rg, g64):
+    net = rnmod.RoadNetwork.from_graph(g64)
+    R, S = rg.sample_disjoint(g64.V, 64, 64, 1)
+    assert_same(gpu_kcp(rnmod, net, R, S, 16), orc.kcp_join(g64, R, S, 16))
+
+
+@pytest.mark.parametrize("k", [1, 2, 7, 100, 1000, 4096, 5000])
+def test_k_range(rnmod, orc, rg, g64, k):
+    net = rnmod.RoadNetwork.from_graph(g64)
+    R, S = rg.sample_disjoint(g64.V, 64, 64, 1)
+    want = orc.kcp_join(g64, R, S, k)
+    assert len(want) == min(k, 64 * 64)          # connected graph: every pair is reachable
+    assert_same(gpu_kcp(rnmod, net, R, S, k), want)
+
+
+def test_config3_clustered_full_size(rnmod, orc, rg):
+    g = rg.road_graph(1024, 0)
+    R, S = rg.sample_clustered(g, 65536, 65536, 3)
+    net = rnmod.RoadNetwork.from_graph(g)
+    want = orc.kcp_join(g, R, S, 1024)
+    assert_same(gpu_kcp(rnmod, net, R, S, 1024), want)
+    assert_same(gpu_kcp(rnmod, net, R, S, 1024), want)   # repeat on the same handle
+
+
+def test_ties_on_uniform_lattice(rnmod, orc, rg):
+    g = rg.full_lattice(40, 5)                     # every distance a multiple of 5: many ties
+    R, S = rg.sample_disjoint(g.V, 150, 150, 21)
+    net = rnmod.RoadNetwork.from_graph(g)
+    for k in (1, 10, 77, 500, 3000):
+        assert_same(gpu_kcp(rnmod, net, R, S, k), orc.kcp_join(g, R, S, k))
+
+
+def test_directed_zero_weights(rnmod, orc, rg):
+    g = rg.random_digraph(2500, 9000, 8, wmin=1, wmax=40, zero_frac=0.25)
+    R, S = rg.sample_disjoint(g.V, 120, 300, 22)
+    net = rnmod.RoadNetwork.from_graph(g)
+    for k in (1, 50, 400):
+        assert_same(gpu_kcp(rnmod, net, R, S, k), orc.kcp_join(g, R, S, k))
+
+
+def test_fewer_reachable_pairs_than_k(rnmod, orc, rg):
+    g = rg.road_graph(40, 4, p_drop=0.5, keep_lcc=False)   # many small components
+    R, S = rg.sample_disjoint(g.V, 30, 30, 23)
+    want = orc.kcp_join(g, R, S, 900)
+    assert len(want) < 900
+    net = rnmod.RoadNetwork.from_graph(g)
+    assert_same(gpu_kcp(rnmod, net, R, S, 900), want)
+
+
+def test_unbounded_search_uses_global_tier(rnmod, orc, rg):
+    g = rg.road_graph(128, 0)
+    R, S = rg.sample_disjoint(g.V, 3, 5, 24)       # k = all 15 pairs: the bound never tightens
+    net = rnmod.RoadNetwork.from_graph(g)
+    want = orc.kcp_join(g, R, S, 15)
+    assert_same(gpu_kcp(rnmod, net, R, S, 15), want)
+    assert net.stats()["global_searches"] == 3
+
+
+def test_kcp_is_join_prefix_at_dk(rnmod, rg, g64):
+    net = rnmod.RoadNetwork.from_graph(g64)
+    R, S = rg.sample_disjoint(g64.V, 200, 300, 25)
+    kc = gpu_kcp(rnmod, net, R, S, 333)
+    dk = int(kc["dist"][-1])
+    join = rnmod.pairs_to_numpy(net.dist_join(R, S, dk))
+    assert_same(join[:333], kc)
+    assert np.all(join["dist"][333:] == dk)
+
+
+def test_partition_and_tuning_never_change_kcp(rnmod, orc, rg):
+    g = rg.road_graph(160, 2)
+    R, S = rg.sample_clustered(g, 3000, 3000, 26)
+    want = orc.kcp_join(g, R, S, 256)
+    net = rnmod.RoadNetwork.from_graph(g)
+    assert_same(gpu_kcp(rnmod, net, R, S, 256), want)
+    net.partition(1.0, 128)
+    for delta, hb in ((0, 11), (41, 9), (500, 14)):
+        net.set_tuning(delta=delta, hash_log2=hb)
+        assert_same(gpu_kcp(rnmod, net, R, S, 256), want)
+
+
+def test_kcp_argument_errors(rnmod, rg, g64):
+    net = rnmod.RoadNetwork.from_graph(g64)
+    R, S = rg.sample_disjoint(g64.V, 10, 10, 27)
+    with pytest.raises(rnmod.RnError) as ei:
+        net.kcp_join(R, S, 0)
+    assert ei.value.status == rnmod.RN_ERR_ARG
+    S2 = S.copy()
+    S2[0] = R[0]
+    with pytest.raises(rnmod.RnError) as ei:
+        net.kcp_join(R, S2, 5)
+    assert ei.value.status == rnmod.RN_ERR_ARG
