@@ -49,6 +49,84 @@ def workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_1607_07696_amd", "csrc", "rn_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_join_join1024_traffic.txt")
+
+
+def kernel_source_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per relaxation launch from the committed PMC summary, or None.
+
+    The summary records FETCH_SIZE and WRITE_SIZE of the relaxation kernel and
+    of a plain device copy of known size, plus a hash of the kernel source it
+    was taken on; a changed kernel makes the figure stale (None)."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    try:
+        fetch = float(kv["relax_fetch_kib"]) / float(kv["copy_fetch_factor"])
+        write = float(kv["relax_write_kib"]) / float(kv["copy_write_factor"])
+    except (KeyError, ValueError, ZeroDivisionError):
+        return None
+    return int((fetch + write) * 1024)
+
+
+def copy_probe(torch, mib=256):
+    """One plain device-to-device copy of `mib` MiB (counter calibration)."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    log(f"copy probe: {mib} MiB device copy done")
+
+
+def kcp_leg(torch, rn, steps):
+    """k-closest pairs on the clustered 1024x1024 workload (timed per query)."""
+    from paper_1607_07696_amd import roadgen
+    g = roadgen.road_graph(1024, 0)
+    R, S = roadgen.sample_clustered(g, 65536, 65536, 3)
+    net = rn.RoadNetwork.from_graph(g)
+    Rd = torch.as_tensor(R, device="cuda")
+    Sd = torch.as_tensor(S, device="cuda")
+    net.set_profiling(times=True, work=True)
+    out = net.kcp_join(Rd, Sd, 1024)
+    dk = int(out[-1, 2].item())
+    net.kcp_join(Rd, Sd, 1024)
+    st = net.stats()
+    net.set_profiling(times=True, work=False)
+    lat, dev = [], []
+    for _ in range(steps):
+        a = time.perf_counter()
+        net.kcp_join(Rd, Sd, 1024)
+        lat.append(time.perf_counter() - a)
+        dev.append(net.stats()["total_ms"])
+    # work: arcs out of every vertex within d_k of each source (theta-join at d_k)
+    net.set_profiling(times=False, work=True)
+    net.dist_join(Rd, Sd, dk)
+    arcs_dk = net.stats()["arcs"]
+    ms = float(np.median(lat)) * 1e3
+    return {"workload": ("k-closest pairs, 1024x1024 road graph (seed 0), |R|=|S|=65536, half uniform "
+                         "and half around 32 shared Gaussian centres (sigma 20, seed 3), k=1024"),
+            "k": 1024, "d_k": dk, "ms_per_query": round(ms, 4),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
+                           "p99": round(float(np.percentile(lat, 99)) * 1e3, 4)},
+            "device_ms": round(float(np.median(dev)), 4),
+            "gteps_at_dk": round(arcs_dk / (ms / 1e3) / 1e9, 3),
+            "candidates": int(st["pairs"]), "arcs_scanned": int(st["arcs"])}
+
+
 def cpu_baseline(g, R, S, theta, arcs_total, budget_s):
     from oracle import oracle
     times = []
@@ -78,6 +156,9 @@ def main():
     ap.add_argument("--partition", default="1.0,256", help="alpha,max_leaf or 'none'")
     ap.add_argument("--cpu-budget", type=float, default=8.0, help="seconds of oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kcp", action="store_true", help="skip the k-closest-pairs leg")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run one 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -90,6 +171,9 @@ def main():
 
     assert torch.cuda.is_available(), "no HIP device"
     torch.cuda.set_device(0)
+    if args.copy_probe:
+        copy_probe(torch)
+        return
     g, R, S, theta, desc = workload(args.workload)
     log(f"graph V={g.V} A={g.A}; |R|={len(R)} |S|={len(S)} theta={theta}")
     net = rn.RoadNetwork.from_graph(g)
@@ -153,7 +237,8 @@ def main():
                    "nS": len(S), "tuning": dict(zip(("delta", "hash_log2"), net.tuning())),
                    "partition": args.partition},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic() if args.workload == "join1024" else None,
                      "kernel": "k_join (first table tier)",
                      "algorithmic_bytes": int(alg_bytes)},
         "pairs": int(npairs),
@@ -168,6 +253,9 @@ def main():
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 4)},
         "partition_s": None if part_s is None else round(part_s, 3),
     }
+    if not args.no_kcp:
+        log("k-closest-pairs leg")
+        result["kcp"] = kcp_leg(torch, rn, max(5, args.steps))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(g, R, S, theta, arcs, args.cpu_budget)
