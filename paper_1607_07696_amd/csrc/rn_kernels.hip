@@ -23,8 +23,7 @@ namespace rn {
 
 namespace {
 
-constexpr uint32_t kEmpty = 0x7FFFFFFFu;  // empty table key (never a vertex id)
-constexpr uint32_t kPend = 0x80000000u;   // key flag: the vertex is in the pending list
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // empty table key (vertex ids are below 2^31 - 1)
 constexpr uint32_t kWin = 256;            // frontier arcs expanded per window (4 per lane)
 
 // ------------------------------------------------------------------ wave helpers
@@ -147,16 +146,27 @@ struct Tier {
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
 };
 
+// Distance words: (distance << 1) | pending, the low bit set while the vertex
+// is in the pending list.  One atomicMin with (nd << 1) | 1 lowers the distance
+// and marks the vertex pending only when nd is strictly smaller (an equal
+// distance over a zero-weight arc leaves the word alone); the lane that finds
+// the old word idle or empty appends the vertex.  Expansion clears the bit.
+// On-chip tables therefore hold distances up to 2^31 - 2; a search that needs
+// longer ones moves on to the global tier.
+constexpr uint32_t kWordNone = 0xFFFFFFFFu;   // empty slot (above every stored word)
+constexpr uint32_t kPackMax = 0x7FFFFFFEu;    // largest distance an on-chip table holds
+constexpr uint32_t kNoKey = 0xFFFFFFFEu;      // compare value no stored key equals
+
 template <int HB>
 struct SearchLds {
     static constexpr int H = Tier<HB>::H;
     static constexpr int PC = Tier<HB>::PC;
-    uint32_t key[H];            // vertex id | kPend, or kEmpty
-    uint32_t dist[H];           // tentative distance (kInf when empty)
-    uint32_t slot[2][PC + 1];   // two vertex lists: table slot and arc range;
-    int32_t beg[2][PC + 1];     //   entry PC of each is a write sink for lanes
-    int32_t end[2][PC + 1];     //   that have nothing to store
-    uint8_t own[kWin];          // window arc -> owning frontier lane
+    uint32_t key[H];            // vertex id, or kEmpty
+    uint32_t dw[H];             // distance word, kWordNone when empty
+    uint32_t ent[2][PC + 1];    // two vertex lists: slot | (arc count << 16) and first arc;
+    int32_t beg[2][PC + 1];     //   entry PC of each is a write sink for lanes with nothing to store
+    int32_t widx[kWin];         // window arc -> arc index
+    uint32_t wd[kWin];          // window arc -> distance of the arc's tail
 };
 
 struct WaveState {
@@ -173,38 +183,35 @@ __device__ __forceinline__ uint32_t current_bound(const JoinArgs &a) {
 }
 
 // Relax NJ window arcs per lane (slot j holds window arc j*64 + lane) and
-// append targets that became pending to list P.  Each step (first probe,
-// claim, min, pending flag) is issued for all NJ slots before any result is
-// used, so the slots' LDS latencies overlap; idle lanes issue no-op atomics
-// instead of branching.  Called by all 64 lanes; st.ovf is wave-uniform
-// afterwards.
+// append targets that became pending to list P.  Two LDS steps, each issued
+// for all NJ slots before any result is used: claim-or-find the target's slot
+// (compare-and-swap on an empty home slot doubles as the first probe), then
+// the packed atomicMin.  Idle lanes issue no-op atomics instead of branching.
+// Called by all 64 lanes; st.ovf is wave-uniform afterwards.
 template <int HB, int NJ>
 __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, uint32_t P,
                                              const ArcRec *r, const uint32_t *nd, uint32_t bound) {
     constexpr uint32_t H = Tier<HB>::H;
     constexpr uint32_t PC = Tier<HB>::PC;
-    // slot states: 0 idle, 1 slot holds y, 2 slot claimed for y, 3 keep probing, 4 home slot empty
-    uint32_t h[NJ], k[NJ], stt[NJ], old[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) h[j] = slot_hash<HB>(static_cast<uint32_t>(r[j].y));
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) k[j] = lds_load(&L.key[h[j]]);
+    // slot states: 0 idle, 1 slot holds y, 2 slot claimed for y, 3 keep probing
+    uint32_t h[NJ], stt[NJ], old[NJ];
+    bool big = false;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const uint32_t y = static_cast<uint32_t>(r[j].y);
-        stt[j] = nd[j] > bound ? 0u : ((k[j] & ~kPend) == y ? 1u : (k[j] == kEmpty ? 4u : 3u));
+        h[j] = slot_hash<HB>(static_cast<uint32_t>(r[j].y));
+        big |= nd[j] <= bound && nd[j] > kPackMax;
     }
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
-        old[j] = atomicCAS(&L.key[h[j]], stt[j] == 4u ? kEmpty : 0xFFFFFFFFu, static_cast<uint32_t>(r[j].y));
+        old[j] = atomicCAS(&L.key[h[j]], nd[j] <= bound ? kEmpty : kNoKey, static_cast<uint32_t>(r[j].y));
     bool probe = false;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const uint32_t y = static_cast<uint32_t>(r[j].y);
-        if (stt[j] == 4u) stt[j] = old[j] == kEmpty ? 2u : ((old[j] & ~kPend) == y ? 1u : 3u);
+        stt[j] = nd[j] > bound ? 0u : (old[j] == kEmpty ? 2u : (old[j] == y ? 1u : 3u));
         probe |= stt[j] == 3u;
     }
-    bool lost = false;
+    bool lost = big;
     if (__ballot(probe) != 0) {
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
@@ -213,41 +220,37 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, ui
                 uint32_t hh = h[j];
                 for (uint32_t q = 1; q < H; ++q) {
                     hh = (hh + 1) & (H - 1);
-                    const uint32_t kk = lds_load(&L.key[hh]);
-                    if ((kk & ~kPend) == y) { stt[j] = 1u; break; }
-                    if (kk == kEmpty) {
-                        const uint32_t o = atomicCAS(&L.key[hh], kEmpty, y);
-                        if (o == kEmpty) { stt[j] = 2u; break; }
-                        if ((o & ~kPend) == y) { stt[j] = 1u; break; }
-                    }
+                    const uint32_t o = atomicCAS(&L.key[hh], kEmpty, y);
+                    if (o == kEmpty) { stt[j] = 2u; break; }
+                    if (o == y) { stt[j] = 1u; break; }
                 }
                 if (stt[j] == 3u) lost = true;
                 h[j] = hh;
             }
         }
     }
-    uint32_t v[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        v[j] = (stt[j] == 1u || stt[j] == 2u) ? nd[j] : kInf;
-        old[j] = atomicMin(&L.dist[h[j]], v[j]);
-    }
-    bool imp[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        imp[j] = v[j] < old[j];
-        old[j] = atomicOr(&L.key[h[j]], imp[j] ? kPend : 0u);
+        const uint32_t v =
+            (stt[j] == 1u || stt[j] == 2u) && nd[j] <= kPackMax ? (nd[j] << 1) | 1u : kWordNone;
+        old[j] = atomicMin(&L.dw[h[j]], v);
+        // 4: improved a pending vertex; 5: improved an idle or new one, which this lane appends
+        stt[j] = (v < old[j]) ? ((old[j] == kWordNone || (old[j] & 1u) == 0u) ? 5u : 4u) : stt[j];
     }
     uint64_t mA[NJ];
     uint32_t nadd = 0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const bool app = imp[j] && (old[j] & kPend) == 0;
-        st.imin = min(st.imin, imp[j] ? nd[j] : kInf);
-        st.nins += popc(__ballot(stt[j] == 2u));
-        mA[j] = __ballot(app);
+        const bool imp = stt[j] >= 4u;
+        st.imin = min(st.imin, imp ? nd[j] : kInf);
+        mA[j] = __ballot(stt[j] == 5u);
         nadd += popc(mA[j]);
+        lost |= stt[j] == 5u && (r[j].yend - r[j].ybeg) > 0xFFFF;
     }
+    uint32_t ins = 0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) ins += popc(__ballot(old[j] == kWordNone && stt[j] >= 4u));
+    st.nins += ins;
     if (__ballot(lost) != 0 || st.nins > (3u * H) / 4u || st.np + nadd > PC) {
         st.ovf = true;
         return;
@@ -255,44 +258,38 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, ui
     uint32_t base = st.np;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const bool app = (mA[j] >> lane_id()) & 1u;
+        const bool app = stt[j] == 5u;
         const uint32_t idx = app ? base + mbcnt(mA[j]) : PC;
-        L.slot[P][idx] = h[j];
+        L.ent[P][idx] = h[j] | (static_cast<uint32_t>(r[j].yend - r[j].ybeg) << 16);
         L.beg[P][idx] = r[j].ybeg;
-        L.end[P][idx] = r[j].yend;
         base += popc(mA[j]);
     }
     st.np = base;
 }
 
-// Load window arcs j*64 + lane (j < NJ) of the flattened frontier arc list
-// and relax them.  Every load is issued before any is used; lanes past the
-// window's end load arc 0 and stay idle.
+// Load window arcs j*64 + lane (j < NJ) and relax them.  Every load is issued
+// before any is used; lanes past the window's end load arc 0 and stay idle.
 template <int HB, int NJ>
 __device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, uint32_t P,
-                                            const ArcRec *__restrict__ arcs, uint32_t cnt, uint32_t wb,
-                                            int32_t b, uint32_t excl, uint32_t d, uint32_t bound) {
+                                            const ArcRec *__restrict__ arcs, uint32_t cnt,
+                                            uint32_t bound) {
     const uint32_t lane = lane_id();
     int32_t idx[NJ];
     uint32_t od[NJ];
-    bool act[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const uint32_t t = j * 64 + lane;
-        act[j] = t < cnt;
-        const uint32_t o = L.own[act[j] ? t : 0u];
-        const int32_t ob = __shfl(b, static_cast<int>(o));
-        const uint32_t ox = static_cast<uint32_t>(__shfl(static_cast<int>(excl), static_cast<int>(o)));
-        od[j] = static_cast<uint32_t>(__shfl(static_cast<int>(d), static_cast<int>(o)));
-        idx[j] = act[j] ? ob + static_cast<int32_t>(wb + t - ox) : 0;
+        const uint32_t tc = t < cnt ? t : 0u;
+        idx[j] = t < cnt ? L.widx[tc] : 0;
+        od[j] = L.wd[tc];
     }
     ArcRec r[NJ];
     uint32_t nd[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) r[j] = arcs[idx[j]];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) nd[j] = act[j] ? sat_add(od[j], r[j].w) : kInf;
-    wave_sync();  // own[] fully read before the next window rewrites it
+    for (int j = 0; j < NJ; ++j) nd[j] = (j * 64 + lane < cnt) ? sat_add(od[j], r[j].w) : kInf;
+    wave_sync();  // window map fully read before the next window rewrites it
     relax_window<HB, NJ>(L, st, P, r, nd, bound);
 }
 
@@ -306,7 +303,7 @@ __device__ __forceinline__ void tighten_bound(const JoinArgs &a) {
     if ((threadIdx.x & 63u) == 0) atomicMin(&a.ctl->theta, b);
 }
 
-// Write this wave's staged pairs (L.beg[0] = v, L.end[0] = dist) for source u.
+// Write this wave's staged pairs (v in L.beg[0], dist in L.ent[0]) for source u.
 template <int HB>
 __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a, int32_t u,
                                             uint32_t &nst) {
@@ -322,7 +319,7 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
             rn_pair p;
             p.u = u;
             p.v = L.beg[0][i];
-            p.dist = static_cast<uint32_t>(L.end[0][i]);
+            p.dist = L.ent[0][i];
             a.pairs[idx] = p;
         }
     }
@@ -350,22 +347,21 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
     const int32_t ue = a.row_ptr[u + 1];
     if (lane == 0) {
         const uint32_t h0 = slot_hash<HB>(static_cast<uint32_t>(u));   // table is empty
-        lds_store(&L.key[h0], static_cast<uint32_t>(u) | kPend);
-        L.dist[h0] = 0;
-        L.slot[0][0] = h0;
+        lds_store(&L.key[h0], static_cast<uint32_t>(u));
+        L.dw[h0] = 1u;                                                // distance 0, pending
+        L.ent[0][0] = h0 | (static_cast<uint32_t>(min(ue - ub, 0xFFFF)) << 16);
         L.beg[0][0] = ub;
-        L.end[0][0] = ue;
     }
     wave_sync();
     WaveState st;
     st.np = 1;
     st.nins = 1;
-    st.ovf = false;
+    st.ovf = (ue - ub) > 0xFFFF;
     uint32_t P = 0;      // list receiving appends (the pending list)
     uint32_t pmin = 0;
     uint32_t bound = a.theta;
 
-    while (st.np > 0) {
+    while (st.np > 0 && !st.ovf) {
         bound = current_bound(a);
         uint32_t F, nf;
         uint32_t kmin = kInf;
@@ -384,24 +380,21 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
                 const uint32_t i = base + lane;
                 const bool valid = i < st.np;
                 const uint32_t ic = valid ? i : 0u;
-                const uint32_t s = L.slot[P][ic];
+                const uint32_t e = L.ent[P][ic];
                 const int32_t b = L.beg[P][ic];
-                const int32_t e = L.end[P][ic];
-                const uint32_t d = L.dist[s];
+                const uint32_t d = L.dw[e & 0xFFFFu] >> 1;
                 const bool isF = valid && d < thr && d <= bound;
                 const bool isK = valid && d >= thr && d <= bound;
                 const bool drop = valid && d > bound;
                 const uint64_t mF = __ballot(isF), mK = __ballot(isK);
                 wave_sync();  // every lane has read its entry before the in-place compaction
-                atomicAnd(&L.key[s], drop ? ~kPend : 0xFFFFFFFFu);
+                atomicAnd(&L.dw[e & 0xFFFFu], drop ? ~1u : 0xFFFFFFFFu);   // dropped: no longer pending
                 const uint32_t fi = isF ? nf + mbcnt(mF) : static_cast<uint32_t>(PC);
-                L.slot[F][fi] = s;
+                L.ent[F][fi] = e;
                 L.beg[F][fi] = b;
-                L.end[F][fi] = e;
                 const uint32_t ki = isK ? nk + mbcnt(mK) : static_cast<uint32_t>(PC);
-                L.slot[P][ki] = s;
+                L.ent[P][ki] = e;
                 L.beg[P][ki] = b;
-                L.end[P][ki] = e;
                 kmin = min(kmin, isK ? d : kInf);
                 nf += popc(mF);
                 nk += popc(mK);
@@ -415,25 +408,28 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
             const uint32_t f = fb + lane;
             const bool valid = f < nf;
             const uint32_t fc = valid ? f : 0u;
-            const uint32_t s = L.slot[F][fc];
+            const uint32_t e = L.ent[F][fc];
             const int32_t b = L.beg[F][fc];
-            const int32_t e = L.end[F][fc];
-            const uint32_t d = L.dist[s];
-            atomicAnd(&L.key[s], valid ? ~kPend : 0xFFFFFFFFu);  // expanded now: no longer pending
-            const uint32_t deg = (valid && d <= bound) ? static_cast<uint32_t>(e - b) : 0u;
+            const uint32_t s = e & 0xFFFFu;
+            const uint32_t d = L.dw[s] >> 1;
+            atomicAnd(&L.dw[s], valid ? ~1u : 0xFFFFFFFFu);  // expanded now: no longer pending
+            const uint32_t deg = (valid && d <= bound) ? (e >> 16) : 0u;
             const uint32_t incl = wave_incl_scan(deg);
             const uint32_t excl = incl - deg;
             const uint32_t total = readlane(incl, 63);
             for (uint32_t wb = 0; wb < total && !st.ovf; wb += kWin) {
                 const uint32_t lo = max(excl, wb), hi = min(excl + deg, wb + kWin);
-                for (uint32_t p = lo; p < hi; ++p) L.own[p - wb] = static_cast<uint8_t>(lane);
+                for (uint32_t p = lo; p < hi; ++p) {
+                    L.widx[p - wb] = b + static_cast<int32_t>(p - excl);
+                    L.wd[p - wb] = d;
+                }
                 wave_sync();
                 const uint32_t cnt = min(kWin, total - wb);
                 switch ((cnt + 63u) / 64u) {
-                    case 1: window_step<HB, 1>(L, st, P, a.arcs, cnt, wb, b, excl, d, bound); break;
-                    case 2: window_step<HB, 2>(L, st, P, a.arcs, cnt, wb, b, excl, d, bound); break;
-                    case 3: window_step<HB, 3>(L, st, P, a.arcs, cnt, wb, b, excl, d, bound); break;
-                    default: window_step<HB, 4>(L, st, P, a.arcs, cnt, wb, b, excl, d, bound); break;
+                    case 1: window_step<HB, 1>(L, st, P, a.arcs, cnt, bound); break;
+                    case 2: window_step<HB, 2>(L, st, P, a.arcs, cnt, bound); break;
+                    case 3: window_step<HB, 3>(L, st, P, a.arcs, cnt, bound); break;
+                    default: window_step<HB, 4>(L, st, P, a.arcs, cnt, bound); break;
                 }
                 wave_sync();
             }
@@ -453,16 +449,15 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
         for (int j = 0; j < U; ++j) {
             const uint32_t slot = g0 + j * 64 + lane;
             k[j] = lds_load(&L.key[slot]);
-            d[j] = L.dist[slot];
+            d[j] = L.dw[slot] >> 1;
             sb[j] = 0;
-            if (!st.ovf && k[j] != kEmpty) sb[j] = a.sbits[(k[j] & ~kPend) >> 5];
+            if (!st.ovf && k[j] != kEmpty) sb[j] = a.sbits[k[j] >> 5];
         }
         if (a.count_work && !st.ovf) {
 #pragma unroll
             for (int j = 0; j < U; ++j)
                 if (k[j] != kEmpty && d[j] <= bound) {
-                    const uint32_t y = k[j] & ~kPend;
-                    warcs += static_cast<unsigned long long>(a.row_ptr[y + 1] - a.row_ptr[y]);
+                    warcs += static_cast<unsigned long long>(a.row_ptr[k[j] + 1] - a.row_ptr[k[j]]);
                     wsettled += 1;
                 }
         }
@@ -470,18 +465,18 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
         for (int j = 0; j < U; ++j) {
             const uint32_t slot = g0 + j * 64 + lane;
             lds_store(&L.key[slot], kEmpty);
-            L.dist[slot] = kInf;
+            L.dw[slot] = kWordNone;
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            const uint32_t y = k[j] & ~kPend;
-            const bool m = !st.ovf && k[j] != kEmpty && ((sb[j] >> (y & 31u)) & 1u) && d[j] <= bound;
+            const uint32_t y = k[j];
+            const bool m = !st.ovf && y != kEmpty && ((sb[j] >> (y & 31u)) & 1u) && d[j] <= bound;
             const uint64_t mM = __ballot(m);
             if (a.kcp && m) atomicAdd(&a.cand_hist[dist_bin(d[j])], 1u);
             emitted += popc(mM);
             const uint32_t idx = m ? nst + mbcnt(mM) : static_cast<uint32_t>(PC);
             L.beg[0][idx] = static_cast<int32_t>(y);
-            L.end[0][idx] = static_cast<int32_t>(d[j]);
+            L.ent[0][idx] = d[j];
             nst += popc(mM);
             if (nst + 64 > static_cast<uint32_t>(PC)) {
                 wave_sync();
@@ -524,7 +519,7 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
     if (blockIdx.x >= 8u * per) return;
     for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(H); i += 64) {
         lds_store(&L.key[i], kEmpty);
-        L.dist[i] = kInf;
+        L.dw[i] = kWordNone;
     }
     wave_sync();
     for (uint32_t t = blockIdx.x; t < 8u * per; t += gridDim.x) {
