@@ -198,7 +198,8 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, ui
     bool big = false;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        h[j] = slot_hash<HB>(static_cast<uint32_t>(r[j].y));
+        // idle lanes aim their no-op atomics at distinct slots: a shared address would serialise
+        h[j] = nd[j] <= bound ? slot_hash<HB>(static_cast<uint32_t>(r[j].y)) : lane_id();
         big |= nd[j] <= bound && nd[j] > kPackMax;
     }
 #pragma unroll
@@ -388,7 +389,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
                 const bool drop = valid && d > bound;
                 const uint64_t mF = __ballot(isF), mK = __ballot(isK);
                 wave_sync();  // every lane has read its entry before the in-place compaction
-                atomicAnd(&L.dw[e & 0xFFFFu], drop ? ~1u : 0xFFFFFFFFu);   // dropped: no longer pending
+                atomicAnd(&L.dw[valid ? (e & 0xFFFFu) : lane], drop ? ~1u : 0xFFFFFFFFu);  // dropped: not pending
                 const uint32_t fi = isF ? nf + mbcnt(mF) : static_cast<uint32_t>(PC);
                 L.ent[F][fi] = e;
                 L.beg[F][fi] = b;
@@ -412,7 +413,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
             const int32_t b = L.beg[F][fc];
             const uint32_t s = e & 0xFFFFu;
             const uint32_t d = L.dw[s] >> 1;
-            atomicAnd(&L.dw[s], valid ? ~1u : 0xFFFFFFFFu);  // expanded now: no longer pending
+            atomicAnd(&L.dw[valid ? s : lane], valid ? ~1u : 0xFFFFFFFFu);  // expanded now: not pending
             const uint32_t deg = (valid && d <= bound) ? (e >> 16) : 0u;
             const uint32_t incl = wave_incl_scan(deg);
             const uint32_t excl = incl - deg;
@@ -744,11 +745,11 @@ __global__ __launch_bounds__(1024) void k_rank_emit(const uint32_t *rbits, uint3
 // ------------------------------------------------------------------ radix sort
 // Pairs are ordered by the key (dist, u, v).  When dist and the two ids fit in
 // 64 bits the pairs are packed into uint64 keys dist:u:v (vb bits per id) and
-// sorted by one launch per 8-bit digit: each pass takes its block offsets from
-// a per-tile digit histogram, which the previous pass accumulated for the
-// tiles its items landed in.  Otherwise a two-launch-per-digit sort of the
-// 12-byte records is used.
-constexpr uint32_t kSortBlocks = 64;
+// sorted by 8-bit digits, two launches per digit: a scan of the per-tile
+// digit histogram (which the previous pass accumulated for the tiles its items
+// landed in) and the stable scatter.  Otherwise a three-launch-per-digit sort
+// of the 12-byte records is used.
+constexpr uint32_t kSortBlocks = 256;
 constexpr uint32_t kSortPassesMax = 8;
 
 __device__ __forceinline__ void sort_tile(const unsigned long long *nptr, unsigned long long cap,
@@ -792,23 +793,23 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *ws
     return off + incl - v;
 }
 
-// This block's first output position for each digit (thread d computes digit
-// d from its row of kSortBlocks counts, read as independent 16-byte loads).
-__device__ __forceinline__ uint32_t digit_base(const uint32_t *hist, uint32_t *ws) {
-    const uint32_t tid = threadIdx.x, blk = blockIdx.x;
-    const uint4 *row = reinterpret_cast<const uint4 *>(hist + tid * kSortBlocks);
-    uint4 v[kSortBlocks / 4];
-#pragma unroll
-    for (uint32_t q = 0; q < kSortBlocks / 4; ++q) v[q] = row[q];
-    uint32_t tot = 0, pre = 0;
-#pragma unroll
-    for (uint32_t q = 0; q < kSortBlocks / 4; ++q) {
-        const uint32_t b = 4 * q;
-        tot += v[q].x + v[q].y + v[q].z + v[q].w;
-        pre += (b < blk ? v[q].x : 0u) + (b + 1 < blk ? v[q].y : 0u) + (b + 2 < blk ? v[q].z : 0u) +
-               (b + 3 < blk ? v[q].w : 0u);
-    }
-    return block_excl_scan_256(tot, ws) + pre;
+// Scan of one pass's histogram, laid out [digit][tile]: each row becomes its
+// exclusive prefix over tiles, and tot[d] the row total (one block per digit).
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t *hist, uint32_t *tot) {
+    __shared__ uint32_t ws[4];
+    const uint32_t d = blockIdx.x, tid = threadIdx.x;
+    const uint32_t v = hist[d * kSortBlocks + tid];
+    const uint32_t e = block_excl_scan_256(v, ws);
+    hist[d * kSortBlocks + tid] = e;
+    if (tid == kSortBlocks - 1) tot[d] = e + v;
+}
+
+// This block's first output position for each digit (thread d computes digit d)
+// from the scanned histogram row and the digit totals.
+__device__ __forceinline__ uint32_t digit_start(const uint32_t *hist, const uint32_t *tot, uint32_t *ws) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t pre = hist[tid * kSortBlocks + blockIdx.x];
+    return block_excl_scan_256(tot[tid], ws) + pre;
 }
 
 __device__ __forceinline__ uint64_t pack_pair(const rn_pair &p, uint32_t vb) {
@@ -840,7 +841,7 @@ __global__ __launch_bounds__(256) void k_sort_pack(const rn_pair *in, uint64_t *
 __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *in, uint64_t *out, rn_pair *out_pairs,
                                                    const unsigned long long *nptr, unsigned long long cap,
                                                    uint32_t shift, uint32_t vb, const uint32_t *hist,
-                                                   uint32_t *hist_next, uint32_t next_shift,
+                                                   const uint32_t *tot, uint32_t *hist_next, uint32_t next_shift,
                                                    const QueryCtl *ctl, unsigned long long user_cap,
                                                    unsigned long long out_limit, int last_tier) {
     __shared__ uint32_t base[256];
@@ -852,7 +853,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *in, uint64_t 
         if (ctl->err != 0 || n > cap || min(n, out_limit) > user_cap) return;
         if (last_tier >= 0 && ctl->novf[last_tier] != 0) return;
     }
-    base[tid] = digit_base(hist, ws);
+    base[tid] = digit_start(hist, tot, ws);
     uint64_t beg, end, tile;
     sort_tile(nptr, cap, beg, end, tile);
     const uint32_t mask = (1u << vb) - 1u;
@@ -914,12 +915,13 @@ __global__ __launch_bounds__(256) void k_radix_hist(const rn_pair *in, const uns
 __global__ __launch_bounds__(256) void k_radix_scatter(const rn_pair *in, rn_pair *out,
                                                        const unsigned long long *nptr,
                                                        unsigned long long cap, uint32_t bit,
-                                                       uint32_t vb, const uint32_t *hist) {
+                                                       uint32_t vb, const uint32_t *hist,
+                                                       const uint32_t *tot) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t ws[4];
     const uint32_t tid = threadIdx.x;
-    base[tid] = digit_base(hist, ws);
+    base[tid] = digit_start(hist, tot, ws);
     uint64_t beg, end, tile;
     sort_tile(nptr, cap, beg, end, tile);
     for (uint64_t c = beg; c < end; c += 256) {
@@ -1078,7 +1080,8 @@ hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslot
     return hipGetLastError();
 }
 
-size_t sort_hist_words() { return static_cast<size_t>(kSortPassesMax + 1) * 256u * kSortBlocks; }
+// per pass: a [256 digits][kSortBlocks tiles] histogram, then 256 digit totals
+size_t sort_hist_words() { return static_cast<size_t>(kSortPassesMax + 1) * 256u * (kSortBlocks + 1); }
 
 hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned long long *n,
                               unsigned long long cap, uint32_t max_dist, int32_t V, uint32_t *hist,
@@ -1091,13 +1094,16 @@ hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned l
         uint64_t *ka = reinterpret_cast<uint64_t *>(scratch);
         uint64_t *kb = reinterpret_cast<uint64_t *>(pairs);   // records are packed into ka first
         const size_t hw = 256u * kSortBlocks;
+        uint32_t *tot = hist + (kSortPassesMax + 1) * hw;
         hipLaunchKernelGGL(k_sort_pack, dim3(kSortBlocks), dim3(256), 0, s, pairs, ka, n, cap, vb, hist);
         uint64_t *in = ka, *o = kb;
         for (uint32_t p = 0; p < passes; ++p) {
             const bool last = p + 1 == passes;
+            hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist + p * hw, tot + p * 256u);
             hipLaunchKernelGGL(k_sort_pass, dim3(kSortBlocks), dim3(256), 0, s, in, o, last ? out : nullptr,
-                               n, cap, 8u * p, vb, hist + p * hw, last ? nullptr : hist + (p + 1) * hw,
-                               8u * (p + 1), ctl, user_cap, out_limit, last_tier);
+                               n, cap, 8u * p, vb, hist + p * hw, tot + p * 256u,
+                               last ? nullptr : hist + (p + 1) * hw, 8u * (p + 1), ctl, user_cap, out_limit,
+                               last_tier);
             uint64_t *t = in;
             in = o;
             o = t;
@@ -1105,10 +1111,12 @@ hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned l
         return hipGetLastError();
     }
     rn_pair *in = pairs, *o = scratch;
+    uint32_t *tot = hist + 256u * kSortBlocks;
     for (uint32_t bit = 0; bit < bits; bit += 8) {
         hipLaunchKernelGGL(k_radix_hist, dim3(kSortBlocks), dim3(256), 0, s, in, n, cap, bit, vb, hist);
+        hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tot);
         hipLaunchKernelGGL(k_radix_scatter, dim3(kSortBlocks), dim3(256), 0, s, in, o, n, cap, bit, vb,
-                           hist);
+                           hist, tot);
         rn_pair *t = in;
         in = o;
         o = t;
