@@ -90,7 +90,7 @@ rn_status rn_graph_load(int32_t V, int64_t A, const int32_t *row_ptr, const int3
 /* Free a handle and all its device memory.  NULL is accepted. */
 void rn_graph_free(rn_graph *g);
 
-/* Number of vertices / arcs of a loaded graph (0 for NULL). */
+/* Number of vertices / arcs of a loaded graph, summed over its graphs (0 for NULL). */
 int32_t rn_graph_num_vertices(const rn_graph *g);
 int64_t rn_graph_num_arcs(const rn_graph *g);
 
@@ -115,16 +115,17 @@ rn_status rn_partition_host(int32_t V, int64_t A, const int32_t *row_ptr, const 
                             int32_t *part_out, int32_t *order_out);
 
 /*
- * rn_partition -- partition a loaded graph (as rn_partition_host) and keep the
- * leaf-by-leaf vertex order in the handle.  Later joins visit their sources in
- * that order, so sources of one leaf run next to each other on the device
- * (well-separated regions, Section 3).  Join results never depend on it.
- *   part_out  host int32[V] or NULL, as in rn_partition_host
+ * rn_partition -- partition each graph of a handle (as rn_partition_host) and
+ * keep the leaf-by-leaf vertex order in the handle.  Later joins visit their
+ * sources in that order, so sources of one leaf run next to each other on the
+ * device (well-separated regions, Section 3).  Join results never depend on it.
+ *   part_out  host int32[total V] or NULL: the leaf id of each vertex, graph
+ *             after graph; leaf ids are numbered on across the graphs
  */
 rn_status rn_partition(rn_graph *g, float alpha, int32_t max_leaf, int32_t *part_out);
 
 /*
- * rn_dist_join -- the theta-join.
+ * rn_dist_join -- the theta-join (on graph 0 of the handle).
  *   R, nR   device int32[nR], nR >= 1: the left set; ids in [0, V), no duplicates
  *   S, nS   device int32[nS], nS >= 1: the right set; ids in [0, V), no
  *           duplicates, disjoint from R (the paper's sets are disjoint)
@@ -141,7 +142,7 @@ rn_status rn_dist_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t 
                        uint32_t theta, rn_pair *out, int64_t cap, int64_t *n_out, void *stream);
 
 /*
- * rn_kcp_join -- the k-closest-pairs join.
+ * rn_kcp_join -- the k-closest-pairs join (on graph 0 of the handle).
  *   R, nR, S, nS  as for rn_dist_join
  *   k       1 <= k <= 2^24
  *   out     device rn_pair[cap]; cap >= min(k, nR * nS) always suffices
@@ -163,6 +164,102 @@ rn_status rn_kcp_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *
  */
 rn_status rn_set_tuning(rn_graph *g, int64_t delta, int32_t hash_log2);
 rn_status rn_get_tuning(const rn_graph *g, uint32_t *delta, int32_t *hash_log2);
+
+/*
+ * ---- Several graphs, many queries per call (the batched form).
+ *
+ * A handle may hold several independent graphs.  rn_join_batch runs any mix
+ * of theta-joins and k-closest-pairs queries over them as one launch sequence
+ * on one stream: the searches of all queries share the device at once, so
+ * many small queries cost about as much as one large one.
+ */
+
+/*
+ * rn_graph_load_many -- load n graphs into one handle (graph i keeps its own
+ * vertex ids 0 .. V[i]-1).  Each graph is a CSR as for rn_graph_load; the
+ * arrays are host pointers.  The total vertex count must stay below 2^31 - 1
+ * and the total arc count below 2^31.  rn_graph_load is this call with n = 1.
+ */
+rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, const int32_t *const *row_ptr,
+                             const int32_t *const *col, const uint32_t *const *w, rn_graph **out);
+
+/* Number of graphs in a handle (0 for NULL), and the size of graph i. */
+int32_t rn_graph_count(const rn_graph *g);
+rn_status rn_graph_size(const rn_graph *g, int32_t i, int32_t *V, int64_t *A);
+
+#define RN_DELTA_DEFAULT 0xFFFFFFFFu   /* rn_query.delta: use the handle's setting */
+
+/*
+ * One query of a batch.
+ *   R, S      device int32[nR], int32[nS]: node sets of graph `graph`, with the
+ *             rules of rn_dist_join (ids in [0, V), no duplicates, disjoint)
+ *   graph     index of the graph in the handle
+ *   k         0: the theta-join (every pair within theta).  1 <= k <= 2^24:
+ *             the first min(k, n) pairs of the (dist, u, v) order among the n
+ *             pairs within theta, i.e. the k closest pairs within the bound
+ *             (theta = 2^32 - 2 for the unbounded query; Section 4 casts both
+ *             queries as "k results within theta")
+ *   theta     distance bound, inclusive, <= 2^32 - 2
+ *   delta     bucket width for this query's searches, or RN_DELTA_DEFAULT
+ *   hash_log2 first on-chip table size for its searches (8..14), or 0 for the
+ *             default (the handle's setting for a theta-join, 8 for k > 0)
+ * delta and hash_log2 never change results.
+ */
+typedef struct rn_query {
+    const int32_t *R;
+    const int32_t *S;
+    int32_t nR, nS;
+    int32_t graph;
+    int32_t k;
+    uint32_t theta;
+    uint32_t delta;
+    int32_t hash_log2;
+    int32_t reserved;   /* set to 0 */
+} rn_query;
+
+/*
+ * rn_join_batch -- run nq queries (1 <= nq <= 65536) as one call.
+ *   out       device rn_pair[cap]: query i's pairs are out[offsets[i] ..
+ *             offsets[i+1]), sorted by (dist, u, v), ids local to its graph
+ *   offsets   host int64[nq + 1]: segment starts; offsets[nq] = total pairs
+ *   status    host int32[nq] or NULL: RN_OK, or RN_ERR_ARG for a query whose
+ *             R or S is invalid (bad id, duplicate, overlap); such a query
+ *             gets an empty segment and the others are still answered
+ * Returns RN_OK when every query succeeded.  RN_ERR_CAPACITY when the total
+ * exceeds cap: offsets then give the layout needed and out is left untouched.
+ * RN_ERR_ARG when a query is malformed on the host side (bad graph index,
+ * count, pointer, k or theta; nothing runs, status marks it) or invalid on
+ * the device (status marks it; the valid queries' results are written).
+ */
+rn_status rn_join_batch(rn_graph *g, const rn_query *q, int32_t nq, rn_pair *out, int64_t cap, int64_t *offsets,
+                        int32_t *status, void *stream);
+
+/*
+ * rn_autotune -- choose delta and hash_log2 for each query by timing a few
+ * candidate settings on a sample of its sources (the first min(nR, sample)
+ * entries of R) and keeping the one with the least relaxation time.  Writes
+ * q[i].delta and q[i].hash_log2; results never depend on them.  The device
+ * work runs on `stream`.
+ */
+rn_status rn_autotune(rn_graph *g, rn_query *q, int32_t nq, int32_t sample, void *stream);
+
+/*
+ * Captured plans: a batch recorded once into a HIP graph and replayed with
+ * one graph launch per run.  The plan keeps q[] (and so the device pointers
+ * R, S) and out, cap as given; callers may change the contents of R, S
+ * between runs but not their sizes.  A plan owns its own call buffers; runs
+ * and other calls on the same handle must not overlap (RN_ERR_BUSY).
+ *   rn_plan_create  runs the batch once on `stream` to size its buffers, then
+ *                   captures it
+ *   rn_plan_run     replays it on `stream` and reports as rn_join_batch (if a
+ *                   run outgrows the record buffer it is re-sized, re-run and
+ *                   re-captured)
+ */
+typedef struct rn_plan rn_plan;
+rn_status rn_plan_create(rn_graph *g, const rn_query *q, int32_t nq, rn_pair *out, int64_t cap, void *stream,
+                         rn_plan **plan);
+rn_status rn_plan_run(rn_plan *p, int64_t *offsets, int32_t *status, void *stream);
+void rn_plan_free(rn_plan *p);
 
 /* Per-call statistics of the most recent join on a handle. */
 typedef struct rn_stats {

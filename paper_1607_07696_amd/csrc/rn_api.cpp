@@ -1,9 +1,10 @@
 // rn_api.cpp -- host side of the C ABI declared in include/rn.h.
 //
-// Owns graph residency (rn_graph_load), query buffers, argument checks, the
-// launch sequence of a join and the read-back of its control block.  All
-// device work of a call is enqueued on the caller's stream; the call waits for
-// it once, at the end, to report the result count.
+// Owns graph residency (one concatenated CSR for all graphs of a handle),
+// call buffers, argument checks, the launch sequence of a call and the
+// read-back of its control block.  All device work of a call is enqueued on
+// the caller's stream; the call waits for it once, at the end, to report the
+// result counts.  Single queries are batches of one.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -11,6 +12,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "rn.h"
@@ -38,6 +40,12 @@ rn_status hip_fail(hipError_t e, const char *what) {
         if (_e != hipSuccess) return hip_fail(_e, what);    \
     } while (0)
 
+#define RN_TRY(call)                          \
+    do {                                      \
+        rn_status _s = (call);                \
+        if (_s != RN_OK) return _s;           \
+    } while (0)
+
 template <typename T>
 hipError_t dev_alloc(T **p, size_t count) {
     *p = nullptr;
@@ -51,55 +59,149 @@ void dev_free(T *&p) {
     p = nullptr;
 }
 
+template <typename T>
+void host_free(T *&p) {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+}
+
 // Stage timing events (used when profiling is on).
 enum { EV_START, EV_STAGED, EV_TIER0, EV_RELAXED, EV_SELECTED, EV_DONE, EV_COUNT };
+
+constexpr int kSide = kMaxHB - kMinHB;   // side streams for concurrent first-tier launches
+constexpr int32_t kMaxQueries = 65536;
+constexpr unsigned long long kRecCapMax = 1ull << 31;
+
+size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
+
+uint32_t bitlen(uint64_t x) {
+    uint32_t b = 0;
+    while (x) { ++b; x >>= 1; }
+    return b;
+}
+
+// Device and pinned host buffers of calls; a handle owns one for its eager
+// calls, every plan owns its own.
+struct Workspace {
+    uint32_t *d_block = nullptr;    // CallCtl | QueryState[nq] | S bitmaps | rank bitmaps | histograms | sort
+    size_t block_words = 0;
+    uint8_t *d_desc = nullptr;      // QueryDesc[nq] | ebase[nq+1] | rbase[nq+1] | perm[nq]
+    size_t desc_bytes = 0;
+    uint8_t *h_desc = nullptr;      // pinned staging of the same
+    size_t h_desc_bytes = 0;
+    uint8_t *h_state = nullptr;     // pinned read-back of CallCtl | QueryState[nq]
+    size_t h_state_bytes = 0;
+    uint32_t *d_stage = nullptr;
+    size_t stage_words = 0;
+    int32_t *d_src = nullptr;
+    uint32_t *d_srcq = nullptr;
+    int32_t *d_list[kLists] = {};
+    uint32_t *d_listq[kLists] = {};
+    size_t src_cap = 0;
+    Rec *d_recs[2] = {};
+    unsigned long long rec_cap = 0;
+    hipStream_t side[kSide] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[kSide] = {};
+    hipEvent_t ev[EV_COUNT] = {};
+
+    void release() {
+        dev_free(d_block);
+        dev_free(d_desc);
+        host_free(h_desc);
+        host_free(h_state);
+        dev_free(d_stage);
+        dev_free(d_src);
+        dev_free(d_srcq);
+        for (int i = 0; i < kLists; ++i) {
+            dev_free(d_list[i]);
+            dev_free(d_listq[i]);
+        }
+        dev_free(d_recs[0]);
+        dev_free(d_recs[1]);
+        block_words = desc_bytes = h_desc_bytes = h_state_bytes = stage_words = src_cap = 0;
+        rec_cap = 0;
+        for (auto &s : side)
+            if (s) (void)hipStreamDestroy(s), s = nullptr;
+        if (fork) (void)hipEventDestroy(fork), fork = nullptr;
+        for (auto &e : join)
+            if (e) (void)hipEventDestroy(e), e = nullptr;
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e), e = nullptr;
+    }
+};
+
+// One group of queries whose searches start with the same table size.
+struct Group {
+    int hb;
+    int32_t first;          // staging positions [first, end)
+    int32_t end;
+    uint64_t sources;       // sum of nR
+};
+
+// Host-side plan of one call: descriptors, pools and launch shapes.
+struct Prepared {
+    int32_t nq = 0;
+    std::vector<QueryDesc> qd;
+    std::vector<unsigned long long> ebase;
+    std::vector<uint32_t> rbase;
+    std::vector<uint32_t> perm;
+    std::vector<Group> groups;
+    bool any_kcp = false;
+    bool need_list0 = false;
+    bool need_list1 = false;
+    uint32_t qb = 0, vb = 1, max_passes = 1;
+    uint64_t total_R = 0;
+    unsigned long long total_elems = 0;
+    // word offsets in the call block
+    size_t off_qs = 0, off_sbits = 0, off_rbits = 0, off_hists = 0, off_sort = 0, block_words = 0;
+    size_t zero_words = 0;
+    uint32_t sbits_words = 0, rbits_words = 0;
+    size_t desc_bytes = 0, off_ebase = 0, off_rbase = 0, off_perm = 0;
+};
 
 }  // namespace
 
 struct rn_graph {
     int device = 0;
-    int32_t V = 0;
-    int64_t A = 0;
-    std::vector<int32_t> row_ptr, col;
+    int32_t ngraphs = 0;
+    std::vector<int32_t> voff;      // [ngraphs + 1] vertex offsets
+    std::vector<int64_t> aoff;      // [ngraphs + 1] arc offsets
+    std::vector<uint32_t> w_min;    // per graph (0 when it has no arcs)
+    int32_t V = 0;                  // total vertices
+    int64_t A = 0;                  // total arcs
+    int32_t Vmax = 0;
+    std::vector<int32_t> row_ptr, col;   // concatenated, global ids
     std::vector<uint32_t> w;
-    uint32_t w_min = 0, w_max = 0;
 
     int32_t *d_row_ptr = nullptr;
     ArcRec *d_arcs = nullptr;
-    int32_t *d_rank = nullptr;    // vertex -> rank in the source order (nullptr = identity)
-    int32_t *d_order = nullptr;   // rank -> vertex
+    int32_t *d_rank = nullptr;      // global vertex -> rank within its graph (nullptr = identity)
+    int32_t *d_order = nullptr;     // voff + rank -> local vertex
 
     uint32_t delta = 0;
     int hash_log2 = 11;
 
-    // query buffers (grown on demand)
-    uint32_t *d_qblock = nullptr;  // QueryCtl | S bitmap | R bitmap | sort histograms, cleared as one
-    size_t qblock_words = 0;
-    int32_t *d_src = nullptr;
-    uint32_t *d_ovf[kTiers] = {};
-    size_t src_cap = 0;
-    rn_pair *d_pairs[2] = {};
-    unsigned long long pair_cap = 0;
-    uint32_t *d_stage = nullptr;   // source-listing block sums
-    uint32_t *d_gslots = nullptr;  // global-memory tier state (global_slot_words(V) per slot)
+    Workspace ws;
+    uint32_t *d_gslots = nullptr;   // global-memory tier state (global_slot_words(Vmax) per slot)
     uint32_t n_gslots = 0;
-    QueryCtl *h_ctl = nullptr;     // pinned read-back of the control block
 
     std::atomic<int> busy{0};
     bool profiling = false;
     bool count_work = false;
-    hipEvent_t ev[EV_COUNT] = {};
     rn_stats stats{};
+};
 
-    // bitmap sizes rounded to 256-byte multiples keep every region 16-byte aligned
-    size_t bitmap_words() const { return ((static_cast<size_t>(V) + 31) / 32 + 63) / 64 * 64; }
-    size_t ctl_words() const { return (sizeof(QueryCtl) + 255) / 256 * 64; }
-    QueryCtl *d_ctl() const { return reinterpret_cast<QueryCtl *>(d_qblock); }
-    uint32_t *d_sbits() const { return d_qblock + ctl_words(); }
-    uint32_t *d_rbits() const { return d_qblock + ctl_words() + bitmap_words(); }
-    uint32_t *d_hist() const { return d_qblock + ctl_words() + 2 * bitmap_words(); }
-    uint32_t *d_seed_hist() const { return d_hist() + sort_hist_words(); }
-    uint32_t *d_cand_hist() const { return d_seed_hist() + kDistBins; }
+struct rn_plan {
+    rn_graph *g = nullptr;
+    Workspace ws;
+    std::vector<rn_query> q;
+    Prepared prep;
+    rn_pair *out = nullptr;
+    int64_t cap = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
 };
 
 namespace {
@@ -116,108 +218,8 @@ struct BusyGuard {
     }
 };
 
-void release_buffers(rn_graph *g) {
-    dev_free(g->d_qblock);
-    dev_free(g->d_src);
-    for (auto &p : g->d_ovf) dev_free(p);
-    dev_free(g->d_pairs[0]);
-    dev_free(g->d_pairs[1]);
-    dev_free(g->d_stage);
-    dev_free(g->d_gslots);
-    g->n_gslots = 0;
-    g->qblock_words = 0;
-    g->src_cap = 0;
-    g->pair_cap = 0;
-}
-
-rn_status ensure_query_buffers(rn_graph *g, int32_t nR) {
-    const size_t qwords = g->ctl_words() + 2 * g->bitmap_words() + sort_hist_words() + 2 * kDistBins;
-    if (g->qblock_words < qwords) {
-        dev_free(g->d_qblock);
-        RN_HIP(dev_alloc(&g->d_qblock, qwords), "allocating query bitmaps");
-        g->qblock_words = qwords;
-    }
-    if (g->src_cap < static_cast<size_t>(nR)) {
-        dev_free(g->d_src);
-        for (auto &p : g->d_ovf) dev_free(p);
-        const size_t cap = std::max<size_t>(static_cast<size_t>(nR), 1024);
-        RN_HIP(dev_alloc(&g->d_src, cap), "allocating the source list");
-        for (auto &p : g->d_ovf) RN_HIP(dev_alloc(&p, cap), "allocating the re-run lists");
-        g->src_cap = cap;
-    }
-    if (!g->d_stage) RN_HIP(dev_alloc(&g->d_stage, stage_scratch_words(g->V)), "allocating staging scratch");
-    if (!g->d_gslots) {
-        // up to 64 concurrent global-tier searches, within 8 GiB
-        const size_t words = global_slot_words(g->V);
-        size_t n = (size_t{8} << 30) / (4 * words);
-        n = std::max<size_t>(1, std::min<size_t>(n, 64));
-        RN_HIP(dev_alloc(&g->d_gslots, n * words), "allocating global search slots");
-        g->n_gslots = static_cast<uint32_t>(n);
-        const size_t V = static_cast<size_t>(g->V);
-        for (size_t i = 0; i < n; ++i) {
-            RN_HIP(launch_fill_u32(g->d_gslots + i * words, V, kInf, nullptr), "clearing search slots");
-            RN_HIP(launch_fill_u32(g->d_gslots + i * words + V, (V + 31) / 32, 0u, nullptr),
-                   "clearing search slots");
-        }
-        RN_HIP(hipDeviceSynchronize(), "clearing search slots");
-    }
-    if (g->pair_cap == 0) {
-        const unsigned long long cap = 1ull << 20;
-        RN_HIP(dev_alloc(&g->d_pairs[0], cap), "allocating the pair buffer");
-        RN_HIP(dev_alloc(&g->d_pairs[1], cap), "allocating the pair buffer");
-        g->pair_cap = cap;
-    }
-    return RN_OK;
-}
-
-rn_status grow_pairs(rn_graph *g, unsigned long long need) {
-    unsigned long long cap = std::max(need + need / 4, 2 * g->pair_cap);
-    dev_free(g->d_pairs[0]);
-    dev_free(g->d_pairs[1]);
-    g->pair_cap = 0;
-    RN_HIP(dev_alloc(&g->d_pairs[0], cap), "growing the pair buffer");
-    RN_HIP(dev_alloc(&g->d_pairs[1], cap), "growing the pair buffer");
-    g->pair_cap = cap;
-    return RN_OK;
-}
-
-void record(rn_graph *g, int which, hipStream_t s) {
-    if (g->profiling) (void)hipEventRecord(g->ev[which], s);
-}
-
-float elapsed(rn_graph *g, int a, int b) {
-    float ms = 0.f;
-    if (!g->profiling) return 0.f;
-    if (hipEventElapsedTime(&ms, g->ev[a], g->ev[b]) != hipSuccess) return 0.f;
-    return ms;
-}
-
-// On-chip table tiers tried in order: the handle's first choice (a small table
-// for k-closest pairs, whose searches are usually cut short by the bound),
-// then larger ones; the global-memory tier follows them.
-int tier_list(const rn_graph *g, bool kcp, int *hb) {
-    int n = 0;
-    const int first = kcp ? 8 : g->hash_log2;
-    const int cand[kLdsTiers] = {first, std::min(std::max(first + 3, g->hash_log2), 14), 14};
-    for (int c : cand)
-        if (n == 0 || c > hb[n - 1]) hb[n++] = c;
-    return n;
-}
-
-rn_status check_sets(const rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS,
-                     int64_t *n_out) {
-    if (!n_out) return fail(RN_ERR_ARG, "n_out is NULL");
-    *n_out = 0;
-    if (!g) return fail(RN_ERR_ARG, "graph handle is NULL");
-    if (nR < 1 || nS < 1) return fail(RN_ERR_ARG, "R and S must each hold at least one vertex");
-    if (!R || !S) return fail(RN_ERR_ARG, "R or S is NULL");
-    if (static_cast<int64_t>(nR) + nS > static_cast<int64_t>(g->V))
-        return fail(RN_ERR_ARG, "R and S together exceed the vertex count (they must be disjoint)");
-    return RN_OK;
-}
-
 std::string describe_err(uint32_t err) {
-    std::string m = "invalid node sets:";
+    std::string m;
     if (err & kErrRange) m += " id outside [0, V);";
     if (err & kErrDupR) m += " duplicate in R;";
     if (err & kErrDupS) m += " duplicate in S;";
@@ -225,24 +227,449 @@ std::string describe_err(uint32_t err) {
     return m;
 }
 
-// The shared launch sequence of both joins.  `bound` is theta (theta-join) or
-// the largest distance a k-closest-pairs answer may hold.
-rn_status run_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS,
-                   uint32_t bound, bool kcp, int32_t k, rn_pair *out, int64_t cap, int64_t *n_out,
-                   hipStream_t stream);
+// ------------------------------------------------------------------ preparation
+rn_status check_queries(const rn_graph *g, const rn_query *q, int32_t nq, int32_t *status) {
+    if (!g) return fail(RN_ERR_ARG, "graph handle is NULL");
+    if (!q || nq < 1 || nq > kMaxQueries) return fail(RN_ERR_ARG, "need 1 to 65536 queries");
+    int bad = -1;
+    std::string why;
+    uint64_t total_R = 0;
+    for (int32_t i = 0; i < nq; ++i) {
+        const rn_query &x = q[i];
+        const char *m = nullptr;
+        if (x.graph < 0 || x.graph >= g->ngraphs) m = "graph index out of range";
+        else if (x.nR < 1 || x.nS < 1) m = "R and S must each hold at least one vertex";
+        else if (!x.R || !x.S) m = "R or S is NULL";
+        else if (static_cast<int64_t>(x.nR) + x.nS > g->voff[x.graph + 1] - g->voff[x.graph])
+            m = "R and S together exceed the vertex count (they must be disjoint)";
+        else if (x.k < 0 || x.k > (1 << 24)) m = "k must be 0 (theta-join) or in [1, 2^24]";
+        else if (x.theta > kMaxDist) m = "theta must be <= 2^32 - 2";
+        else if (x.hash_log2 != 0 && !join_tier_supported(x.hash_log2)) m = "hash_log2 must be 0 or in [8, 14]";
+        if (status) status[i] = m ? RN_ERR_ARG : RN_OK;
+        if (m && bad < 0) {
+            bad = i;
+            why = m;
+        }
+        total_R += static_cast<uint64_t>(std::max(x.nR, 0));
+    }
+    if (bad >= 0) return fail(RN_ERR_ARG, "query " + std::to_string(bad) + ": " + why);
+    if (total_R >= 0x7FFFFFFFull) return fail(RN_ERR_ARG, "the queries' R sets together exceed 2^31 - 2 sources");
+    return RN_OK;
+}
 
-}  // namespace
+rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p) {
+    p = Prepared{};
+    p.nq = nq;
+    p.qd.resize(nq);
+    p.ebase.assign(nq + 1, 0);
+    p.rbase.assign(nq + 1, 0);
+    p.perm.resize(nq);
+    std::vector<int> hb(nq);
+    uint32_t dmax = 0;
+    for (int32_t i = 0; i < nq; ++i) {
+        const rn_query &x = q[i];
+        hb[i] = x.hash_log2 ? x.hash_log2 : (x.k ? kMinHB : g->hash_log2);
+        p.any_kcp |= x.k > 0;
+        dmax = std::max(dmax, x.theta);
+        p.total_R += static_cast<uint64_t>(x.nR);
+    }
+    // staging order: grouped by first table size, query order within a group
+    for (int32_t i = 0; i < nq; ++i) p.perm[i] = static_cast<uint32_t>(i);
+    std::stable_sort(p.perm.begin(), p.perm.end(), [&](uint32_t a, uint32_t b) { return hb[a] < hb[b]; });
+    uint64_t sw = 0, rw = 0;
+    uint32_t nkcp = 0;
+    for (int32_t s = 0; s < nq; ++s) {
+        const uint32_t i = p.perm[s];
+        const rn_query &x = q[i];
+        const int32_t V = g->voff[x.graph + 1] - g->voff[x.graph];
+        const uint32_t words = static_cast<uint32_t>((static_cast<int64_t>(V) + 31) / 32);
+        QueryDesc &d = p.qd[i];
+        std::memset(&d, 0, sizeof(d));
+        d.R = x.R;
+        d.S = x.S;
+        d.nR = x.nR;
+        d.nS = x.nS;
+        d.voff = g->voff[x.graph];
+        d.V = V;
+        d.theta = x.theta;
+        d.k = static_cast<uint32_t>(x.k);
+        d.delta = x.delta == RN_DELTA_DEFAULT ? g->delta : x.delta;
+        d.sbits = static_cast<uint32_t>(sw);
+        d.rbits = static_cast<uint32_t>(rw);
+        d.hist = x.k ? nkcp * 2 * kDistBins : 0;
+        nkcp += x.k ? 1 : 0;
+        p.rbase[s] = static_cast<uint32_t>(rw);
+        p.ebase[s + 1] = p.ebase[s] + static_cast<unsigned long long>(x.nS) + static_cast<unsigned long long>(x.nR);
+        sw += round_up(words, 4);
+        rw += words;
+        if (sw >= 0xFFFFFFFFull || rw >= 0xFFFFFFFFull) return fail(RN_ERR_ARG, "too many vertices in one call");
+        if (p.groups.empty() || p.groups.back().hb != hb[i]) p.groups.push_back(Group{hb[i], s, s + 1, 0});
+        p.groups.back().end = s + 1;
+        p.groups.back().sources += static_cast<uint64_t>(x.nR);
+    }
+    p.rbase[nq] = static_cast<uint32_t>(rw);
+    p.total_elems = p.ebase[nq];
+    p.sbits_words = static_cast<uint32_t>(sw);
+    p.rbits_words = static_cast<uint32_t>(rw);
+    for (const Group &gr : p.groups) {
+        p.need_list0 |= gr.hb < kRetryHB1;
+        p.need_list1 |= gr.hb < kMaxHB;
+    }
+    p.qb = nq > 1 ? bitlen(static_cast<uint64_t>(nq - 1)) : 0u;
+    p.vb = std::max<uint32_t>(1u, bitlen(static_cast<uint64_t>(std::max(g->Vmax - 1, 0))));
+    p.max_passes = std::max<uint32_t>(1u, (p.qb + std::max<uint32_t>(bitlen(dmax), 1u) + 2u * p.vb + 7u) / 8u);
+    // call block: words, every region 64-word (256-byte) aligned
+    p.off_qs = sizeof(CallCtl) / 4;
+    p.off_sbits = round_up(p.off_qs + static_cast<size_t>(nq) * (sizeof(QueryState) / 4), 64);
+    p.off_rbits = round_up(p.off_sbits + sw, 64);
+    p.off_hists = round_up(p.off_rbits + rw, 64);
+    p.off_sort = round_up(p.off_hists + static_cast<size_t>(nkcp) * 2 * kDistBins, 64);
+    p.block_words = p.off_sort + sort_hist_words();
+    // the pass-0 histogram is written whole and the digit totals before use;
+    // the histograms later passes accumulate start at zero
+    p.zero_words = p.off_sort + static_cast<size_t>(p.max_passes + 1) * 256u * 256u;
+    p.off_ebase = round_up(static_cast<size_t>(nq) * sizeof(QueryDesc), 16);
+    p.off_rbase = round_up(p.off_ebase + static_cast<size_t>(nq + 1) * sizeof(unsigned long long), 16);
+    p.off_perm = round_up(p.off_rbase + static_cast<size_t>(nq + 1) * sizeof(uint32_t), 16);
+    p.desc_bytes = p.off_perm + static_cast<size_t>(nq) * sizeof(uint32_t);
+    return RN_OK;
+}
 
-extern "C" {
+rn_status ensure_gslots(rn_graph *g) {
+    if (g->d_gslots) return RN_OK;
+    // up to 64 concurrent global-tier searches, within 8 GiB
+    const size_t words = global_slot_words(g->Vmax);
+    size_t n = (size_t{8} << 30) / (4 * words);
+    n = std::max<size_t>(1, std::min<size_t>(n, 64));
+    RN_HIP(dev_alloc(&g->d_gslots, n * words), "allocating global search slots");
+    g->n_gslots = static_cast<uint32_t>(n);
+    const size_t V = static_cast<size_t>(g->Vmax);
+    for (size_t i = 0; i < n; ++i) {
+        RN_HIP(launch_fill_u32(g->d_gslots + i * words, V, kInf, nullptr), "clearing search slots");
+        RN_HIP(launch_fill_u32(g->d_gslots + i * words + V, (V + 31) / 32, 0u, nullptr), "clearing search slots");
+    }
+    RN_HIP(hipDeviceSynchronize(), "clearing search slots");
+    return RN_OK;
+}
 
-const char *rn_last_error(void) { return t_err.c_str(); }
+rn_status ensure_buffers(Workspace &ws, const Prepared &p) {
+    if (ws.block_words < p.block_words) {
+        dev_free(ws.d_block);
+        ws.block_words = 0;
+        const size_t words = p.block_words + p.block_words / 4;
+        RN_HIP(dev_alloc(&ws.d_block, words), "allocating call buffers");
+        ws.block_words = words;
+    }
+    if (ws.desc_bytes < p.desc_bytes) {
+        dev_free(ws.d_desc);
+        host_free(ws.h_desc);
+        ws.desc_bytes = 0;
+        const size_t bytes = std::max<size_t>(p.desc_bytes + p.desc_bytes / 4, 4096);
+        RN_HIP(dev_alloc(&ws.d_desc, bytes), "allocating query descriptors");
+        RN_HIP(hipHostMalloc(reinterpret_cast<void **>(&ws.h_desc), bytes, 0), "allocating query descriptors");
+        ws.desc_bytes = bytes;
+    }
+    const size_t state_bytes = sizeof(CallCtl) + static_cast<size_t>(p.nq) * sizeof(QueryState);
+    if (ws.h_state_bytes < state_bytes) {
+        host_free(ws.h_state);
+        ws.h_state_bytes = 0;
+        const size_t bytes = std::max<size_t>(state_bytes + state_bytes / 4, 4096);
+        RN_HIP(hipHostMalloc(reinterpret_cast<void **>(&ws.h_state), bytes, 0), "allocating the read-back buffer");
+        ws.h_state_bytes = bytes;
+    }
+    const size_t sw = stage_scratch_words(p.rbits_words);
+    if (ws.stage_words < sw) {
+        dev_free(ws.d_stage);
+        ws.stage_words = 0;
+        RN_HIP(dev_alloc(&ws.d_stage, sw + sw / 4), "allocating staging scratch");
+        ws.stage_words = sw + sw / 4;
+    }
+    if (ws.src_cap < p.total_R) {
+        dev_free(ws.d_src);
+        dev_free(ws.d_srcq);
+        for (int i = 0; i < kLists; ++i) {
+            dev_free(ws.d_list[i]);
+            dev_free(ws.d_listq[i]);
+        }
+        ws.src_cap = 0;
+        const size_t cap = std::max<size_t>(p.total_R + p.total_R / 4, 1024);
+        RN_HIP(dev_alloc(&ws.d_src, cap), "allocating the source list");
+        RN_HIP(dev_alloc(&ws.d_srcq, cap), "allocating the source list");
+        for (int i = 0; i < kLists; ++i) {
+            RN_HIP(dev_alloc(&ws.d_list[i], cap), "allocating the re-run lists");
+            RN_HIP(dev_alloc(&ws.d_listq[i], cap), "allocating the re-run lists");
+        }
+        ws.src_cap = cap;
+    }
+    if (ws.rec_cap == 0) {
+        const unsigned long long cap = 1ull << 20;
+        RN_HIP(dev_alloc(&ws.d_recs[0], cap), "allocating the record buffer");
+        RN_HIP(dev_alloc(&ws.d_recs[1], cap), "allocating the record buffer");
+        ws.rec_cap = cap;
+    }
+    if (!ws.fork) {
+        RN_HIP(hipEventCreateWithFlags(&ws.fork, hipEventDisableTiming), "creating events");
+        for (auto &e : ws.join) RN_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming), "creating events");
+        for (auto &e : ws.ev) RN_HIP(hipEventCreate(&e), "creating events");
+    }
+    return RN_OK;
+}
 
-const char *rn_version(void) { return "rn 0.1 (gfx950)"; }
+rn_status grow_recs(Workspace &ws, unsigned long long need) {
+    if (need >= kRecCapMax) return fail(RN_ERR_NOMEM, "a call may emit at most 2^31 - 1 records");
+    const unsigned long long cap = std::min(kRecCapMax - 1, std::max(need + need / 4, 2 * ws.rec_cap));
+    dev_free(ws.d_recs[0]);
+    dev_free(ws.d_recs[1]);
+    ws.rec_cap = 0;
+    RN_HIP(dev_alloc(&ws.d_recs[0], cap), "growing the record buffer");
+    RN_HIP(dev_alloc(&ws.d_recs[1], cap), "growing the record buffer");
+    ws.rec_cap = cap;
+    return RN_OK;
+}
 
-rn_status rn_graph_load(int32_t V, int64_t A, const int32_t *row_ptr, const int32_t *col,
-                        const uint32_t *w, rn_graph **out) {
-    if (!out) return fail(RN_ERR_ARG, "out is NULL");
-    *out = nullptr;
+void fill_host_desc(const Prepared &p, uint8_t *h) {
+    std::memcpy(h, p.qd.data(), static_cast<size_t>(p.nq) * sizeof(QueryDesc));
+    std::memcpy(h + p.off_ebase, p.ebase.data(), p.ebase.size() * sizeof(unsigned long long));
+    std::memcpy(h + p.off_rbase, p.rbase.data(), p.rbase.size() * sizeof(uint32_t));
+    std::memcpy(h + p.off_perm, p.perm.data(), p.perm.size() * sizeof(uint32_t));
+}
+
+CallBuffers call_buffers(const Workspace &ws, const Prepared &p) {
+    CallBuffers b;
+    b.nq = p.nq;
+    b.qd = reinterpret_cast<const QueryDesc *>(ws.d_desc);
+    b.ebase = reinterpret_cast<const unsigned long long *>(ws.d_desc + p.off_ebase);
+    b.rbase = reinterpret_cast<const uint32_t *>(ws.d_desc + p.off_rbase);
+    b.perm = reinterpret_cast<const uint32_t *>(ws.d_desc + p.off_perm);
+    b.ctl = reinterpret_cast<CallCtl *>(ws.d_block);
+    b.qs = reinterpret_cast<QueryState *>(ws.d_block + p.off_qs);
+    b.sbits = ws.d_block + p.off_sbits;
+    b.rbits = ws.d_block + p.off_rbits;
+    b.rwords = p.rbits_words;
+    b.hists = ws.d_block + p.off_hists;
+    b.sort_hist = ws.d_block + p.off_sort;
+    b.stage_scratch = ws.d_stage;
+    b.src = ws.d_src;
+    b.srcq = ws.d_srcq;
+    for (int i = 0; i < kLists; ++i) {
+        b.list[i] = ws.d_list[i];
+        b.listq[i] = ws.d_listq[i];
+    }
+    b.recs[0] = ws.d_recs[0];
+    b.recs[1] = ws.d_recs[1];
+    b.rec_cap = ws.rec_cap;
+    return b;
+}
+
+// ------------------------------------------------------------------ launch sequence
+void record(const rn_graph *g, Workspace &ws, bool timed, int which, hipStream_t s) {
+    if (timed && g->profiling) (void)hipEventRecord(ws.ev[which], s);
+}
+
+rn_status ensure_side_streams(Workspace &ws, size_t n) {
+    for (size_t i = 0; i < n && i < static_cast<size_t>(kSide); ++i)
+        if (!ws.side[i]) RN_HIP(hipStreamCreateWithFlags(&ws.side[i], hipStreamNonBlocking), "creating streams");
+    return RN_OK;
+}
+
+// Enqueue the whole call on s (descriptors already on the device).  timed:
+// record the profiling events (never during graph capture).
+rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *out, int64_t cap, hipStream_t s,
+                       bool timed) {
+    const CallBuffers b = call_buffers(ws, p);
+    record(g, ws, timed, EV_START, s);
+    RN_HIP(launch_fill_u32(ws.d_block, p.zero_words, 0u, s), "clearing call state");
+    RN_HIP(launch_stage(b, p.total_elems, g->d_rank, g->d_order, s), "staging the queries");
+    record(g, ws, timed, EV_STAGED, s);
+
+    JoinArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.row_ptr = g->d_row_ptr;
+    a.arcs = g->d_arcs;
+    a.qd = b.qd;
+    a.qs = b.qs;
+    a.sbits = b.sbits;
+    a.hists = b.hists;
+    a.ctl = b.ctl;
+    a.recs = b.recs[0];
+    a.rec_cap = b.rec_cap;
+    a.count_work = g->count_work ? 1 : 0;
+    if (p.any_kcp) {
+        JoinArgs k = a;
+        k.src = b.src;
+        k.srcq = b.srcq;
+        k.sbeg = nullptr;
+        k.send = &b.ctl->nsrc;
+        RN_HIP(launch_kcp_seed(k, b, static_cast<uint32_t>(p.total_R), s), "seeding the k-closest-pairs bounds");
+    }
+    // first tiers, one launch per table size; several run side by side
+    const size_t ng = p.groups.size();
+    if (ng > 1) {
+        RN_TRY(ensure_side_streams(ws, ng - 1));
+        RN_HIP(hipEventRecord(ws.fork, s), "forking streams");
+    }
+    for (size_t gi = 0; gi < ng; ++gi) {
+        const Group &gr = p.groups[gi];
+        hipStream_t st = gi == 0 ? s : ws.side[gi - 1];
+        if (gi > 0) RN_HIP(hipStreamWaitEvent(st, ws.fork, 0), "forking streams");
+        JoinArgs t = a;
+        t.src = b.src;
+        t.srcq = b.srcq;
+        t.sbeg = &b.qs[p.perm[gr.first]].src_start;
+        t.send = gr.end < p.nq ? &b.qs[p.perm[gr.end]].src_start : &b.ctl->nsrc;
+        const int li = retry_list_after(gr.hb);
+        t.ovf = b.list[li];
+        t.ovfq = b.listq[li];
+        t.novf = &b.ctl->nlist[li];
+        t.first_tier = 1;
+        RN_HIP(launch_join(t, gr.hb, static_cast<uint32_t>(gr.sources), st), "launching the relaxation");
+        if (gi > 0) RN_HIP(hipEventRecord(ws.join[gi - 1], st), "joining streams");
+    }
+    for (size_t gi = 1; gi < ng; ++gi) RN_HIP(hipStreamWaitEvent(s, ws.join[gi - 1], 0), "joining streams");
+    record(g, ws, timed, EV_TIER0, s);
+    // re-runs: 2^11-slot tables, 2^14-slot tables, then the global tier
+    const uint32_t maxs = static_cast<uint32_t>(p.total_R);
+    for (int li = 0; li < 2; ++li) {
+        if (li == 0 && !p.need_list0) continue;
+        if (li == 1 && !p.need_list1) continue;
+        JoinArgs t = a;
+        t.src = b.list[li];
+        t.srcq = b.listq[li];
+        t.sbeg = nullptr;
+        t.send = &b.ctl->nlist[li];
+        t.ovf = b.list[li + 1];
+        t.ovfq = b.listq[li + 1];
+        t.novf = &b.ctl->nlist[li + 1];
+        t.first_tier = 0;
+        RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, maxs, s), "launching the relaxation");
+    }
+    {
+        RN_TRY(ensure_gslots(g));
+        JoinArgs t = a;
+        t.src = b.list[2];
+        t.srcq = b.listq[2];
+        t.sbeg = nullptr;
+        t.send = &b.ctl->nlist[2];
+        RN_HIP(launch_join_global(t, g->d_gslots, g->n_gslots, g->Vmax, maxs, s), "launching the global relaxation");
+    }
+    record(g, ws, timed, EV_RELAXED, s);
+    if (p.any_kcp) RN_HIP(launch_select(b, s), "selecting candidates");
+    RN_HIP(launch_layout(b, p.any_kcp ? 1 : 0, p.qb, p.vb, s), "laying out the output");
+    record(g, ws, timed, EV_SELECTED, s);
+    RN_HIP(launch_sort_out(b, p.any_kcp ? 1 : 0, p.max_passes, p.vb, out, static_cast<unsigned long long>(cap), s),
+           "sorting pairs");
+    record(g, ws, timed, EV_DONE, s);
+    return RN_OK;
+}
+
+rn_status read_back(Workspace &ws, const Prepared &p, hipStream_t s) {
+    const size_t bytes = sizeof(CallCtl) + static_cast<size_t>(p.nq) * sizeof(QueryState);
+    RN_HIP(hipMemcpyAsync(ws.h_state, ws.d_block, bytes, hipMemcpyDeviceToHost, s), "reading the call status");
+    RN_HIP(hipStreamSynchronize(s), "waiting for the call");
+    return RN_OK;
+}
+
+float elapsed(const rn_graph *g, const Workspace &ws, int a, int b) {
+    float ms = 0.f;
+    if (!g->profiling) return 0.f;
+    if (hipEventElapsedTime(&ms, ws.ev[a], ws.ev[b]) != hipSuccess) return 0.f;
+    return ms;
+}
+
+// Turn the read-back state into offsets / status / the return code.
+// Returns RN_ERR_NOMEM + sets *regrow when the records outgrew the buffer.
+rn_status finish(rn_graph *g, Workspace &ws, const Prepared &p, int64_t cap, int64_t *offsets, int32_t *status,
+                 bool timed, bool *regrow) {
+    const CallCtl &c = *reinterpret_cast<const CallCtl *>(ws.h_state);
+    const QueryState *qs = reinterpret_cast<const QueryState *>(ws.h_state + sizeof(CallCtl));
+    *regrow = false;
+    if (c.npairs > ws.rec_cap) {
+        *regrow = true;
+        RN_TRY(grow_recs(ws, c.npairs));
+        return RN_OK;
+    }
+    if (timed) {
+        rn_stats &st = g->stats;
+        st = rn_stats{};
+        st.stage_ms = elapsed(g, ws, EV_START, EV_STAGED);
+        st.relax_ms = elapsed(g, ws, EV_STAGED, EV_TIER0);
+        st.retry_ms = elapsed(g, ws, EV_TIER0, EV_RELAXED);
+        st.select_ms = elapsed(g, ws, EV_RELAXED, EV_SELECTED);
+        st.sort_ms = elapsed(g, ws, EV_SELECTED, EV_DONE);
+        st.total_ms = elapsed(g, ws, EV_START, EV_DONE);
+        st.pairs = static_cast<int64_t>(c.npairs);
+        st.arcs = static_cast<int64_t>(c.arcs);
+        st.settled = static_cast<int64_t>(c.settled);
+        st.retried = static_cast<int32_t>(c.nretry);
+        st.global_searches = static_cast<int32_t>(c.nlist[2]);
+        st.relax_launches = static_cast<int32_t>(p.groups.size()) + (p.need_list0 ? 1 : 0) + (p.need_list1 ? 1 : 0) + 1;
+    }
+    int bad = -1;
+    for (int32_t i = 0; i < p.nq; ++i) {
+        if (offsets) offsets[i] = static_cast<int64_t>(qs[i].off);
+        if (status) status[i] = qs[i].err ? RN_ERR_ARG : RN_OK;
+        if (qs[i].err && bad < 0) bad = i;
+    }
+    if (offsets) offsets[p.nq] = static_cast<int64_t>(c.nout);
+    if (c.nout > static_cast<unsigned long long>(cap)) return fail(RN_ERR_CAPACITY, "output buffer too small");
+    if (bad >= 0)
+        return fail(RN_ERR_ARG, (p.nq > 1 ? "query " + std::to_string(bad) + ": " : std::string()) +
+                                    "invalid node sets:" + describe_err(qs[bad].err));
+    return RN_OK;
+}
+
+// One eager call on workspace ws (prepared p); retries when the record buffer
+// was too small.
+rn_status run_eager(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *out, int64_t cap, int64_t *offsets,
+                    int32_t *status, hipStream_t s, bool timed) {
+    RN_TRY(ensure_buffers(ws, p));
+    for (int attempt = 0; attempt < 3; ++attempt) {
+        fill_host_desc(p, ws.h_desc);
+        RN_HIP(hipMemcpyAsync(ws.d_desc, ws.h_desc, p.desc_bytes, hipMemcpyHostToDevice, s), "uploading queries");
+        RN_TRY(enqueue_call(g, ws, p, out, cap, s, timed));
+        RN_TRY(read_back(ws, p, s));
+        bool regrow = false;
+        const rn_status st = finish(g, ws, p, cap, offsets, status, timed, &regrow);
+        if (!regrow) return st;
+    }
+    return fail(RN_ERR_NOMEM, "record buffer did not settle");
+}
+
+rn_status run_batch(rn_graph *g, const rn_query *q, int32_t nq, rn_pair *out, int64_t cap, int64_t *offsets,
+                    int32_t *status, hipStream_t s) {
+    if (cap < 0 || (cap > 0 && !out)) return fail(RN_ERR_ARG, "bad output buffer");
+    RN_TRY(check_queries(g, q, nq, status));
+    RN_HIP(hipSetDevice(g->device), "selecting the device");
+    Prepared p;
+    RN_TRY(prepare(g, q, nq, p));
+    return run_eager(g, g->ws, p, out, cap, offsets, status, s, true);
+}
+
+rn_status run_single(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS, uint32_t theta,
+                     int32_t k, rn_pair *out, int64_t cap, int64_t *n_out, void *stream) {
+    if (!n_out) return fail(RN_ERR_ARG, "n_out is NULL");
+    *n_out = 0;
+    if (!g) return fail(RN_ERR_ARG, "graph handle is NULL");
+    rn_query q;
+    std::memset(&q, 0, sizeof(q));
+    q.R = R;
+    q.S = S;
+    q.nR = nR;
+    q.nS = nS;
+    q.graph = 0;
+    q.k = k;
+    q.theta = theta;
+    q.delta = RN_DELTA_DEFAULT;
+    q.hash_log2 = 0;
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(RN_ERR_BUSY, "handle in use by another call");
+    int64_t off[2] = {0, 0};
+    const rn_status st = run_batch(g, &q, 1, out, cap, off, nullptr, reinterpret_cast<hipStream_t>(stream));
+    if (st == RN_OK || st == RN_ERR_CAPACITY) *n_out = off[1];
+    return st;
+}
+
+rn_status validate_csr(int32_t V, int64_t A, const int32_t *row_ptr, const int32_t *col, const uint32_t *w) {
     if (V < 1 || V >= 0x7FFFFFFF) return fail(RN_ERR_ARG, "V must be in [1, 2^31 - 2]");
     if (A < 0 || A >= 0x7FFFFFFFLL) return fail(RN_ERR_ARG, "A must be in [0, 2^31 - 1]");
     if (!row_ptr || (A > 0 && (!col || !w))) return fail(RN_ERR_ARG, "CSR array is NULL");
@@ -252,6 +679,31 @@ rn_status rn_graph_load(int32_t V, int64_t A, const int32_t *row_ptr, const int3
         if (row_ptr[x + 1] < row_ptr[x]) return fail(RN_ERR_ARG, "row_ptr must be non-decreasing");
     for (int64_t a = 0; a < A; ++a)
         if (col[a] < 0 || col[a] >= V) return fail(RN_ERR_ARG, "col entry outside [0, V)");
+    return RN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *rn_last_error(void) { return t_err.c_str(); }
+
+const char *rn_version(void) { return "rn 0.2 (gfx950)"; }
+
+rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, const int32_t *const *row_ptr,
+                             const int32_t *const *col, const uint32_t *const *w, rn_graph **out) {
+    if (!out) return fail(RN_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (n < 1 || !V || !A || !row_ptr || !col || !w) return fail(RN_ERR_ARG, "need n >= 1 graphs and their arrays");
+    int64_t totV = 0, totA = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const rn_status st = validate_csr(V[i], A[i], row_ptr[i], col[i], w[i]);
+        if (st != RN_OK) return fail(st, "graph " + std::to_string(i) + ": " + t_err);
+        totV += V[i];
+        totA += A[i];
+    }
+    if (totV >= 0x7FFFFFFF) return fail(RN_ERR_ARG, "the graphs together exceed 2^31 - 2 vertices");
+    if (totA >= 0x7FFFFFFFLL) return fail(RN_ERR_ARG, "the graphs together exceed 2^31 - 1 arcs");
 
     rn_graph *g = new (std::nothrow) rn_graph();
     if (!g) return fail(RN_ERR_NOMEM, "allocating the handle");
@@ -260,36 +712,51 @@ rn_status rn_graph_load(int32_t V, int64_t A, const int32_t *row_ptr, const int3
         delete g;
         return hip_fail(e, "no HIP device");
     }
-    g->V = V;
-    g->A = A;
+    g->ngraphs = n;
+    g->V = static_cast<int32_t>(totV);
+    g->A = totA;
+    std::vector<ArcRec> arcs;
     try {
-        g->row_ptr.assign(row_ptr, row_ptr + V + 1);
-        g->col.assign(col, col + A);
-        g->w.assign(w, w + A);
+        g->voff.assign(n + 1, 0);
+        g->aoff.assign(n + 1, 0);
+        g->w_min.assign(n, 0);
+        g->row_ptr.resize(static_cast<size_t>(totV) + 1);
+        g->col.resize(static_cast<size_t>(totA));
+        g->w.resize(static_cast<size_t>(totA));
+        arcs.resize(static_cast<size_t>(totA));
     } catch (...) {
         delete g;
         return fail(RN_ERR_NOMEM, "copying the CSR");
     }
-    g->w_min = A ? *std::min_element(g->w.begin(), g->w.end()) : 0;
-    g->w_max = A ? *std::max_element(g->w.begin(), g->w.end()) : 0;
-
-    std::vector<ArcRec> arcs(static_cast<size_t>(A));
-    for (int64_t a = 0; a < A; ++a) {
-        const int32_t y = col[a];
-        arcs[a] = ArcRec{y, w[a], row_ptr[y], row_ptr[y + 1]};
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t vo = g->voff[i];
+        const int64_t ao = g->aoff[i];
+        g->voff[i + 1] = vo + V[i];
+        g->aoff[i + 1] = ao + A[i];
+        g->Vmax = std::max(g->Vmax, V[i]);
+        for (int32_t x = 0; x < V[i]; ++x) g->row_ptr[vo + x] = static_cast<int32_t>(ao + row_ptr[i][x]);
+        uint32_t wm = A[i] ? 0xFFFFFFFFu : 0u;
+        for (int64_t a = 0; a < A[i]; ++a) {
+            g->col[ao + a] = vo + col[i][a];
+            g->w[ao + a] = w[i][a];
+            wm = std::min(wm, w[i][a]);
+        }
+        g->w_min[i] = wm;
+    }
+    g->row_ptr[totV] = static_cast<int32_t>(totA);
+    for (int64_t a = 0; a < totA; ++a) {
+        const int32_t y = g->col[a];
+        arcs[a] = ArcRec{y, g->w[a], g->row_ptr[y], g->row_ptr[y + 1]};
     }
     rn_status st = RN_OK;
-    if ((e = dev_alloc(&g->d_row_ptr, static_cast<size_t>(V) + 1)) != hipSuccess ||
-        (e = dev_alloc(&g->d_arcs, static_cast<size_t>(A))) != hipSuccess ||
-        (e = hipMemcpy(g->d_row_ptr, row_ptr, (static_cast<size_t>(V) + 1) * sizeof(int32_t),
+    if ((e = dev_alloc(&g->d_row_ptr, static_cast<size_t>(totV) + 1)) != hipSuccess ||
+        (e = dev_alloc(&g->d_arcs, static_cast<size_t>(totA))) != hipSuccess ||
+        (e = hipMemcpy(g->d_row_ptr, g->row_ptr.data(), (static_cast<size_t>(totV) + 1) * sizeof(int32_t),
                        hipMemcpyHostToDevice)) != hipSuccess ||
-        (A > 0 && (e = hipMemcpy(g->d_arcs, arcs.data(), static_cast<size_t>(A) * sizeof(ArcRec),
-                                 hipMemcpyHostToDevice)) != hipSuccess) ||
-        (e = hipHostMalloc(reinterpret_cast<void **>(&g->h_ctl), sizeof(QueryCtl), 0)) != hipSuccess) {
+        (totA > 0 && (e = hipMemcpy(g->d_arcs, arcs.data(), static_cast<size_t>(totA) * sizeof(ArcRec),
+                                    hipMemcpyHostToDevice)) != hipSuccess)) {
         st = hip_fail(e, "uploading the graph");
     }
-    for (int i = 0; st == RN_OK && i < EV_COUNT; ++i)
-        if ((e = hipEventCreate(&g->ev[i])) != hipSuccess) st = hip_fail(e, "creating events");
     if (st != RN_OK) {
         rn_graph_free(g);
         return st;
@@ -300,40 +767,44 @@ rn_status rn_graph_load(int32_t V, int64_t A, const int32_t *row_ptr, const int3
     return RN_OK;
 }
 
+rn_status rn_graph_load(int32_t V, int64_t A, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+                        rn_graph **out) {
+    return rn_graph_load_many(1, &V, &A, &row_ptr, &col, &w, out);
+}
+
 void rn_graph_free(rn_graph *g) {
     if (!g) return;
     (void)hipSetDevice(g->device);
-    release_buffers(g);
+    (void)hipDeviceSynchronize();
+    g->ws.release();
+    dev_free(g->d_gslots);
     dev_free(g->d_row_ptr);
     dev_free(g->d_arcs);
     dev_free(g->d_rank);
     dev_free(g->d_order);
-    if (g->h_ctl) (void)hipHostFree(g->h_ctl);
-    for (auto &ev : g->ev)
-        if (ev) (void)hipEventDestroy(ev);
     delete g;
 }
 
 int32_t rn_graph_num_vertices(const rn_graph *g) { return g ? g->V : 0; }
 int64_t rn_graph_num_arcs(const rn_graph *g) { return g ? g->A : 0; }
+int32_t rn_graph_count(const rn_graph *g) { return g ? g->ngraphs : 0; }
 
-rn_status rn_partition_host(int32_t V, int64_t A, const int32_t *row_ptr, const int32_t *col,
-                            const uint32_t *w, float alpha, int32_t max_leaf, int32_t *part_out,
-                            int32_t *order_out) {
-    if (V < 1 || A < 0 || !row_ptr || (A > 0 && (!col || !w)))
-        return fail(RN_ERR_ARG, "malformed CSR");
-    if (row_ptr[0] != 0 || static_cast<int64_t>(row_ptr[V]) != A)
-        return fail(RN_ERR_ARG, "row_ptr must start at 0 and end at A");
-    for (int32_t x = 0; x < V; ++x)
-        if (row_ptr[x + 1] < row_ptr[x]) return fail(RN_ERR_ARG, "row_ptr must be non-decreasing");
-    for (int64_t a = 0; a < A; ++a)
-        if (col[a] < 0 || col[a] >= V) return fail(RN_ERR_ARG, "col entry outside [0, V)");
+rn_status rn_graph_size(const rn_graph *g, int32_t i, int32_t *V, int64_t *A) {
+    if (!g) return fail(RN_ERR_ARG, "graph handle is NULL");
+    if (i < 0 || i >= g->ngraphs) return fail(RN_ERR_ARG, "graph index out of range");
+    if (V) *V = g->voff[i + 1] - g->voff[i];
+    if (A) *A = g->aoff[i + 1] - g->aoff[i];
+    return RN_OK;
+}
+
+rn_status rn_partition_host(int32_t V, int64_t A, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+                            float alpha, int32_t max_leaf, int32_t *part_out, int32_t *order_out) {
+    RN_TRY(validate_csr(V, A, row_ptr, col, w));
     if (!(alpha >= 0.f && alpha <= 1.f)) return fail(RN_ERR_ARG, "alpha must be in [0, 1]");
     if (max_leaf < 1) return fail(RN_ERR_ARG, "max_leaf must be >= 1");
     std::vector<int32_t> part, order;
     std::string msg;
-    if (!partition_graph(V, row_ptr, col, w, alpha, max_leaf, part, order, msg))
-        return fail(RN_ERR_NOMEM, msg);
+    if (!partition_graph(V, row_ptr, col, w, alpha, max_leaf, part, order, msg)) return fail(RN_ERR_NOMEM, msg);
     if (part_out) std::memcpy(part_out, part.data(), static_cast<size_t>(V) * sizeof(int32_t));
     if (order_out) std::memcpy(order_out, order.data(), static_cast<size_t>(V) * sizeof(int32_t));
     return RN_OK;
@@ -341,19 +812,57 @@ rn_status rn_partition_host(int32_t V, int64_t A, const int32_t *row_ptr, const 
 
 rn_status rn_partition(rn_graph *g, float alpha, int32_t max_leaf, int32_t *part_out) {
     if (!g) return fail(RN_ERR_ARG, "graph handle is NULL");
+    if (!(alpha >= 0.f && alpha <= 1.f)) return fail(RN_ERR_ARG, "alpha must be in [0, 1]");
+    if (max_leaf < 1) return fail(RN_ERR_ARG, "max_leaf must be >= 1");
     BusyGuard guard(g);
     if (!guard.ok) return fail(RN_ERR_BUSY, "handle in use by another call");
-    std::vector<int32_t> order(static_cast<size_t>(g->V));
-    rn_status st = rn_partition_host(g->V, g->A, g->row_ptr.data(), g->col.data(), g->w.data(), alpha,
-                                     max_leaf, part_out, order.data());
-    if (st != RN_OK) return st;
-    std::vector<int32_t> rank(static_cast<size_t>(g->V));
-    for (int32_t r = 0; r < g->V; ++r) rank[order[r]] = r;
+    const int32_t n = g->ngraphs;
+    std::vector<std::vector<int32_t>> parts(n), orders(n);
+    std::vector<std::string> msgs(n);
+    std::vector<char> ok(n, 0);
+    // graphs are independent: partition them on several host threads
+    std::atomic<int32_t> next{0};
+    auto work = [&]() {
+        for (int32_t i = next++; i < n; i = next++) {
+            const int32_t vo = g->voff[i], V = g->voff[i + 1] - vo;
+            const int64_t ao = g->aoff[i], A = g->aoff[i + 1] - ao;
+            std::vector<int32_t> rp(static_cast<size_t>(V) + 1), cl(static_cast<size_t>(A));
+            for (int32_t x = 0; x <= V; ++x) rp[x] = static_cast<int32_t>(g->row_ptr[vo + x] - ao);
+            for (int64_t a = 0; a < A; ++a) cl[a] = g->col[ao + a] - vo;
+            ok[i] = partition_graph(V, rp.data(), cl.data(), g->w.data() + ao, alpha, max_leaf, parts[i], orders[i],
+                                    msgs[i]) ? 1 : 0;
+        }
+    };
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const unsigned nt = std::min<unsigned>(hw, static_cast<unsigned>(n));
+    std::vector<std::thread> pool;
+    try {
+        for (unsigned t = 1; t < nt; ++t) pool.emplace_back(work);
+    } catch (...) {
+    }
+    work();
+    for (auto &t : pool) t.join();
+    for (int32_t i = 0; i < n; ++i)
+        if (!ok[i]) return fail(RN_ERR_NOMEM, msgs[i]);
+    std::vector<int32_t> rank(static_cast<size_t>(g->V)), order(static_cast<size_t>(g->V));
+    int32_t leaf0 = 0;
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t vo = g->voff[i], V = g->voff[i + 1] - vo;
+        int32_t nleaf = 0;
+        for (int32_t r = 0; r < V; ++r) {
+            order[vo + r] = orders[i][r];
+            rank[vo + orders[i][r]] = r;
+        }
+        for (int32_t x = 0; x < V; ++x) {
+            nleaf = std::max(nleaf, parts[i][x] + 1);
+            if (part_out) part_out[vo + x] = leaf0 + parts[i][x];
+        }
+        leaf0 += nleaf;
+    }
     RN_HIP(hipSetDevice(g->device), "selecting the device");
     if (!g->d_rank) RN_HIP(dev_alloc(&g->d_rank, static_cast<size_t>(g->V)), "allocating ranks");
     if (!g->d_order) RN_HIP(dev_alloc(&g->d_order, static_cast<size_t>(g->V)), "allocating ranks");
-    RN_HIP(hipMemcpy(g->d_rank, rank.data(), rank.size() * sizeof(int32_t), hipMemcpyHostToDevice),
-           "uploading ranks");
+    RN_HIP(hipMemcpy(g->d_rank, rank.data(), rank.size() * sizeof(int32_t), hipMemcpyHostToDevice), "uploading ranks");
     RN_HIP(hipMemcpy(g->d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice),
            "uploading ranks");
     return RN_OK;
@@ -362,8 +871,7 @@ rn_status rn_partition(rn_graph *g, float alpha, int32_t max_leaf, int32_t *part
 rn_status rn_set_tuning(rn_graph *g, int64_t delta, int32_t hash_log2) {
     if (!g) return fail(RN_ERR_ARG, "graph handle is NULL");
     if (delta > static_cast<int64_t>(kMaxDist)) return fail(RN_ERR_ARG, "delta out of range");
-    if (hash_log2 >= 0 && !join_tier_supported(hash_log2))
-        return fail(RN_ERR_ARG, "hash_log2 must be in [8, 14]");
+    if (hash_log2 >= 0 && !join_tier_supported(hash_log2)) return fail(RN_ERR_ARG, "hash_log2 must be in [8, 14]");
     if (delta >= 0) g->delta = static_cast<uint32_t>(delta);
     if (hash_log2 >= 0) g->hash_log2 = hash_log2;
     return RN_OK;
@@ -389,141 +897,180 @@ rn_status rn_last_stats(const rn_graph *g, rn_stats *out) {
     return RN_OK;
 }
 
-rn_status rn_dist_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS,
-                       uint32_t theta, rn_pair *out, int64_t cap, int64_t *n_out, void *stream) {
-    rn_status st = check_sets(g, R, nR, S, nS, n_out);
-    if (st != RN_OK) return st;
-    if (theta > kMaxDist) return fail(RN_ERR_ARG, "theta must be <= 2^32 - 2");
-    if (cap < 0 || (cap > 0 && !out)) return fail(RN_ERR_ARG, "bad output buffer");
-    BusyGuard guard(g);
-    if (!guard.ok) return fail(RN_ERR_BUSY, "handle in use by another call");
-    return run_join(g, R, nR, S, nS, theta, false, 0, out, cap, n_out,
-                    reinterpret_cast<hipStream_t>(stream));
+rn_status rn_dist_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS, uint32_t theta,
+                       rn_pair *out, int64_t cap, int64_t *n_out, void *stream) {
+    return run_single(g, R, nR, S, nS, theta, 0, out, cap, n_out, stream);
 }
 
-rn_status rn_kcp_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS,
-                      int32_t k, rn_pair *out, int64_t cap, int64_t *n_out, void *stream) {
-    rn_status st = check_sets(g, R, nR, S, nS, n_out);
-    if (st != RN_OK) return st;
+rn_status rn_kcp_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS, int32_t k,
+                      rn_pair *out, int64_t cap, int64_t *n_out, void *stream) {
+    if (n_out) *n_out = 0;
     if (k < 1 || k > (1 << 24)) return fail(RN_ERR_ARG, "k must be in [1, 2^24]");
-    if (cap < 0 || (cap > 0 && !out)) return fail(RN_ERR_ARG, "bad output buffer");
+    return run_single(g, R, nR, S, nS, kMaxDist, k, out, cap, n_out, stream);
+}
+
+rn_status rn_join_batch(rn_graph *g, const rn_query *q, int32_t nq, rn_pair *out, int64_t cap, int64_t *offsets,
+                        int32_t *status, void *stream) {
+    if (!g) return fail(RN_ERR_ARG, "graph handle is NULL");
+    if (!offsets) return fail(RN_ERR_ARG, "offsets is NULL");
+    if (nq >= 1 && nq <= kMaxQueries) std::fill(offsets, offsets + nq + 1, 0);
     BusyGuard guard(g);
     if (!guard.ok) return fail(RN_ERR_BUSY, "handle in use by another call");
-    return run_join(g, R, nR, S, nS, kMaxDist, true, k, out, cap, n_out,
-                    reinterpret_cast<hipStream_t>(stream));
+    return run_batch(g, q, nq, out, cap, offsets, status, reinterpret_cast<hipStream_t>(stream));
+}
+
+rn_status rn_autotune(rn_graph *g, rn_query *q, int32_t nq, int32_t sample, void *stream) {
+    if (sample < 1) return fail(RN_ERR_ARG, "sample must be >= 1");
+    RN_TRY(check_queries(g, q, nq, nullptr));
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(RN_ERR_BUSY, "handle in use by another call");
+    RN_HIP(hipSetDevice(g->device), "selecting the device");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const bool prof = g->profiling, work = g->count_work;
+    g->profiling = true;
+    g->count_work = false;
+    rn_status result = RN_OK;
+    for (int32_t i = 0; i < nq && result == RN_OK; ++i) {
+        rn_query t = q[i];
+        t.nR = std::min(t.nR, sample);
+        const uint32_t wm = std::max(1u, g->w_min[t.graph]);
+        const uint32_t deltas[3] = {0u, wm, 4u * wm};
+        const int hbs_join[4] = {9, 10, 11, 12};
+        const int hbs_kcp[3] = {8, 9, 10};
+        const int *hbs = t.k ? hbs_kcp : hbs_join;
+        const int nh = t.k ? 3 : 4;
+        float best = 3.4e38f;
+        uint32_t best_delta = g->delta;
+        int best_hb = t.k ? kMinHB : g->hash_log2;
+        for (int di = 0; di < 3 && result == RN_OK; ++di) {
+            for (int hi = 0; hi < nh && result == RN_OK; ++hi) {
+                t.delta = deltas[di];
+                t.hash_log2 = hbs[hi];
+                Prepared p;
+                result = prepare(g, &t, 1, p);
+                if (result != RN_OK) break;
+                float ms = 3.4e38f;
+                for (int rep = 0; rep < 3 && result == RN_OK; ++rep) {
+                    result = run_eager(g, g->ws, p, nullptr, 0, nullptr, nullptr, s, true);
+                    if (result == RN_ERR_CAPACITY) result = RN_OK;   // counts only: no output wanted
+                    if (result == RN_ERR_ARG) {
+                        result = RN_OK;   // invalid node sets: keep the defaults for this query
+                        break;
+                    }
+                    if (rep > 0) ms = std::min(ms, g->stats.relax_ms + g->stats.retry_ms);
+                }
+                if (ms < best) {
+                    best = ms;
+                    best_delta = t.delta;
+                    best_hb = t.hash_log2;
+                }
+            }
+        }
+        q[i].delta = best_delta;
+        q[i].hash_log2 = best_hb;
+    }
+    g->profiling = prof;
+    g->count_work = work;
+    return result;
+}
+
+void rn_plan_free(rn_plan *p) {
+    if (!p) return;
+    if (p->g) (void)hipSetDevice(p->g->device);
+    (void)hipDeviceSynchronize();
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    p->ws.release();
+    delete p;
 }
 
 }  // extern "C"
 
 namespace {
 
-rn_status run_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS,
-                   uint32_t bound, bool kcp, int32_t k, rn_pair *out, int64_t cap, int64_t *n_out,
-                   hipStream_t stream) {
-    RN_HIP(hipSetDevice(g->device), "selecting the device");
-    rn_status st = ensure_query_buffers(g, nR);
-    if (st != RN_OK) return st;
-    int hb[kLdsTiers];
-    const int nlds = tier_list(g, kcp, hb);
-    const int ntiers = nlds + 1;
-    QueryCtl *ctl = g->d_ctl();
-    g->stats = rn_stats{};
-
-    for (int attempt = 0; attempt < 3; ++attempt) {
-        record(g, EV_START, stream);
-        RN_HIP(launch_fill_u32(g->d_qblock, g->qblock_words, 0u, stream), "clearing query state");
-        RN_HIP(launch_stage(R, nR, S, nS, g->V, g->d_rank, g->d_order, g->d_rbits(), g->d_sbits(),
-                            g->d_src, ctl, g->d_stage, stream),
-               "staging the query");
-        record(g, EV_STAGED, stream);
-        if (kcp)
-            RN_HIP(launch_kcp_seed(g->d_src, &ctl->nsrc, static_cast<uint32_t>(nR), g->d_row_ptr, g->d_arcs,
-                                   g->d_sbits(), g->d_seed_hist(), static_cast<uint32_t>(k), ctl, stream),
-                   "seeding the k-closest-pairs bound");
-        for (int t = 0; t < ntiers; ++t) {
-            JoinArgs a;
-            a.row_ptr = g->d_row_ptr;
-            a.arcs = g->d_arcs;
-            a.sbits = g->d_sbits();
-            a.src = t == 0 ? g->d_src : reinterpret_cast<const int32_t *>(g->d_ovf[t - 1]);
-            a.nsrc = t == 0 ? &ctl->nsrc : &ctl->novf[t - 1];
-            a.ctl = ctl;
-            a.pairs = g->d_pairs[0];
-            a.pair_cap = g->pair_cap;
-            a.ovf = g->d_ovf[t];
-            a.novf = &ctl->novf[t];
-            a.theta = bound;
-            a.delta = g->delta;
-            a.kcp = kcp ? 1 : 0;
-            a.count_work = g->count_work ? 1 : 0;
-            a.k = static_cast<uint32_t>(k);
-            a.cand_hist = g->d_cand_hist();
-            if (t < nlds)
-                RN_HIP(launch_join(a, hb[t], static_cast<uint32_t>(nR), stream), "launching the relaxation");
-            else
-                RN_HIP(launch_join_global(a, g->d_gslots, g->n_gslots, g->V, static_cast<uint32_t>(nR),
-                                          stream),
-                       "launching the global relaxation");
-            if (t == 0) record(g, EV_TIER0, stream);
-        }
-        record(g, EV_RELAXED, stream);
-        if (!kcp) {
-            record(g, EV_SELECTED, stream);
-            RN_HIP(launch_sort_to_out(g->d_pairs[0], g->d_pairs[1], &ctl->npairs, g->pair_cap, bound, g->V,
-                                      g->d_hist(), out, static_cast<unsigned long long>(cap), ~0ull, ctl,
-                                      ntiers - 1, stream),
-                   "sorting pairs");
-        } else {
-            // the final bound fixes the sort key width: read it back first
-            RN_HIP(hipMemcpyAsync(g->h_ctl, ctl, sizeof(QueryCtl), hipMemcpyDeviceToHost, stream),
-                   "reading the query status");
-            RN_HIP(hipStreamSynchronize(stream), "waiting for the searches");
-            const QueryCtl c = *g->h_ctl;
-            if (c.err) return fail(RN_ERR_ARG, describe_err(c.err));
-            if (c.npairs > g->pair_cap) {
-                st = grow_pairs(g, c.npairs);
-                if (st != RN_OK) return st;
-                continue;
-            }
-            RN_HIP(launch_kcp_filter(g->d_pairs[0], g->pair_cap, g->d_pairs[1], ctl, stream),
-                   "filtering candidates");
-            record(g, EV_SELECTED, stream);
-            RN_HIP(launch_sort_to_out(g->d_pairs[1], g->d_pairs[0], &ctl->nsel, g->pair_cap, c.theta, g->V,
-                                      g->d_hist(), out, static_cast<unsigned long long>(cap),
-                                      static_cast<unsigned long long>(k), ctl, ntiers - 1, stream),
-                   "sorting pairs");
-        }
-        record(g, EV_DONE, stream);
-        RN_HIP(hipMemcpyAsync(g->h_ctl, ctl, sizeof(QueryCtl), hipMemcpyDeviceToHost, stream),
-               "reading the query status");
-        RN_HIP(hipStreamSynchronize(stream), "waiting for the query");
-        const QueryCtl c = *g->h_ctl;
-        if (c.err) return fail(RN_ERR_ARG, describe_err(c.err));
-        if (c.novf[ntiers - 1]) return fail(RN_ERR_DEVICE, "global search tier overflowed");
-        if (c.npairs > g->pair_cap) {
-            st = grow_pairs(g, c.npairs);
-            if (st != RN_OK) return st;
-            continue;
-        }
-        g->stats.stage_ms = elapsed(g, EV_START, EV_STAGED);
-        g->stats.relax_ms = elapsed(g, EV_STAGED, EV_TIER0);
-        g->stats.retry_ms = elapsed(g, EV_TIER0, EV_RELAXED);
-        g->stats.select_ms = elapsed(g, EV_RELAXED, EV_SELECTED);
-        g->stats.sort_ms = elapsed(g, EV_SELECTED, EV_DONE);
-        g->stats.total_ms = elapsed(g, EV_START, EV_DONE);
-        g->stats.pairs = static_cast<int64_t>(c.npairs);
-        g->stats.arcs = static_cast<int64_t>(c.arcs);
-        g->stats.settled = static_cast<int64_t>(c.settled);
-        g->stats.retried = static_cast<int32_t>(c.novf[0]);
-        g->stats.global_searches = static_cast<int32_t>(c.novf[nlds - 1]);
-        g->stats.relax_launches = ntiers;
-        const unsigned long long n =
-            kcp ? std::min<unsigned long long>(c.nsel, static_cast<unsigned long long>(k)) : c.npairs;
-        *n_out = static_cast<int64_t>(n);
-        if (n > static_cast<unsigned long long>(cap)) return fail(RN_ERR_CAPACITY, "output buffer too small");
-        return RN_OK;
+// Capture the plan's call into a graph (descriptors already uploaded).
+rn_status capture_plan(rn_plan *pl, const Prepared &p) {
+    rn_graph *g = pl->g;
+    if (pl->exec) (void)hipGraphExecDestroy(pl->exec), pl->exec = nullptr;
+    if (pl->graph) (void)hipGraphDestroy(pl->graph), pl->graph = nullptr;
+    RN_TRY(ensure_gslots(g));
+    RN_TRY(ensure_side_streams(pl->ws, p.groups.size()));
+    RN_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal), "starting the capture");
+    const rn_status st = enqueue_call(g, pl->ws, p, pl->out, pl->cap, pl->cap_stream, false);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(pl->cap_stream, &graph);
+    if (st != RN_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
     }
-    return fail(RN_ERR_NOMEM, "pair buffer did not settle");
+    if (e != hipSuccess) return hip_fail(e, "ending the capture");
+    pl->graph = graph;
+    RN_HIP(hipGraphInstantiate(&pl->exec, graph, nullptr, nullptr, 0), "instantiating the graph");
+    return RN_OK;
+}
+
+// Eager run to size the buffers, then capture.
+rn_status plan_build(rn_plan *pl, const Prepared &p, hipStream_t s, int64_t *offsets, int32_t *status) {
+    const rn_status st = run_eager(pl->g, pl->ws, p, pl->out, pl->cap, offsets, status, s, false);
+    if (st != RN_OK && st != RN_ERR_CAPACITY && st != RN_ERR_ARG) return st;
+    RN_TRY(capture_plan(pl, p));
+    return st;
 }
 
 }  // namespace
+
+extern "C" {
+
+rn_status rn_plan_create(rn_graph *g, const rn_query *q, int32_t nq, rn_pair *out, int64_t cap, void *stream,
+                         rn_plan **plan) {
+    if (!plan) return fail(RN_ERR_ARG, "plan is NULL");
+    *plan = nullptr;
+    if (cap < 0 || (cap > 0 && !out)) return fail(RN_ERR_ARG, "bad output buffer");
+    RN_TRY(check_queries(g, q, nq, nullptr));
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(RN_ERR_BUSY, "handle in use by another call");
+    RN_HIP(hipSetDevice(g->device), "selecting the device");
+    rn_plan *pl = new (std::nothrow) rn_plan();
+    if (!pl) return fail(RN_ERR_NOMEM, "allocating the plan");
+    pl->g = g;
+    pl->out = out;
+    pl->cap = cap;
+    pl->q.assign(q, q + nq);
+    Prepared &p = pl->prep;
+    rn_status st = prepare(g, q, nq, p);
+    hipError_t e = hipSuccess;
+    if (st == RN_OK && (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        st = hip_fail(e, "creating the capture stream");
+    if (st == RN_OK) {
+        st = plan_build(pl, p, reinterpret_cast<hipStream_t>(stream), nullptr, nullptr);
+        if (st == RN_ERR_CAPACITY || st == RN_ERR_ARG) st = RN_OK;   // reported again by every run
+    }
+    if (st != RN_OK) {
+        const std::string msg = t_err;
+        rn_plan_free(pl);
+        return fail(st, msg);
+    }
+    *plan = pl;
+    return RN_OK;
+}
+
+rn_status rn_plan_run(rn_plan *pl, int64_t *offsets, int32_t *status, void *stream) {
+    if (!pl || !pl->exec) return fail(RN_ERR_ARG, "plan is NULL");
+    if (!offsets) return fail(RN_ERR_ARG, "offsets is NULL");
+    rn_graph *g = pl->g;
+    BusyGuard guard(g);
+    if (!guard.ok) return fail(RN_ERR_BUSY, "handle in use by another call");
+    RN_HIP(hipSetDevice(g->device), "selecting the device");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    const Prepared &p = pl->prep;
+    RN_HIP(hipGraphLaunch(pl->exec, s), "launching the graph");
+    RN_TRY(read_back(pl->ws, p, s));
+    bool regrow = false;
+    const rn_status st = finish(g, pl->ws, p, pl->cap, offsets, status, false, &regrow);
+    if (!regrow) return st;
+    // the records outgrew the buffer (grown by finish): run eagerly, re-capture
+    return plan_build(pl, p, s, offsets, status);
+}
+
+}  // extern "C"

@@ -11,7 +11,7 @@ namespace rn {
 constexpr uint32_t kInf = 0xFFFFFFFFu;     // unreachable / empty distance
 constexpr uint32_t kMaxDist = 0xFFFFFFFEu; // largest representable distance
 
-// Argument errors found on the device while staging a query (QueryCtl::err bits).
+// Argument errors found on the device while staging a query (QueryState::err bits).
 enum : uint32_t {
     kErrRange = 1u,    // an id outside [0, V)
     kErrDupR = 2u,     // a duplicate in R
@@ -19,32 +19,83 @@ enum : uint32_t {
     kErrOverlap = 8u,  // a vertex in both R and S
 };
 
-// Search tiers: up to three on-chip table sizes, then the global-memory tier
-// that takes any search (novf[t] counts the sources re-run after tier t).
-constexpr int kLdsTiers = 3;
-constexpr int kTiers = kLdsTiers + 1;
-
-// Device-resident control block of one query.  Zeroed before every query.
-struct QueryCtl {
-    uint32_t err;                   // kErr* bits
-    uint32_t nsrc;                  // sources staged
-    unsigned long long npairs;      // pairs emitted (may exceed the pair buffer)
-    uint32_t novf[kTiers];          // sources that outgrew tier t (re-run at tier t+1)
-    uint32_t theta;                 // k-closest pairs: current distance bound
-    uint32_t ncand;                 // k-closest pairs: bound-seeding candidate count
-    unsigned long long arcs;        // work count: out-arcs of every settled (source, vertex)
-    unsigned long long settled;     // work count: settled (source, vertex) pairs
-    unsigned long long nsel;        // k-closest pairs: candidates kept by the final bound
-};
+// On-chip table sizes (log2 of the slot count) a search may start with, and
+// the two fixed re-run sizes: a search that outgrows its first table is re-run
+// with a 2^11-slot table when it started below that, else with 2^14 slots; one
+// that outgrows 2^14 slots moves to the global-memory tier, which takes any
+// search.  Re-run lists: 0 -> 2^11, 1 -> 2^14, 2 -> global.
+constexpr int kMinHB = 8;
+constexpr int kMaxHB = 14;
+constexpr int kRetryHB1 = 11;
+constexpr int kLists = 3;
+inline int retry_list_after(int hb) { return hb < kRetryHB1 ? 0 : (hb < kMaxHB ? 1 : 2); }
 
 // k-closest pairs: distances are counted in log-spaced bins (16 per octave:
 // exact below 16, then 16 steps per power of two); the upper edge of the bin
 // holding the k-th count bounds the k-th smallest distance from above.
 constexpr uint32_t kDistBins = 512;   // 464 used
-static_assert(sizeof(QueryCtl) % 4 == 0, "QueryCtl is cleared as 32-bit words");
+
+// One query of a call as the kernels read it (uploaded per call).  Ids in R
+// and S are local to the query's graph; the graph's vertices are the global
+// ids voff .. voff + V - 1 of the resident CSR.
+struct QueryDesc {
+    const int32_t *R;           // device int32[nR]
+    const int32_t *S;           // device int32[nS]
+    int32_t nR, nS;
+    int32_t voff, V;
+    uint32_t theta;             // distance bound (inclusive)
+    uint32_t k;                 // 0: theta-join; else the k closest pairs within theta
+    uint32_t delta;             // bucket width (0 = one bucket)
+    uint32_t sbits;             // word offset of the query's S bitmap in the S-bitmap pool
+    uint32_t rbits;             // word offset of the query's rank bitmap in the rank-bitmap pool
+    uint32_t hist;              // k > 0: word offset of its two histograms in the histogram pool
+    uint32_t pad[2];
+};
+static_assert(sizeof(QueryDesc) == 64, "QueryDesc is 64 bytes");
+
+// Per-query device state of one call.  Zeroed first.
+struct QueryState {
+    uint32_t err;               // kErr* bits
+    uint32_t bound;             // k > 0: current distance bound (seeded, then lowered)
+    uint32_t src_start;         // first entry of the query's sources in the source list
+    uint32_t pad;
+    unsigned long long npairs;  // records the query emitted
+    unsigned long long nsel;    // records kept by the final bound
+    unsigned long long start;   // first kept record of the query in the sorted order
+    unsigned long long nout;    // pairs written for the query
+    unsigned long long off;     // first output position of the query
+    unsigned long long pad2;
+};
+static_assert(sizeof(QueryState) == 64, "QueryState is 64 bytes");
+
+// Control block of one call.  Zeroed first; QueryState[nq] follows it.
+struct CallCtl {
+    uint32_t err;               // OR of every query's error bits
+    uint32_t nsrc;              // sources staged
+    unsigned long long npairs;  // records emitted (may exceed the record buffer)
+    uint32_t nlist[kLists];     // sources queued on each re-run list
+    uint32_t nretry;            // sources that outgrew their first table
+    unsigned long long arcs;    // work count: out-arcs of every settled (source, vertex)
+    unsigned long long settled; // work count: settled (source, vertex) pairs
+    unsigned long long nsel;    // records kept by the final bounds
+    unsigned long long nout;    // pairs owed to the caller
+    uint32_t sort_db;           // distance bits of the sort key
+    uint32_t sort_passes;       // 8-bit digit passes the sort needs
+    uint32_t pad[2];
+};
+static_assert(sizeof(CallCtl) == 80, "CallCtl is 80 bytes");
+
+// One emitted (u, v, dist) of query q, ids local to the query's graph.
+struct alignas(16) Rec {
+    int32_t u;
+    int32_t v;
+    uint32_t d;
+    uint32_t q;
+};
 
 // One arc as the relaxation kernels read it: target, weight, and the target's
 // own arc range, so expanding a vertex needs no separate row_ptr lookup.
+// Vertex ids and arc indices are global across the resident graphs.
 struct alignas(16) ArcRec {
     int32_t y;
     uint32_t w;
@@ -52,68 +103,98 @@ struct alignas(16) ArcRec {
     int32_t yend;
 };
 
-// Arguments of one relaxation launch.
+// Arguments of one relaxation launch.  The launch searches from the sources
+// src[b .. e) with b = *sbeg (0 if sbeg is null) and e = *send.
 struct JoinArgs {
-    const int32_t *row_ptr;     // [V+1]
-    const ArcRec *arcs;         // [A]
-    const uint32_t *sbits;      // S membership bitmap
-    const int32_t *src;         // source vertex ids
-    const uint32_t *nsrc;       // device count of src
-    QueryCtl *ctl;
-    rn_pair *pairs;             // emitted pairs
-    unsigned long long pair_cap;
-    uint32_t *ovf;              // sources that outgrew this tier (vertex ids)
-    uint32_t *novf;             // device count of ovf
-    uint32_t theta;             // bound for the theta-join
-    uint32_t delta;             // bucket width (0 = one bucket)
-    int32_t kcp;                // 1: bound is ctl->theta, read every phase
+    const int32_t *row_ptr;     // resident CSR row pointers (global ids)
+    const ArcRec *arcs;
+    const QueryDesc *qd;
+    QueryState *qs;
+    const uint32_t *sbits;      // S-bitmap pool
+    uint32_t *hists;            // histogram pool (k-closest pairs)
+    const int32_t *src;         // sources (global ids) and their queries
+    const uint32_t *srcq;
+    const uint32_t *sbeg;
+    const uint32_t *send;
+    CallCtl *ctl;
+    Rec *recs;                  // emitted records
+    unsigned long long rec_cap;
+    int32_t *ovf;               // where searches that outgrow this tier are queued
+    uint32_t *ovfq;
+    uint32_t *novf;
+    int32_t first_tier;         // 1: count re-queued searches in ctl->nretry
     int32_t count_work;         // 1: accumulate ctl->arcs / ctl->settled
-    uint32_t k;                 // k-closest pairs: k
-    uint32_t *cand_hist;        // k-closest pairs: kDistBins counts of emitted distances
 };
 
 // Per-source state of the global-memory tier, one slot per concurrent block:
-// dist[V] | queued bitmap[ceil(V/32)] | frontier[V] | next frontier[V] | touched[V].
-// Between searches dist is all kInf and the bitmap all zero.
+// dist[V] | queued bitmap[ceil(V/32)] | frontier[V] | next frontier[V] | touched[V],
+// V the largest graph's vertex count.  Between searches dist is all kInf and
+// the bitmap all zero.
 inline size_t global_slot_words(int32_t V) {
     return 4 * static_cast<size_t>(V) + (static_cast<size_t>(V) + 31) / 32;
 }
 
-// Launchers (rn_kernels.hip).  All take the stream to enqueue on.
+// Host-side description of the call buffers the launch sequence uses.
+struct CallBuffers {
+    int32_t nq;
+    const QueryDesc *qd;        // [nq]
+    const unsigned long long *ebase;   // [nq+1] prefix of nS + nR in staging order
+    const uint32_t *rbase;      // [nq+1] rank-pool word prefix in staging order
+    const uint32_t *perm;       // [nq] query at each staging position
+    CallCtl *ctl;               // followed by QueryState[nq]
+    QueryState *qs;
+    uint32_t *sbits;            // S-bitmap pool
+    uint32_t *rbits;            // rank-bitmap pool
+    uint32_t rwords;            // its words
+    uint32_t *hists;            // histogram pool
+    uint32_t *sort_hist;        // sort_hist_words() words
+    uint32_t *stage_scratch;    // stage_scratch_words(rwords) words
+    int32_t *src;               // source list and its queries
+    uint32_t *srcq;
+    int32_t *list[kLists];      // re-run lists and their queries
+    uint32_t *listq[kLists];
+    Rec *recs[2];
+    unsigned long long rec_cap;
+};
+
+// ---- launchers (rn_kernels.hip); all enqueue on stream s
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
-hipError_t launch_stage(const int32_t *R, int32_t nR, const int32_t *S, int32_t nS, int32_t V,
-                        const int32_t *rank, const int32_t *order, uint32_t *rbits,
-                        uint32_t *sbits, int32_t *src, QueryCtl *ctl, uint32_t *scratch,
-                        hipStream_t s);
-size_t stage_scratch_words(int32_t V);
-// Relaxation at table tier `tier` (log2 size hash_log2); grid chosen inside.
+
+// Validate every query's R and S, set the S bitmaps and rank bitmaps, and list
+// the sources query by query (staging order) in rank order.
+// rank/order: per-graph vertex order (nullptr: identity).  max_elems: sum of
+// nS + nR over the queries.
+hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, const int32_t *rank,
+                        const int32_t *order, hipStream_t s);
+size_t stage_scratch_words(size_t rwords);
+
+// Relaxation at the on-chip tier with table size 2^hash_log2; grid chosen inside.
 hipError_t launch_join(const JoinArgs &a, int hash_log2, uint32_t max_sources, hipStream_t s);
 int join_tier_supported(int hash_log2);
 // The global-memory tier: one block per source, nslots slots of
-// global_slot_words(V) words each.
-hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslots, int32_t V,
+// global_slot_words(Vmax) words each.
+hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslots, int32_t Vmax,
                               uint32_t max_sources, hipStream_t s);
-// Sort pairs[0 .. min(*n, cap)) by (dist, u, v) (scratch: another buffer of
-// cap pairs) and write them to out when the query succeeded and the result
-// fits (no argument error, no search left over, *n <= user_cap, *n <= cap).
-// hist: sort_hist_words() words, zero on entry.  max_dist bounds every dist.
-// Only the first out_limit sorted pairs are written (all of them for a theta-join).
-hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned long long *n,
-                              unsigned long long cap, uint32_t max_dist, int32_t V, uint32_t *hist,
-                              rn_pair *out, unsigned long long user_cap, unsigned long long out_limit,
-                              const QueryCtl *ctl, int last_tier, hipStream_t s);
+
+// k closest pairs: seed every k-query's bound from the direct arcs between its
+// R and S, capped by its theta.
+hipError_t launch_kcp_seed(const JoinArgs &a, const CallBuffers &b, uint32_t max_sources, hipStream_t s);
+
+// Keep the records within their query's final bound (into recs[1]).
+hipError_t launch_select(const CallBuffers &b, hipStream_t s);
+
+// Per-query segments of the sorted records and of the output, the key layout
+// of the sort (ctl->sort_db, ctl->sort_passes); selected: records were
+// filtered by launch_select (else every emitted record is kept in place).
+hipError_t launch_layout(const CallBuffers &b, int selected, uint32_t qb, uint32_t vb, hipStream_t s);
+
+// Sort the kept records by (query, dist, u, v) and write each query's first
+// nout pairs to out at its offset, unless the records outgrew the buffer or
+// the total exceeds user_cap.  Launches max_passes digit passes; those beyond
+// ctl->sort_passes return at once.
+hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_passes, uint32_t vb,
+                           rn_pair *out, unsigned long long user_cap, hipStream_t s);
 size_t sort_hist_words();
-// k-closest pairs: seed the bound ctl->theta from the direct arcs between R and
-// S (seed_hist: kDistBins zeroed words), then, after the searches, keep the
-// emitted pairs within the final bound (into `kept`, count ctl->nsel).
-hipError_t launch_kcp_seed(const int32_t *src, const uint32_t *nsrc, uint32_t max_sources,
-                           const int32_t *row_ptr, const ArcRec *arcs, const uint32_t *sbits,
-                           uint32_t *seed_hist, uint32_t k, QueryCtl *ctl, hipStream_t s);
-hipError_t launch_kcp_filter(const rn_pair *pairs, unsigned long long cap, rn_pair *kept, QueryCtl *ctl,
-                             hipStream_t s);
-// Copy sorted pairs to the caller when the query succeeded and fits.
-hipError_t launch_copy_out(const rn_pair *src, rn_pair *dst, const unsigned long long *n,
-                           const QueryCtl *ctl, unsigned long long user_cap, unsigned long long limit,
-                           unsigned long long out_limit, int last_tier, hipStream_t s);
+constexpr uint32_t kSortPassesMax = 16;
 
 }  // namespace rn

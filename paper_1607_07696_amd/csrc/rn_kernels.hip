@@ -1,13 +1,19 @@
 // rn_kernels.hip -- gfx950 kernels of the network-distance joins.
 //
-// Query pipeline (one HIP stream, no host round trip in between):
-//   stage     validate R and S, build the S-membership bitmap and the ordered
-//             source list (k_mark, k_overlap, k_compact)
+// A call runs any mix of theta-joins and k-closest-pairs queries, each on one
+// of the resident graphs, as one launch sequence on one HIP stream:
+//   stage     validate every query's R and S, set its S-membership bitmap and
+//             list all sources query by query (k_mark, k_overlap, k_rank_*)
+//   seed      k-closest pairs: a first distance bound per query from the
+//             direct R-S arcs (k_kcp_seed_*)
 //   relax     one wavefront per source: a bounded, bucketed label-correcting
 //             search whose whole state (distance table, pending set, frontier)
-//             lives in LDS; emits (u, v, dist) for v in S (k_join)
-//   sort      LSD radix sort of the pairs on the (dist, u, v) key
-//   copy-out  into the caller's buffer when the query succeeded and fits
+//             lives in LDS; emits (u, v, dist, query) for v in S (k_join), with
+//             larger tables and a global-memory tier for searches that outgrow
+//             the first
+//   select    k-closest pairs: keep the records within the final bounds
+//   sort      LSD radix sort of the records on the (query, dist, u, v) key;
+//             the last digit pass writes each query's segment of the output
 //
 // The queries are the paper's theta-join and k-closest pairs (Abstract;
 // Section 1; Section 4).  The per-source search plays the role of the paper's
@@ -176,10 +182,44 @@ struct WaveState {
     bool ovf;       // the search outgrew this tier
 };
 
-__device__ __forceinline__ uint32_t current_bound(const JoinArgs &a) {
-    if (!a.kcp) return a.theta;
-    uint32_t t = __hip_atomic_load(&a.ctl->theta, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return min(t, a.theta);
+// What a search needs to know about its query (read once per source; uniform
+// across the wave, so the compiler keeps it in scalar registers).
+struct SrcCtx {
+    uint32_t theta;                 // the query's own bound
+    uint32_t k;                     // 0: theta-join
+    uint32_t delta;
+    int32_t voff;                   // first global id of the query's graph
+    uint32_t q;
+    const uint32_t *sbits;          // the query's S bitmap (local ids)
+    uint32_t *cand_hist;            // k > 0: emitted-distance histogram
+    uint32_t *bound;                // k > 0: the shared, shrinking bound
+    unsigned long long *npairs;     // records the query emitted so far
+};
+
+__device__ __forceinline__ SrcCtx load_ctx(const JoinArgs &a, uint32_t q) {
+    const QueryDesc &d = a.qd[q];
+    SrcCtx c;
+    c.theta = d.theta;
+    c.k = d.k;
+    c.delta = d.delta;
+    c.voff = d.voff;
+    c.q = q;
+    c.sbits = a.sbits + d.sbits;
+    c.cand_hist = a.hists + d.hist + kDistBins;
+    c.bound = &a.qs[q].bound;
+    c.npairs = &a.qs[q].npairs;
+    return c;
+}
+
+__device__ __forceinline__ uint32_t current_bound(const SrcCtx &c) {
+    if (c.k == 0) return c.theta;
+    const uint32_t t = __hip_atomic_load(c.bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return min(t, c.theta);
+}
+
+__device__ __forceinline__ bool in_s(const SrcCtx &c, uint32_t y) {
+    const uint32_t yl = y - static_cast<uint32_t>(c.voff);
+    return (c.sbits[yl >> 5] >> (yl & 31u)) & 1u;
 }
 
 // Relax NJ window arcs per lane (slot j holds window arc j*64 + lane) and
@@ -294,34 +334,44 @@ __device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, uin
     relax_window<HB, NJ>(L, st, P, r, nd, bound);
 }
 
-// k-closest pairs: once k pairs have been emitted, bound the k-th distance by
-// the emitted-distance histogram and lower the shared bound.  Whole wave.
-__device__ __forceinline__ void tighten_bound(const JoinArgs &a) {
-    const unsigned long long n =
-        __hip_atomic_load(&a.ctl->npairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (n < a.k) return;
-    const uint32_t b = wave_bound_from_hist(a.cand_hist, a.k);
-    if ((threadIdx.x & 63u) == 0) atomicMin(&a.ctl->theta, b);
+// k-closest pairs: once the query has emitted k records, bound its k-th
+// distance by its emitted-distance histogram and lower the shared bound.
+// Whole wave.
+__device__ __forceinline__ void tighten_bound(const SrcCtx &c) {
+    const unsigned long long n = __hip_atomic_load(c.npairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (n < c.k) return;
+    const uint32_t b = wave_bound_from_hist(c.cand_hist, c.k);
+    if ((threadIdx.x & 63u) == 0) atomicMin(c.bound, b);
+}
+
+// Reserve n record slots for query c (one atomic per wave); the base is
+// returned to every lane.
+__device__ __forceinline__ unsigned long long reserve_recs(const JoinArgs &a, const SrcCtx &c, uint32_t n) {
+    unsigned long long base = 0;
+    if (lane_id() == 0) {
+        base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(n));
+        atomicAdd(c.npairs, static_cast<unsigned long long>(n));
+    }
+    return (static_cast<unsigned long long>(readlane(static_cast<uint32_t>(base >> 32), 0)) << 32) |
+           readlane(static_cast<uint32_t>(base), 0);
 }
 
 // Write this wave's staged pairs (v in L.beg[0], dist in L.ent[0]) for source u.
 template <int HB>
-__device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a, int32_t u,
+__device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
                                             uint32_t &nst) {
     if (nst == 0) return;
-    unsigned long long base = 0;
-    if (lane_id() == 0) base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(nst));
-    base = (static_cast<unsigned long long>(readlane(static_cast<uint32_t>(base >> 32), 0)) << 32) |
-           readlane(static_cast<uint32_t>(base), 0);
+    const unsigned long long base = reserve_recs(a, c, nst);
     wave_sync();
     for (uint32_t i = lane_id(); i < nst; i += 64) {
         const unsigned long long idx = base + i;
-        if (idx < a.pair_cap) {
-            rn_pair p;
-            p.u = u;
-            p.v = L.beg[0][i];
-            p.dist = L.ent[0][i];
-            a.pairs[idx] = p;
+        if (idx < a.rec_cap) {
+            Rec r;
+            r.u = u - c.voff;
+            r.v = L.beg[0][i] - c.voff;
+            r.d = L.ent[0][i];
+            r.q = c.q;
+            a.recs[idx] = r;
         }
     }
     wave_sync();
@@ -339,7 +389,7 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
 // at once.  The search ends when nothing is pending; every table entry then
 // holds its exact distance, and entries in S become pairs.
 template <int HB>
-__device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
+__device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u) {
     constexpr int H = Tier<HB>::H;
     constexpr int PC = Tier<HB>::PC;
     constexpr int U = Tier<HB>::U;
@@ -360,19 +410,19 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
     st.ovf = (ue - ub) > 0xFFFF;
     uint32_t P = 0;      // list receiving appends (the pending list)
     uint32_t pmin = 0;
-    uint32_t bound = a.theta;
+    uint32_t bound = c.theta;
 
     while (st.np > 0 && !st.ovf) {
-        bound = current_bound(a);
+        bound = current_bound(c);
         uint32_t F, nf;
         uint32_t kmin = kInf;
-        if (a.delta == 0) {
+        if (c.delta == 0) {
             F = P;
             nf = st.np;
             P ^= 1u;
             st.np = 0;
         } else {
-            const uint64_t t64 = (static_cast<uint64_t>(pmin / a.delta) + 1ull) * a.delta;
+            const uint64_t t64 = (static_cast<uint64_t>(pmin / c.delta) + 1ull) * c.delta;
             const uint32_t thr = t64 > kInf ? kInf : static_cast<uint32_t>(t64);
             F = P ^ 1u;
             nf = 0;
@@ -436,23 +486,23 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
             }
         }
         if (st.ovf) break;
-        if (a.delta != 0) pmin = min(wave_min(kmin), wave_min(st.imin));
+        if (c.delta != 0) pmin = min(wave_min(kmin), wave_min(st.imin));
     }
 
     // ---- emit table entries in S, and clear the table for the next source
-    bound = current_bound(a);
+    bound = current_bound(c);
     uint32_t nst = 0, emitted = 0;
     unsigned long long warcs = 0;
     uint32_t wsettled = 0;
     for (uint32_t g0 = 0; g0 < static_cast<uint32_t>(H); g0 += 64 * U) {
-        uint32_t k[U], d[U], sb[U];
+        uint32_t k[U], d[U];
+        bool sb[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const uint32_t slot = g0 + j * 64 + lane;
             k[j] = lds_load(&L.key[slot]);
             d[j] = L.dw[slot] >> 1;
-            sb[j] = 0;
-            if (!st.ovf && k[j] != kEmpty) sb[j] = a.sbits[k[j] >> 5];
+            sb[j] = !st.ovf && k[j] != kEmpty && in_s(c, k[j]);
         }
         if (a.count_work && !st.ovf) {
 #pragma unroll
@@ -470,24 +520,23 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
         }
 #pragma unroll
         for (int j = 0; j < U; ++j) {
-            const uint32_t y = k[j];
-            const bool m = !st.ovf && y != kEmpty && ((sb[j] >> (y & 31u)) & 1u) && d[j] <= bound;
+            const bool m = sb[j] && d[j] <= bound;
             const uint64_t mM = __ballot(m);
-            if (a.kcp && m) atomicAdd(&a.cand_hist[dist_bin(d[j])], 1u);
+            if (c.k && m) atomicAdd(&c.cand_hist[dist_bin(d[j])], 1u);
             emitted += popc(mM);
             const uint32_t idx = m ? nst + mbcnt(mM) : static_cast<uint32_t>(PC);
-            L.beg[0][idx] = static_cast<int32_t>(y);
+            L.beg[0][idx] = static_cast<int32_t>(k[j]);
             L.ent[0][idx] = d[j];
             nst += popc(mM);
             if (nst + 64 > static_cast<uint32_t>(PC)) {
                 wave_sync();
-                flush_pairs<HB>(L, a, u, nst);
+                flush_pairs<HB>(L, a, c, u, nst);
             }
         }
     }
     wave_sync();
-    flush_pairs<HB>(L, a, u, nst);
-    if (a.kcp && emitted != 0) tighten_bound(a);
+    flush_pairs<HB>(L, a, c, u, nst);
+    if (c.k && emitted != 0) tighten_bound(c);
     if (a.count_work && !st.ovf) {
         for (int o = 32; o > 0; o >>= 1) {
             const uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(warcs & 0xFFFFFFFFull), o));
@@ -502,20 +551,29 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, int32_t u) {
     }
     if (st.ovf && lane == 0) {
         const uint32_t idx = atomicAdd(a.novf, 1u);
-        a.ovf[idx] = static_cast<uint32_t>(u);
+        a.ovf[idx] = u;
+        a.ovfq[idx] = c.q;
+        if (a.first_tier) atomicAdd(&a.ctl->nretry, 1u);
     }
     wave_sync();
 }
 
-// One wavefront per block; sources split into 8 contiguous chunks, chunk c
-// taken by the blocks with blockIdx % 8 == c so that each XCD (blocks are
-// dealt to the 8 XCDs round-robin) sweeps one region of the source order and
-// keeps its part of the graph in its own L2.
+__device__ __forceinline__ void launch_range(const JoinArgs &a, uint32_t &b, uint32_t &n) {
+    b = a.sbeg ? *a.sbeg : 0u;
+    const uint32_t e = *a.send;
+    n = e > b ? e - b : 0u;
+}
+
+// One wavefront per block; the launch's sources split into 8 contiguous
+// chunks, chunk c taken by the blocks with blockIdx % 8 == c so that each XCD
+// (blocks are dealt to the 8 XCDs round-robin) sweeps one region of the
+// source order and keeps its part of the graph in its own L2.
 template <int HB>
 __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
     __shared__ SearchLds<HB> L;
     constexpr int H = Tier<HB>::H;
-    const uint32_t n = *a.nsrc;
+    uint32_t b, n;
+    launch_range(a, b, n);
     const uint32_t per = (n + 7u) / 8u;
     if (blockIdx.x >= 8u * per) return;
     for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(H); i += 64) {
@@ -526,16 +584,17 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
     for (uint32_t t = blockIdx.x; t < 8u * per; t += gridDim.x) {
         const uint32_t si = (t & 7u) * per + (t >> 3);
         if (si >= n) continue;
-        search_source<HB>(L, a, a.src[si]);
+        const SrcCtx c = load_ctx(a, a.srcq[b + si]);
+        search_source<HB>(L, a, c, a.src[b + si]);
     }
 }
 
 // ------------------------------------------------------------------ global-memory tier
 // A search that outgrows every on-chip table runs here: one 256-thread block
-// per source, its distances in a dense per-slot array, frontier-synchronous
-// (every vertex improved in a round is expanded in the next).  Only rare, very
-// large searches (huge balls, expander graphs, unbounded k-closest-pairs
-// searches) take this path.
+// per source, its distances in a dense per-slot array indexed by the local id,
+// frontier-synchronous (every vertex improved in a round is expanded in the
+// next).  Only rare, very large searches (huge balls, expander graphs,
+// unbounded k-closest-pairs searches) take this path.
 __device__ __forceinline__ uint32_t gload(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -544,22 +603,25 @@ __device__ __forceinline__ void gstore(uint32_t *p, uint32_t v) {
 }
 
 __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots, size_t slot_words,
-                                                     int32_t V) {
+                                                     int32_t Vmax) {
     __shared__ uint32_t s_nf, s_nfn, s_ntouched, s_bound;
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
-    const uint32_t n = *a.nsrc;
-    const size_t nw = (static_cast<size_t>(V) + 31) / 32;
-    uint32_t *dist = slots + blockIdx.x * slot_words;
-    uint32_t *inq = dist + V;
-    uint32_t *fa = inq + nw;
-    uint32_t *fb = fa + V;
-    uint32_t *touched = fb + V;
+    uint32_t sb, n;
+    launch_range(a, sb, n);
+    const size_t nw = (static_cast<size_t>(Vmax) + 31) / 32;
+    uint32_t *dist = slots + blockIdx.x * slot_words;   // local ids
+    uint32_t *inq = dist + Vmax;                         // local ids
+    uint32_t *fa = inq + nw;                             // global ids
+    uint32_t *fb = fa + Vmax;
+    uint32_t *touched = fb + Vmax;                       // local ids
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
-        const int32_t u = a.src[i];
+        const int32_t u = a.src[sb + i];
+        const SrcCtx c = load_ctx(a, a.srcq[sb + i]);
+        const uint32_t voff = static_cast<uint32_t>(c.voff);
         if (tid == 0) {
-            gstore(&dist[u], 0u);
+            gstore(&dist[u - c.voff], 0u);
             fa[0] = static_cast<uint32_t>(u);
-            touched[0] = static_cast<uint32_t>(u);
+            touched[0] = static_cast<uint32_t>(u - c.voff);
             s_nf = 1;
             s_ntouched = 1;
         }
@@ -571,29 +633,29 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
             __syncthreads();
             if (tid == 0) {
                 s_nfn = 0;
-                s_bound = current_bound(a);
+                s_bound = current_bound(c);
             }
             for (uint32_t j = tid; j < nf; j += 256) {
-                const uint32_t x = F[j];
+                const uint32_t x = F[j] - voff;
                 atomicAnd(&inq[x >> 5], ~(1u << (x & 31u)));
             }
             __syncthreads();
             const uint32_t bound = s_bound;
             for (uint32_t j = tid; j < nf; j += 256) {
                 const uint32_t x = F[j];
-                const uint32_t dx = gload(&dist[x]);
+                const uint32_t dx = gload(&dist[x - voff]);
                 if (dx > bound) continue;
                 const int32_t e = a.row_ptr[x + 1];
                 for (int32_t arc = a.row_ptr[x]; arc < e; ++arc) {
                     const ArcRec r = a.arcs[arc];
                     const uint32_t nd = sat_add(dx, r.w);
                     if (nd > bound) continue;
-                    const uint32_t y = static_cast<uint32_t>(r.y);
-                    const uint32_t old = atomicMin(&dist[y], nd);
+                    const uint32_t yl = static_cast<uint32_t>(r.y) - voff;
+                    const uint32_t old = atomicMin(&dist[yl], nd);
                     if (nd >= old) continue;
-                    if (old == kInf) touched[atomicAdd(&s_ntouched, 1u)] = y;
-                    const uint32_t bit = 1u << (y & 31u);
-                    if ((atomicOr(&inq[y >> 5], bit) & bit) == 0) Fn[atomicAdd(&s_nfn, 1u)] = y;
+                    if (old == kInf) touched[atomicAdd(&s_ntouched, 1u)] = yl;
+                    const uint32_t bit = 1u << (yl & 31u);
+                    if ((atomicOr(&inq[yl >> 5], bit) & bit) == 0) Fn[atomicAdd(&s_nfn, 1u)] = static_cast<uint32_t>(r.y);
                 }
             }
             __syncthreads();
@@ -604,7 +666,7 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
             Fn = t;
         }
         // emit S members, count work, reset the slot
-        if (tid == 0) s_bound = current_bound(a);
+        if (tid == 0) s_bound = current_bound(c);
         __syncthreads();
         const uint32_t bound = s_bound;
         const uint32_t nt = s_ntouched;
@@ -612,33 +674,37 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
         uint32_t wsettled = 0;
         for (uint32_t j0 = 0; j0 < nt; j0 += 256) {
             const uint32_t j = j0 + tid;
-            uint32_t y = 0, d = kInf;
+            uint32_t yl = 0, d = kInf;
             bool m = false;
             if (j < nt) {
-                y = touched[j];
-                d = gload(&dist[y]);
-                gstore(&dist[y], kInf);
-                m = d <= bound && ((a.sbits[y >> 5] >> (y & 31u)) & 1u);
+                yl = touched[j];
+                d = gload(&dist[yl]);
+                gstore(&dist[yl], kInf);
+                m = d <= bound && ((c.sbits[yl >> 5] >> (yl & 31u)) & 1u);
                 if (a.count_work && d <= bound) {
-                    warcs += static_cast<unsigned long long>(a.row_ptr[y + 1] - a.row_ptr[y]);
+                    warcs += static_cast<unsigned long long>(a.row_ptr[yl + voff + 1] - a.row_ptr[yl + voff]);
                     wsettled += 1;
                 }
             }
             const uint64_t mm = __ballot(m);
-            if (a.kcp && m) atomicAdd(&a.cand_hist[dist_bin(d)], 1u);
+            if (c.k && m) atomicAdd(&c.cand_hist[dist_bin(d)], 1u);
             if (mm != 0) {
                 unsigned long long base = 0;
-                if (lane == 0) base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(popc(mm)));
+                if (lane == 0) {
+                    base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(popc(mm)));
+                    atomicAdd(c.npairs, static_cast<unsigned long long>(popc(mm)));
+                }
                 const uint32_t lo = static_cast<uint32_t>(__shfl(static_cast<int>(base & 0xFFFFFFFFull), 0));
                 const uint32_t hi = static_cast<uint32_t>(__shfl(static_cast<int>(base >> 32), 0));
                 base = (static_cast<unsigned long long>(hi) << 32) | lo;
                 const unsigned long long idx = base + mbcnt(mm);
-                if (m && idx < a.pair_cap) {
-                    rn_pair p;
-                    p.u = u;
-                    p.v = static_cast<int32_t>(y);
-                    p.dist = d;
-                    a.pairs[idx] = p;
+                if (m && idx < a.rec_cap) {
+                    Rec r;
+                    r.u = u - c.voff;
+                    r.v = static_cast<int32_t>(yl);
+                    r.d = d;
+                    r.q = c.q;
+                    a.recs[idx] = r;
                 }
             }
         }
@@ -655,7 +721,7 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
             }
         }
         __syncthreads();
-        if (a.kcp && tid < 64) tighten_bound(a);
+        if (c.k && tid < 64) tighten_bound(c);
     }
 }
 
@@ -666,29 +732,66 @@ __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
         p[i] = v;
 }
 
-__global__ void k_mark(const int32_t *R, int32_t nR, const int32_t *S, int32_t nS, int32_t V,
-                       const int32_t *rank, uint32_t *rbits, uint32_t *sbits, QueryCtl *ctl) {
-    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (i < nS) {
-        const int32_t s = S[i];
-        if (s < 0 || s >= V) { atomicOr(&ctl->err, kErrRange); return; }
-        const uint32_t bit = 1u << (s & 31);
-        if (atomicOr(&sbits[s >> 5], bit) & bit) atomicOr(&ctl->err, kErrDupS);
-    } else if (i < static_cast<int64_t>(nS) + nR) {
-        const int32_t u = R[i - nS];
-        if (u < 0 || u >= V) { atomicOr(&ctl->err, kErrRange); return; }
-        const int32_t r = rank ? rank[u] : u;
-        const uint32_t bit = 1u << (r & 31);
-        if (atomicOr(&rbits[r >> 5], bit) & bit) atomicOr(&ctl->err, kErrDupR);
+// Largest p in [0, n) with a[p] <= x (a non-decreasing, a[0] <= x).
+template <typename T>
+__device__ __forceinline__ uint32_t seg_of(const T *a, uint32_t n, T x) {
+    uint32_t lo = 0, hi = n;   // answer in [lo, hi)
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (a[mid] <= x) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// One thread per element of the flattened (S then R) lists of every query in
+// staging order: range and duplicate checks, S bits, and rank bits of R.
+__global__ void k_mark(CallBuffers b, const int32_t *rank) {
+    const unsigned long long i = blockIdx.x * static_cast<unsigned long long>(blockDim.x) + threadIdx.x;
+    const uint32_t nq = static_cast<uint32_t>(b.nq);
+    if (i >= b.ebase[nq]) return;
+    const uint32_t p = seg_of(b.ebase, nq, i);
+    const uint32_t q = b.perm[p];
+    const QueryDesc &d = b.qd[q];
+    const unsigned long long j = i - b.ebase[p];
+    uint32_t err = 0;
+    if (j < static_cast<unsigned long long>(d.nS)) {
+        const int32_t s = d.S[j];
+        if (s < 0 || s >= d.V) {
+            err = kErrRange;
+        } else {
+            const uint32_t bit = 1u << (s & 31);
+            if (atomicOr(&b.sbits[d.sbits + (s >> 5)], bit) & bit) err = kErrDupS;
+        }
+    } else {
+        const int32_t u = d.R[j - d.nS];
+        if (u < 0 || u >= d.V) {
+            err = kErrRange;
+        } else {
+            const int32_t r = rank ? rank[d.voff + u] : u;
+            const uint32_t bit = 1u << (r & 31);
+            if (atomicOr(&b.rbits[d.rbits + (r >> 5)], bit) & bit) err = kErrDupR;
+        }
+    }
+    if (err) {
+        atomicOr(&b.qs[q].err, err);
+        atomicOr(&b.ctl->err, err);
     }
 }
 
-__global__ void k_overlap(const int32_t *R, int32_t nR, int32_t V, const uint32_t *sbits,
-                          QueryCtl *ctl) {
-    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-    if (i >= nR) return;
-    const int32_t u = R[i];
-    if (u >= 0 && u < V && ((sbits[u >> 5] >> (u & 31)) & 1u)) atomicOr(&ctl->err, kErrOverlap);
+__global__ void k_overlap(CallBuffers b) {
+    const unsigned long long i = blockIdx.x * static_cast<unsigned long long>(blockDim.x) + threadIdx.x;
+    const uint32_t nq = static_cast<uint32_t>(b.nq);
+    if (i >= b.ebase[nq]) return;
+    const uint32_t p = seg_of(b.ebase, nq, i);
+    const uint32_t q = b.perm[p];
+    const QueryDesc &d = b.qd[q];
+    const unsigned long long j = i - b.ebase[p];
+    if (j < static_cast<unsigned long long>(d.nS)) return;
+    const int32_t u = d.R[j - d.nS];
+    if (u >= 0 && u < d.V && ((b.sbits[d.sbits + (u >> 5)] >> (u & 31)) & 1u)) {
+        atomicOr(&b.qs[q].err, kErrOverlap);
+        atomicOr(&b.ctl->err, kErrOverlap);
+    }
 }
 
 // Block-wide exclusive scan of one value per thread (blockDim.x = 1024); *total
@@ -709,7 +812,7 @@ __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t *w
     return off + incl - v;
 }
 
-// Source listing, pass 1: marked ranks per 1024-word block of the rank bitmap.
+// Source listing, pass 1: marked ranks per 1024-word block of the rank pool.
 __global__ __launch_bounds__(1024) void k_rank_count(const uint32_t *rbits, uint32_t nwords,
                                                      uint32_t *bsum) {
     __shared__ uint32_t wsum[16];
@@ -719,10 +822,10 @@ __global__ __launch_bounds__(1024) void k_rank_count(const uint32_t *rbits, uint
     if (threadIdx.x == 0) bsum[blockIdx.x] = total;
 }
 
-// Source listing, pass 2: list the marked ranks in increasing order as vertex ids.
-__global__ __launch_bounds__(1024) void k_rank_emit(const uint32_t *rbits, uint32_t nwords,
-                                                    const uint32_t *bsum, const int32_t *order,
-                                                    int32_t *src, QueryCtl *ctl) {
+// Source listing, pass 2: list the marked ranks in increasing pool order as
+// global vertex ids with their queries; the first word of each query records
+// where its sources start.
+__global__ __launch_bounds__(1024) void k_rank_emit(CallBuffers b, const uint32_t *bsum, const int32_t *order) {
     __shared__ uint32_t wsum[16];
     const uint32_t tid = threadIdx.x;
     uint32_t acc = 0;
@@ -730,27 +833,168 @@ __global__ __launch_bounds__(1024) void k_rank_emit(const uint32_t *rbits, uint3
     uint32_t pre;
     block_excl_scan_1024(acc, wsum, &pre);
     const uint32_t i = blockIdx.x * 1024u + tid;
-    uint32_t bits = i < nwords ? rbits[i] : 0u;
+    const bool valid = i < b.rwords;
+    uint32_t bits = valid ? b.rbits[i] : 0u;
     uint32_t total;
     uint32_t pos = pre + block_excl_scan_1024(__popc(bits), wsum, &total);
-    while (bits) {
-        const uint32_t b = __ffs(bits) - 1u;
-        const int32_t r = static_cast<int32_t>(i * 32u + b);
-        src[pos++] = order ? order[r] : r;
-        bits &= bits - 1u;
+    if (valid) {
+        const uint32_t p = seg_of(b.rbase, static_cast<uint32_t>(b.nq), i);
+        const uint32_t q = b.perm[p];
+        const uint32_t lw = i - b.rbase[p];
+        const int32_t voff = b.qd[q].voff;
+        if (lw == 0) b.qs[q].src_start = pos;
+        while (bits) {
+            const uint32_t bt = __ffs(bits) - 1u;
+            const int32_t r = static_cast<int32_t>(lw * 32u + bt);
+            b.src[pos] = voff + (order ? order[voff + r] : r);
+            b.srcq[pos] = q;
+            ++pos;
+            bits &= bits - 1u;
+        }
     }
-    if (blockIdx.x == gridDim.x - 1 && tid == 0) ctl->nsrc = pre + total;
+    if (blockIdx.x == gridDim.x - 1 && tid == 0) b.ctl->nsrc = pre + total;
+}
+
+// ------------------------------------------------------------------ k-closest pairs
+// Seed: every distinct (u, y) with u in R, y in S joined by an arc has
+// dist(u, y) <= the lightest such arc's weight, so the bin edge where k of
+// these weights are reached bounds the k-th smallest distance.  A pair with
+// parallel arcs is counted once, at its first lightest arc.
+__global__ void k_kcp_seed_hist(JoinArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= *a.send) return;
+    const SrcCtx c = load_ctx(a, a.srcq[i]);
+    if (c.k == 0) return;
+    uint32_t *seed = c.cand_hist - kDistBins;
+    const int32_t u = a.src[i];
+    const int32_t b = a.row_ptr[u], e = a.row_ptr[u + 1];
+    for (int32_t x = b; x < e; ++x) {
+        const ArcRec r = a.arcs[x];
+        if (!in_s(c, static_cast<uint32_t>(r.y))) continue;
+        bool first = true;
+        for (int32_t z = b; z < e && first; ++z) {
+            const ArcRec o = a.arcs[z];
+            if (o.y == r.y && (o.w < r.w || (o.w == r.w && z < x))) first = false;
+        }
+        if (first) atomicAdd(&seed[dist_bin(r.w)], 1u);
+    }
+}
+
+// One wave per query: the seeded bound of each k-query, capped by its theta.
+__global__ __launch_bounds__(64) void k_kcp_seed_bound(const QueryDesc *qd, QueryState *qs, const uint32_t *hists) {
+    const QueryDesc &d = qd[blockIdx.x];
+    if (d.k == 0) return;
+    const uint32_t b = wave_bound_from_hist(hists + d.hist, d.k);
+    if (threadIdx.x == 0) qs[blockIdx.x].bound = min(b, d.theta);
+}
+
+// Keep the records within their query's final bound (order is restored by the
+// sort).  Counts are taken per wave: one atomic per run of equal queries.
+__global__ void k_select(CallBuffers b) {
+    const unsigned long long n = min(b.ctl->npairs, b.rec_cap);
+    const Rec *in = b.recs[0];
+    Rec *kept = b.recs[1];
+    const unsigned long long stride = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
+    for (unsigned long long i0 = blockIdx.x * static_cast<unsigned long long>(blockDim.x);
+         i0 < n; i0 += stride) {
+        const unsigned long long i = i0 + threadIdx.x;
+        const bool valid = i < n;
+        Rec r{0, 0, 0, 0};
+        bool keep = false;
+        if (valid) {
+            r = in[i];
+            keep = b.qd[r.q].k == 0 || r.d <= b.qs[r.q].bound;
+        }
+        const uint64_t mk = __ballot(keep);
+        if (mk == 0) continue;
+        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(mk)) - 1);
+        const uint32_t q0 = readlane(r.q, static_cast<int>(leader));
+        unsigned long long base = 0;
+        if (lane_id() == leader) base = atomicAdd(&b.ctl->nsel, static_cast<unsigned long long>(popc(mk)));
+        base = (static_cast<unsigned long long>(readlane(static_cast<uint32_t>(base >> 32), static_cast<int>(leader))) << 32) |
+               readlane(static_cast<uint32_t>(base), static_cast<int>(leader));
+        if (keep) kept[base + mbcnt(mk)] = r;
+        const bool same = __ballot(keep && r.q != q0) == 0;
+        if (same) {
+            if (lane_id() == leader) atomicAdd(&b.qs[q0].nsel, static_cast<unsigned long long>(popc(mk)));
+        } else if (keep) {
+            atomicAdd(&b.qs[r.q].nsel, 1ull);
+        }
+    }
+}
+
+// ------------------------------------------------------------------ layout
+// Exclusive scan of 64-bit values over a 1024-thread block (s: 1024 words).
+__device__ __forceinline__ unsigned long long block_excl_scan_u64(unsigned long long v, unsigned long long *s,
+                                                                  unsigned long long *total) {
+    const uint32_t tid = threadIdx.x;
+    s[tid] = v;
+    __syncthreads();
+    for (uint32_t o = 1; o < 1024; o <<= 1) {
+        const unsigned long long x = tid >= o ? s[tid - o] : 0ull;
+        __syncthreads();
+        s[tid] += x;
+        __syncthreads();
+    }
+    const unsigned long long incl = s[tid];
+    *total = s[1023];
+    __syncthreads();
+    return incl - v;
+}
+
+__device__ __forceinline__ uint32_t bitlen32(uint32_t x) { return x ? 32u - static_cast<uint32_t>(__clz(x)) : 0u; }
+
+// One block: per query the kept count, its first position in the sorted
+// order, its output count (0 for a query with an argument error) and output
+// offset; then the sort key layout from the largest kept distance bound.
+__global__ __launch_bounds__(1024) void k_layout(CallBuffers b, int selected, uint32_t qb, uint32_t vb) {
+    __shared__ unsigned long long s[1024];
+    __shared__ uint32_t s_dmax;
+    const uint32_t tid = threadIdx.x;
+    if (tid == 0) s_dmax = 0;
+    unsigned long long cs = 0, co = 0;
+    for (uint32_t q0 = 0; q0 < static_cast<uint32_t>(b.nq); q0 += 1024) {
+        const uint32_t q = q0 + tid;
+        const bool valid = q < static_cast<uint32_t>(b.nq);
+        unsigned long long nsel = 0, nout = 0;
+        if (valid) {
+            const QueryDesc &d = b.qd[q];
+            const QueryState &st = b.qs[q];
+            nsel = selected ? st.nsel : st.npairs;
+            nout = st.err ? 0ull : (d.k ? min(nsel, static_cast<unsigned long long>(d.k)) : nsel);
+            if (nsel) atomicMax(&s_dmax, d.k ? st.bound : d.theta);
+        }
+        unsigned long long ts, to;
+        const unsigned long long es = block_excl_scan_u64(nsel, s, &ts);
+        const unsigned long long eo = block_excl_scan_u64(nout, s, &to);
+        if (valid) {
+            QueryState &st = b.qs[q];
+            st.nsel = nsel;
+            st.start = cs + es;
+            st.nout = nout;
+            st.off = co + eo;
+        }
+        cs += ts;
+        co += to;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        if (!selected) b.ctl->nsel = min(b.ctl->npairs, b.rec_cap);
+        b.ctl->nout = co;
+        const uint32_t db = max(bitlen32(s_dmax), 1u);
+        b.ctl->sort_db = db;
+        b.ctl->sort_passes = max((qb + db + 2u * vb + 7u) / 8u, 1u);
+    }
 }
 
 // ------------------------------------------------------------------ radix sort
-// Pairs are ordered by the key (dist, u, v).  When dist and the two ids fit in
-// 64 bits the pairs are packed into uint64 keys dist:u:v (vb bits per id) and
-// sorted by 8-bit digits, two launches per digit: a scan of the per-tile
-// digit histogram (which the previous pass accumulated for the tiles its items
-// landed in) and the stable scatter.  Otherwise a three-launch-per-digit sort
-// of the 12-byte records is used.
+// Records are ordered by the key (q, d, u, v): v in bits [0, vb), u in
+// [vb, 2vb), d in [2vb, 2vb + db), q above, sorted by 8-bit digits from the
+// least significant, two launches per digit: a scan of the per-tile digit
+// histogram (which the previous pass accumulated for the tiles its items
+// landed in) and the stable scatter.  db and the number of digits come from
+// the device (k_layout); launches for digits beyond it return at once.
 constexpr uint32_t kSortBlocks = 256;
-constexpr uint32_t kSortPassesMax = 8;
 
 __device__ __forceinline__ void sort_tile(const unsigned long long *nptr, unsigned long long cap,
                                           uint64_t &beg, uint64_t &end, uint64_t &tile) {
@@ -759,6 +1003,16 @@ __device__ __forceinline__ void sort_tile(const unsigned long long *nptr, unsign
     if (tile == 0) tile = 1;
     beg = min(n, blockIdx.x * tile);
     end = min(n, beg + tile);
+}
+
+__device__ __forceinline__ uint32_t rec_digit(const Rec &r, uint32_t bit, uint32_t vb, uint32_t db) {
+    const uint32_t sh = 2u * vb;
+    const uint64_t lo = (static_cast<uint64_t>(static_cast<uint32_t>(r.u)) << vb) | static_cast<uint32_t>(r.v);
+    const uint64_t hi = (static_cast<uint64_t>(r.q) << db) | r.d;
+    if (bit >= sh) return static_cast<uint32_t>(hi >> (bit - sh)) & 255u;
+    uint64_t x = lo >> bit;
+    if (bit + 8u > sh) x |= hi << (sh - bit);
+    return static_cast<uint32_t>(x) & 255u;
 }
 
 // Stable within-block ranking of one 256-item chunk by an 8-bit digit:
@@ -793,10 +1047,25 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *ws
     return off + incl - v;
 }
 
-// Scan of one pass's histogram, laid out [digit][tile]: each row becomes its
-// exclusive prefix over tiles, and tot[d] the row total (one block per digit).
-__global__ __launch_bounds__(256) void k_sort_scan(uint32_t *hist, uint32_t *tot) {
+// Pass-0 digit histogram per tile, laid out [digit][tile].
+__global__ __launch_bounds__(256) void k_sort_hist0(const Rec *in, const CallCtl *ctl, unsigned long long cap,
+                                                    uint32_t vb, uint32_t *hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    uint64_t beg, end, tile;
+    sort_tile(&ctl->nsel, cap, beg, end, tile);
+    const uint32_t db = ctl->sort_db;
+    for (uint64_t i = beg + threadIdx.x; i < end; i += 256) atomicAdd(&h[rec_digit(in[i], 0u, vb, db)], 1u);
+    __syncthreads();
+    hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+}
+
+// Scan of one pass's histogram: each digit row becomes its exclusive prefix
+// over tiles, and tot[d] the row total (one block per digit).
+__global__ __launch_bounds__(256) void k_sort_scan(uint32_t *hist, uint32_t *tot, const CallCtl *ctl, uint32_t pass) {
     __shared__ uint32_t ws[4];
+    if (pass >= ctl->sort_passes) return;
     const uint32_t d = blockIdx.x, tid = threadIdx.x;
     const uint32_t v = hist[d * kSortBlocks + tid];
     const uint32_t e = block_excl_scan_256(v, ws);
@@ -804,199 +1073,62 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t *hist, uint32_t *tot
     if (tid == kSortBlocks - 1) tot[d] = e + v;
 }
 
-// This block's first output position for each digit (thread d computes digit d)
-// from the scanned histogram row and the digit totals.
-__device__ __forceinline__ uint32_t digit_start(const uint32_t *hist, const uint32_t *tot, uint32_t *ws) {
-    const uint32_t tid = threadIdx.x;
-    const uint32_t pre = hist[tid * kSortBlocks + blockIdx.x];
-    return block_excl_scan_256(tot[tid], ws) + pre;
-}
-
-__device__ __forceinline__ uint64_t pack_pair(const rn_pair &p, uint32_t vb) {
-    return (static_cast<uint64_t>(p.dist) << (2u * vb)) |
-           (static_cast<uint64_t>(static_cast<uint32_t>(p.u)) << vb) | static_cast<uint32_t>(p.v);
-}
-
-__global__ __launch_bounds__(256) void k_sort_pack(const rn_pair *in, uint64_t *keys,
-                                                   const unsigned long long *nptr, unsigned long long cap,
-                                                   uint32_t vb, uint32_t *hist0) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    uint64_t beg, end, tile;
-    sort_tile(nptr, cap, beg, end, tile);
-    for (uint64_t i = beg + threadIdx.x; i < end; i += 256) {
-        const uint64_t k = pack_pair(in[i], vb);
-        keys[i] = k;
-        atomicAdd(&h[k & 255u], 1u);
-    }
-    __syncthreads();
-    hist0[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
-}
-
-// One digit pass.  hist: [256][gridDim] counts of this pass's digit per input
-// tile.  hist_next (or null): accumulates the next digit per output tile.
-// out_pairs (final pass only): receives the unpacked pairs, written only when
-// the query succeeded and its result fits.
-__global__ __launch_bounds__(256) void k_sort_pass(const uint64_t *in, uint64_t *out, rn_pair *out_pairs,
-                                                   const unsigned long long *nptr, unsigned long long cap,
-                                                   uint32_t shift, uint32_t vb, const uint32_t *hist,
-                                                   const uint32_t *tot, uint32_t *hist_next, uint32_t next_shift,
-                                                   const QueryCtl *ctl, unsigned long long user_cap,
-                                                   unsigned long long out_limit, int last_tier) {
+// One digit pass.  hist: this pass's scanned [256][tiles] histogram; the
+// pass accumulates the next digit per output tile into hist_next.  The last
+// pass writes each query's first nout records to the caller's buffer at the
+// query's offset, when the records all fit and the output fits user_cap.
+__global__ __launch_bounds__(256) void k_sort_pass(const Rec *in, Rec *out, CallBuffers b, uint32_t pass,
+                                                   uint32_t vb, const uint32_t *hist, const uint32_t *tot,
+                                                   uint32_t *hist_next, rn_pair *user_out,
+                                                   unsigned long long user_cap) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t ws[4];
     const uint32_t tid = threadIdx.x, nb = gridDim.x;
-    if (out_pairs) {
-        const unsigned long long n = *nptr;
-        if (ctl->err != 0 || n > cap || min(n, out_limit) > user_cap) return;
-        if (last_tier >= 0 && ctl->novf[last_tier] != 0) return;
+    const CallCtl *ctl = b.ctl;
+    const uint32_t passes = ctl->sort_passes;
+    if (pass >= passes) return;
+    const bool last = pass + 1 == passes;
+    if (last && (ctl->npairs > b.rec_cap || ctl->nout > user_cap)) return;
+    const uint32_t db = ctl->sort_db;
+    {
+        const uint32_t pre = hist[tid * kSortBlocks + blockIdx.x];
+        base[tid] = block_excl_scan_256(tot[tid], ws) + pre;
     }
-    base[tid] = digit_start(hist, tot, ws);
     uint64_t beg, end, tile;
-    sort_tile(nptr, cap, beg, end, tile);
-    const uint32_t mask = (1u << vb) - 1u;
+    sort_tile(&ctl->nsel, b.rec_cap, beg, end, tile);
+    const uint32_t shift = 8u * pass;
     for (uint64_t c = beg; c < end; c += 256) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
         __syncthreads();
         const uint64_t i = c + tid;
         const bool act = i < end;
-        const uint64_t k = act ? in[i] : 0ull;
-        const uint32_t dg = static_cast<uint32_t>(k >> shift) & 255u;
-        const uint32_t r = chunk_rank(act, dg, wcnt);
+        Rec r{0, 0, 0, 0};
+        if (act) r = in[i];
+        const uint32_t dg = act ? rec_digit(r, shift, vb, db) : 0u;
+        const uint32_t rk = chunk_rank(act, dg, wcnt);
         if (act) {
-            const uint32_t pos = base[dg] + r;
-            if (out_pairs) {
-                rn_pair p;
-                p.dist = static_cast<uint32_t>(k >> (2u * vb));
-                p.u = static_cast<int32_t>(static_cast<uint32_t>(k >> vb) & mask);
-                p.v = static_cast<int32_t>(static_cast<uint32_t>(k) & mask);
-                if (pos < out_limit) out_pairs[pos] = p;
+            const uint32_t pos = base[dg] + rk;
+            if (last) {
+                const QueryState &st = b.qs[r.q];
+                const unsigned long long rel = pos - st.start;
+                if (rel < st.nout) {
+                    rn_pair p;
+                    p.u = r.u;
+                    p.v = r.v;
+                    p.dist = r.d;
+                    user_out[st.off + rel] = p;
+                }
             } else {
-                out[pos] = k;
+                out[pos] = r;
+                atomicAdd(&hist_next[rec_digit(r, shift + 8u, vb, db) * nb + pos / static_cast<uint32_t>(tile)], 1u);
             }
-            if (hist_next)
-                atomicAdd(&hist_next[(static_cast<uint32_t>(k >> next_shift) & 255u) * nb +
-                                     pos / static_cast<uint32_t>(tile)],
-                          1u);
         }
         __syncthreads();
         base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
         __syncthreads();
     }
-}
-
-// ---- generic path: 12-byte records, any key width
-__device__ __forceinline__ uint32_t pair_digit(const rn_pair &p, uint32_t bit, uint32_t vb) {
-    const uint32_t sh = 2u * vb;
-    if (bit >= sh) return (p.dist >> (bit - sh)) & 255u;
-    const uint64_t lo = (static_cast<uint64_t>(static_cast<uint32_t>(p.u)) << vb) |
-                        static_cast<uint32_t>(p.v);
-    uint64_t x = lo >> bit;
-    if (bit + 8u > sh) x |= static_cast<uint64_t>(p.dist) << (sh - bit);
-    return static_cast<uint32_t>(x) & 255u;
-}
-
-__global__ __launch_bounds__(256) void k_radix_hist(const rn_pair *in, const unsigned long long *nptr,
-                                                    unsigned long long cap, uint32_t bit,
-                                                    uint32_t vb, uint32_t *hist) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
-    __syncthreads();
-    uint64_t beg, end, tile;
-    sort_tile(nptr, cap, beg, end, tile);
-    for (uint64_t i = beg + threadIdx.x; i < end; i += 256) atomicAdd(&h[pair_digit(in[i], bit, vb)], 1u);
-    __syncthreads();
-    hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
-}
-
-__global__ __launch_bounds__(256) void k_radix_scatter(const rn_pair *in, rn_pair *out,
-                                                       const unsigned long long *nptr,
-                                                       unsigned long long cap, uint32_t bit,
-                                                       uint32_t vb, const uint32_t *hist,
-                                                       const uint32_t *tot) {
-    __shared__ uint32_t base[256];
-    __shared__ uint32_t wcnt[4][256];
-    __shared__ uint32_t ws[4];
-    const uint32_t tid = threadIdx.x;
-    base[tid] = digit_start(hist, tot, ws);
-    uint64_t beg, end, tile;
-    sort_tile(nptr, cap, beg, end, tile);
-    for (uint64_t c = beg; c < end; c += 256) {
-#pragma unroll
-        for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0;
-        __syncthreads();
-        const uint64_t i = c + tid;
-        const bool act = i < end;
-        rn_pair p{0, 0, 0};
-        if (act) p = in[i];
-        const uint32_t dg = act ? pair_digit(p, bit, vb) : 0u;
-        const uint32_t r = chunk_rank(act, dg, wcnt);
-        if (act) out[base[dg] + r] = p;
-        __syncthreads();
-        base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
-        __syncthreads();
-    }
-}
-
-__global__ void k_copy_out(const rn_pair *src, rn_pair *dst, const unsigned long long *nptr,
-                           const QueryCtl *ctl, unsigned long long user_cap, unsigned long long limit,
-                           unsigned long long out_limit, int last_tier) {
-    const unsigned long long n = *nptr;
-    if (ctl->err != 0 || n > limit || min(n, out_limit) > user_cap) return;
-    if (last_tier >= 0 && ctl->novf[last_tier] != 0) return;
-    const unsigned long long m = min(n, out_limit);
-    for (unsigned long long i = blockIdx.x * static_cast<unsigned long long>(blockDim.x) + threadIdx.x;
-         i < m; i += static_cast<unsigned long long>(gridDim.x) * blockDim.x)
-        dst[i] = src[i];
-}
-
-// ------------------------------------------------------------------ k-closest pairs
-// Seed: every distinct (u, y) with u in R, y in S joined by an arc has
-// dist(u, y) <= the lightest such arc's weight, so the bin edge where k of
-// these weights are reached bounds the k-th smallest distance.  A pair with
-// parallel arcs is counted once, at its first lightest arc.
-__global__ void k_kcp_seed_hist(const int32_t *src, const uint32_t *nsrc, const int32_t *row_ptr,
-                                const ArcRec *arcs, const uint32_t *sbits, uint32_t *seed_hist) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= *nsrc) return;
-    const int32_t u = src[i];
-    const int32_t b = row_ptr[u], e = row_ptr[u + 1];
-    for (int32_t x = b; x < e; ++x) {
-        const ArcRec r = arcs[x];
-        const uint32_t y = static_cast<uint32_t>(r.y);
-        if (!((sbits[y >> 5] >> (y & 31u)) & 1u)) continue;
-        bool first = true;
-        for (int32_t z = b; z < e && first; ++z) {
-            const ArcRec q = arcs[z];
-            if (q.y == r.y && (q.w < r.w || (q.w == r.w && z < x))) first = false;
-        }
-        if (first) atomicAdd(&seed_hist[dist_bin(r.w)], 1u);
-    }
-}
-
-__global__ __launch_bounds__(64) void k_kcp_seed_bound(const uint32_t *seed_hist, uint32_t k, QueryCtl *ctl) {
-    const uint32_t b = wave_bound_from_hist(seed_hist, k);
-    if (threadIdx.x == 0) ctl->theta = b;
-}
-
-// Keep the emitted pairs within the final bound (order is restored by the sort).
-__global__ void k_kcp_filter(const rn_pair *pairs, unsigned long long cap, rn_pair *kept, QueryCtl *ctl) {
-    const unsigned long long n = min(ctl->npairs, cap);
-    const uint32_t bound = ctl->theta;
-    for (unsigned long long i = blockIdx.x * static_cast<unsigned long long>(blockDim.x) + threadIdx.x;
-         i < n; i += static_cast<unsigned long long>(gridDim.x) * blockDim.x) {
-        const rn_pair p = pairs[i];
-        if (p.dist <= bound) kept[atomicAdd(&ctl->nsel, 1ull)] = p;
-    }
-}
-
-inline uint32_t bitlen(uint64_t x) {
-    uint32_t b = 0;
-    while (x) { ++b; x >>= 1; }
-    return b;
 }
 
 template <int HB>
@@ -1036,28 +1168,20 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
     return hipGetLastError();
 }
 
-size_t stage_scratch_words(int32_t V) {
-    const size_t nwords = (static_cast<size_t>(V) + 31) / 32;
-    return (nwords + 1023) / 1024 + 1;
-}
+size_t stage_scratch_words(size_t rwords) { return (rwords + 1023) / 1024 + 1; }
 
-hipError_t launch_stage(const int32_t *R, int32_t nR, const int32_t *S, int32_t nS, int32_t V,
-                        const int32_t *rank, const int32_t *order, uint32_t *rbits,
-                        uint32_t *sbits, int32_t *src, QueryCtl *ctl, uint32_t *scratch,
-                        hipStream_t s) {
-    const int64_t n = static_cast<int64_t>(nR) + nS;
-    hipLaunchKernelGGL(k_mark, dim3(static_cast<uint32_t>((n + 255) / 256)), dim3(256), 0, s, R, nR, S,
-                       nS, V, rank, rbits, sbits, ctl);
-    hipLaunchKernelGGL(k_overlap, dim3(static_cast<uint32_t>((nR + 255) / 256)), dim3(256), 0, s, R, nR,
-                       V, sbits, ctl);
-    const uint32_t nwords = static_cast<uint32_t>((static_cast<int64_t>(V) + 31) / 32);
-    const uint32_t nblk = (nwords + 1023u) / 1024u;
-    hipLaunchKernelGGL(k_rank_count, dim3(nblk), dim3(1024), 0, s, rbits, nwords, scratch);
-    hipLaunchKernelGGL(k_rank_emit, dim3(nblk), dim3(1024), 0, s, rbits, nwords, scratch, order, src, ctl);
+hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, const int32_t *rank,
+                        const int32_t *order, hipStream_t s) {
+    const uint32_t eblk = static_cast<uint32_t>((max_elems + 255) / 256);
+    hipLaunchKernelGGL(k_mark, dim3(eblk), dim3(256), 0, s, b, rank);
+    hipLaunchKernelGGL(k_overlap, dim3(eblk), dim3(256), 0, s, b);
+    const uint32_t nblk = (b.rwords + 1023u) / 1024u;
+    hipLaunchKernelGGL(k_rank_count, dim3(nblk), dim3(1024), 0, s, b.rbits, b.rwords, b.stage_scratch);
+    hipLaunchKernelGGL(k_rank_emit, dim3(nblk), dim3(1024), 0, s, b, b.stage_scratch, order);
     return hipGetLastError();
 }
 
-int join_tier_supported(int hash_log2) { return hash_log2 >= 8 && hash_log2 <= 14; }
+int join_tier_supported(int hash_log2) { return hash_log2 >= kMinHB && hash_log2 <= kMaxHB; }
 
 hipError_t launch_join(const JoinArgs &a, int hash_log2, uint32_t max_sources, hipStream_t s) {
     switch (hash_log2) {
@@ -1072,78 +1196,50 @@ hipError_t launch_join(const JoinArgs &a, int hash_log2, uint32_t max_sources, h
     }
 }
 
-hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslots, int32_t V,
+hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslots, int32_t Vmax,
                               uint32_t max_sources, hipStream_t s) {
     uint32_t grid = nslots < max_sources ? nslots : max_sources;
     if (grid == 0) grid = 1;
-    hipLaunchKernelGGL(k_join_global, dim3(grid), dim3(256), 0, s, a, slots, global_slot_words(V), V);
+    hipLaunchKernelGGL(k_join_global, dim3(grid), dim3(256), 0, s, a, slots, global_slot_words(Vmax), Vmax);
     return hipGetLastError();
 }
 
-// per pass: a [256 digits][kSortBlocks tiles] histogram, then 256 digit totals
+hipError_t launch_kcp_seed(const JoinArgs &a, const CallBuffers &b, uint32_t max_sources, hipStream_t s) {
+    hipLaunchKernelGGL(k_kcp_seed_hist, dim3((max_sources + 255) / 256), dim3(256), 0, s, a);
+    hipLaunchKernelGGL(k_kcp_seed_bound, dim3(static_cast<uint32_t>(b.nq)), dim3(64), 0, s, b.qd, b.qs, b.hists);
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const CallBuffers &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_select, dim3(1024), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_layout(const CallBuffers &b, int selected, uint32_t qb, uint32_t vb, hipStream_t s) {
+    hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, b, selected, qb, vb);
+    return hipGetLastError();
+}
+
+// per pass: a [256 digits][kSortBlocks tiles] histogram, then 256 digit totals per pass
 size_t sort_hist_words() { return static_cast<size_t>(kSortPassesMax + 1) * 256u * (kSortBlocks + 1); }
 
-hipError_t launch_sort_to_out(rn_pair *pairs, rn_pair *scratch, const unsigned long long *n,
-                              unsigned long long cap, uint32_t max_dist, int32_t V, uint32_t *hist,
-                              rn_pair *out, unsigned long long user_cap, unsigned long long out_limit,
-                              const QueryCtl *ctl, int last_tier, hipStream_t s) {
-    const uint32_t vb = V > 1 ? bitlen(static_cast<uint64_t>(V - 1)) : 1u;
-    const uint32_t bits = 2u * vb + bitlen(max_dist);
-    const uint32_t passes = (bits + 7u) / 8u;
-    if (bits <= 64 && cap < (1ull << 31)) {
-        uint64_t *ka = reinterpret_cast<uint64_t *>(scratch);
-        uint64_t *kb = reinterpret_cast<uint64_t *>(pairs);   // records are packed into ka first
-        const size_t hw = 256u * kSortBlocks;
-        uint32_t *tot = hist + (kSortPassesMax + 1) * hw;
-        hipLaunchKernelGGL(k_sort_pack, dim3(kSortBlocks), dim3(256), 0, s, pairs, ka, n, cap, vb, hist);
-        uint64_t *in = ka, *o = kb;
-        for (uint32_t p = 0; p < passes; ++p) {
-            const bool last = p + 1 == passes;
-            hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist + p * hw, tot + p * 256u);
-            hipLaunchKernelGGL(k_sort_pass, dim3(kSortBlocks), dim3(256), 0, s, in, o, last ? out : nullptr,
-                               n, cap, 8u * p, vb, hist + p * hw, tot + p * 256u,
-                               last ? nullptr : hist + (p + 1) * hw, 8u * (p + 1), ctl, user_cap, out_limit,
-                               last_tier);
-            uint64_t *t = in;
-            in = o;
-            o = t;
-        }
-        return hipGetLastError();
-    }
-    rn_pair *in = pairs, *o = scratch;
-    uint32_t *tot = hist + 256u * kSortBlocks;
-    for (uint32_t bit = 0; bit < bits; bit += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3(kSortBlocks), dim3(256), 0, s, in, n, cap, bit, vb, hist);
-        hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist, tot);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(kSortBlocks), dim3(256), 0, s, in, o, n, cap, bit, vb,
-                           hist, tot);
-        rn_pair *t = in;
+hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_passes, uint32_t vb,
+                           rn_pair *out, unsigned long long user_cap, hipStream_t s) {
+    if (max_passes > kSortPassesMax) return hipErrorInvalidValue;
+    const size_t hw = 256u * kSortBlocks;
+    uint32_t *hist = b.sort_hist;
+    uint32_t *tot = hist + (kSortPassesMax + 1) * hw;
+    Rec *in = selected ? b.recs[1] : b.recs[0];
+    Rec *o = selected ? b.recs[0] : b.recs[1];
+    hipLaunchKernelGGL(k_sort_hist0, dim3(kSortBlocks), dim3(256), 0, s, in, b.ctl, b.rec_cap, vb, hist);
+    for (uint32_t p = 0; p < max_passes; ++p) {
+        hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist + p * hw, tot + p * 256u, b.ctl, p);
+        hipLaunchKernelGGL(k_sort_pass, dim3(kSortBlocks), dim3(256), 0, s, in, o, b, p, vb, hist + p * hw,
+                           tot + p * 256u, hist + (p + 1) * hw, out, user_cap);
+        Rec *t = in;
         in = o;
         o = t;
     }
-    return launch_copy_out(in, out, n, ctl, user_cap, cap, out_limit, last_tier, s);
-}
-
-hipError_t launch_copy_out(const rn_pair *src, rn_pair *dst, const unsigned long long *n,
-                           const QueryCtl *ctl, unsigned long long user_cap, unsigned long long limit,
-                           unsigned long long out_limit, int last_tier, hipStream_t s) {
-    hipLaunchKernelGGL(k_copy_out, dim3(1024), dim3(256), 0, s, src, dst, n, ctl, user_cap, limit, out_limit,
-                       last_tier);
-    return hipGetLastError();
-}
-
-hipError_t launch_kcp_seed(const int32_t *src, const uint32_t *nsrc, uint32_t max_sources,
-                           const int32_t *row_ptr, const ArcRec *arcs, const uint32_t *sbits,
-                           uint32_t *seed_hist, uint32_t k, QueryCtl *ctl, hipStream_t s) {
-    hipLaunchKernelGGL(k_kcp_seed_hist, dim3((max_sources + 255) / 256), dim3(256), 0, s, src, nsrc, row_ptr,
-                       arcs, sbits, seed_hist);
-    hipLaunchKernelGGL(k_kcp_seed_bound, dim3(1), dim3(64), 0, s, seed_hist, k, ctl);
-    return hipGetLastError();
-}
-
-hipError_t launch_kcp_filter(const rn_pair *pairs, unsigned long long cap, rn_pair *kept, QueryCtl *ctl,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_kcp_filter, dim3(1024), dim3(256), 0, s, pairs, cap, kept, ctl);
     return hipGetLastError();
 }
 

@@ -24,13 +24,24 @@ EXPORTS = (
     "rn_partition_host", "rn_partition", "rn_dist_join", "rn_kcp_join",
     "rn_set_tuning", "rn_get_tuning", "rn_set_profiling", "rn_last_stats",
     "rn_last_error", "rn_version",
+    "rn_graph_load_many", "rn_graph_count", "rn_graph_size", "rn_join_batch", "rn_autotune",
+    "rn_plan_create", "rn_plan_run", "rn_plan_free",
 )
+RN_DELTA_DEFAULT = 0xFFFFFFFF
+MAX_DIST = 0xFFFFFFFE
 
 
 class RnError(RuntimeError):
     def __init__(self, status: int, msg: str, needed: int | None = None):
         super().__init__(f"rn status {status}: {msg}")
         self.status, self.needed = status, needed
+
+
+class Query(C.Structure):
+    """struct rn_query (include/rn.h)."""
+    _fields_ = [("R", C.c_void_p), ("S", C.c_void_p), ("nR", C.c_int32), ("nS", C.c_int32),
+                ("graph", C.c_int32), ("k", C.c_int32), ("theta", C.c_uint32), ("delta", C.c_uint32),
+                ("hash_log2", C.c_int32), ("reserved", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -71,11 +82,23 @@ def load_library(path: str = LIB_PATH):
     lib.rn_get_tuning.argtypes = [vp, u32p, i32p]
     lib.rn_set_profiling.argtypes = [vp, C.c_int32]
     lib.rn_last_stats.argtypes = [vp, C.POINTER(Stats)]
+    pp = C.POINTER(vp)
+    lib.rn_graph_load_many.argtypes = [C.c_int32, i32p, i64p, pp, pp, pp, C.POINTER(vp)]
+    lib.rn_graph_count.argtypes = [vp]
+    lib.rn_graph_size.argtypes = [vp, C.c_int32, i32p, i64p]
+    qp = C.POINTER(Query)
+    lib.rn_join_batch.argtypes = [vp, qp, C.c_int32, vp, C.c_int64, i64p, i32p, vp]
+    lib.rn_autotune.argtypes = [vp, qp, C.c_int32, C.c_int32, vp]
+    lib.rn_plan_create.argtypes = [vp, qp, C.c_int32, vp, C.c_int64, vp, C.POINTER(vp)]
+    lib.rn_plan_run.argtypes = [vp, i64p, i32p, vp]
+    lib.rn_plan_free.argtypes = [vp]
+    lib.rn_plan_free.restype = None
     lib.rn_last_error.restype = C.c_char_p
     lib.rn_version.restype = C.c_char_p
     for name in ("rn_graph_load", "rn_graph_num_vertices", "rn_partition_host", "rn_partition",
                  "rn_dist_join", "rn_kcp_join", "rn_set_tuning", "rn_get_tuning",
-                 "rn_set_profiling", "rn_last_stats"):
+                 "rn_set_profiling", "rn_last_stats", "rn_graph_load_many", "rn_graph_count",
+                 "rn_graph_size", "rn_join_batch", "rn_autotune", "rn_plan_create", "rn_plan_run"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -114,23 +137,45 @@ def pairs_to_numpy(t) -> np.ndarray:
 
 
 class RoadNetwork:
-    """A graph resident on the current HIP device (an rn_graph handle)."""
+    """Graphs resident on the current HIP device (an rn_graph handle).
+
+    A handle holds one graph (``from_graph``) or several (``from_graphs``);
+    the single-query calls use graph 0, ``join_batch`` any of them."""
 
     def __init__(self, row_ptr, col, w):
+        self._load([(row_ptr, col, w)])
+
+    def _load(self, csrs):
         lib = load_library()
-        rp, rpp = _host(row_ptr, np.int32)
-        cl, clp = _host(col, np.int32)
-        ww, wp = _host(w, np.uint32)
+        keep = [(_host(rp, np.int32)[0], _host(cl, np.int32)[0], _host(ww, np.uint32)[0]) for rp, cl, ww in csrs]
+        n = len(keep)
+        Vs = np.array([k[0].shape[0] - 1 for k in keep], dtype=np.int32)
+        As = np.array([k[1].shape[0] for k in keep], dtype=np.int64)
+        ptrs = [(C.c_void_p * n)(*[k[j].ctypes.data for k in keep]) for j in range(3)]
         h = C.c_void_p()
-        _check(lib.rn_graph_load(rp.shape[0] - 1, cl.shape[0], rpp, clp, wp, C.byref(h)))
+        self._h = None
+        _check(lib.rn_graph_load_many(n, Vs.ctypes.data_as(C.POINTER(C.c_int32)),
+                                      As.ctypes.data_as(C.POINTER(C.c_int64)), *ptrs, C.byref(h)))
         self._h = h
-        self.V = rp.shape[0] - 1
-        self.A = cl.shape[0]
+        self.sizes = [(int(v), int(a)) for v, a in zip(Vs, As)]
+        self.V = int(Vs.sum())
+        self.A = int(As.sum())
         self._out = None
+        self._bout = None
 
     @classmethod
     def from_graph(cls, g) -> "RoadNetwork":
         return cls(g.row_ptr, g.col, g.w)
+
+    @classmethod
+    def from_graphs(cls, graphs) -> "RoadNetwork":
+        self = cls.__new__(cls)
+        self._load([(g.row_ptr, g.col, g.w) for g in graphs])
+        return self
+
+    @property
+    def num_graphs(self) -> int:
+        return int(load_library().rn_graph_count(self._h))
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -211,3 +256,125 @@ class RoadNetwork:
     def kcp_join(self, R, S, k: int, stream=None):
         """k closest pairs on the device: int32 tensor [n, 3], n = min(k, reachable pairs)."""
         return self._call(load_library().rn_kcp_join, R, S, C.c_int32(int(k)), stream)
+
+    # -------------------------------------------------------------- batches
+    def make_queries(self, specs, keep: list | None = None):
+        """rn_query array from dicts {R, S, theta=MAX_DIST, k=0, graph=0, delta=None, hash_log2=0}.
+
+        R and S become int32 device tensors, appended to ``keep`` (they must stay
+        alive while the queries are used)."""
+        arr = (Query * len(specs))()
+        keep = [] if keep is None else keep
+        for i, sp in enumerate(specs):
+            R, S = self._dev_ids(sp["R"]), self._dev_ids(sp["S"])
+            keep += [R, S]
+            d = sp.get("delta")
+            arr[i] = Query(R.data_ptr(), S.data_ptr(), R.numel(), S.numel(), int(sp.get("graph", 0)),
+                           int(sp.get("k", 0)), int(sp.get("theta", MAX_DIST)),
+                           RN_DELTA_DEFAULT if d is None else int(d), int(sp.get("hash_log2", 0)), 0)
+        return arr, keep
+
+    def _bout_buffer(self, n: int):
+        import torch
+        if self._bout is None or self._bout.shape[0] < n:
+            self._bout = torch.empty((max(n, 1024), 3), dtype=torch.int32, device="cuda")
+        return self._bout
+
+    def join_batch(self, queries, stream=None, check: bool = True):
+        """Run a batch: returns (pairs tensor [total, 3], offsets int64[nq+1], status int32[nq]).
+
+        ``queries``: an rn_query array (``make_queries``) or a list of dicts.
+        Query i's pairs are rows offsets[i]..offsets[i+1].  With ``check`` an
+        RN_ERR_ARG from the device raises; otherwise status reports it."""
+        import torch
+        keep = []
+        if not isinstance(queries, C.Array):
+            queries, keep = self.make_queries(queries)
+        nq = len(queries)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        sptr = C.c_void_p(stream.cuda_stream)
+        off = np.zeros(nq + 1, dtype=np.int64)
+        status = np.zeros(nq, dtype=np.int32)
+        lib = load_library()
+        out = self._bout_buffer(0)
+
+        def call(o):
+            return lib.rn_join_batch(self._h, queries, nq, C.c_void_p(o.data_ptr()), o.shape[0],
+                                     off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                     status.ctypes.data_as(C.POINTER(C.c_int32)), sptr)
+        st = call(out)
+        if st == RN_ERR_CAPACITY and off[nq] > out.shape[0]:
+            out = self._bout_buffer(int(off[nq]))
+            st = call(out)
+        if st != RN_OK and not (st == RN_ERR_ARG and not check and status.any()):
+            _check(st, int(off[nq]))
+        del keep
+        return out[: int(off[nq])], off, status
+
+    def autotune(self, queries, sample: int = 256, stream=None):
+        """Pick delta / hash_log2 per query in place (rn_autotune)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(load_library().rn_autotune(self._h, queries, len(queries), int(sample),
+                                          C.c_void_p(stream.cuda_stream)))
+        return queries
+
+    def plan(self, queries, cap: int | None = None, stream=None) -> "Plan":
+        """Capture a batch into a HIP graph (see Plan)."""
+        return Plan(self, queries, cap, stream)
+
+
+class Plan:
+    """A batch captured once into a HIP graph and replayed by ``run``.
+
+    The plan keeps the query array (and the device R, S tensors it points to)
+    and an output buffer of ``cap`` pairs (the batch's size when None)."""
+
+    def __init__(self, net: RoadNetwork, queries, cap: int | None = None, stream=None):
+        import torch
+        self.net, self.queries = net, queries
+        if cap is None:
+            _, off, _ = net.join_batch(queries, stream=stream, check=False)
+            cap = int(off[-1]) + 1024
+        self.out = torch.empty((max(int(cap), 1), 3), dtype=torch.int32, device="cuda")
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        h = C.c_void_p()
+        self._h = None
+        _check(load_library().rn_plan_create(net._h, queries, len(queries), C.c_void_p(self.out.data_ptr()),
+                                             int(cap), C.c_void_p(stream.cuda_stream), C.byref(h)))
+        self._h = h
+
+    def run(self, stream=None, check: bool = True):
+        """Replay: returns (pairs tensor view, offsets, status) as join_batch."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        nq = len(self.queries)
+        off = np.zeros(nq + 1, dtype=np.int64)
+        status = np.zeros(nq, dtype=np.int32)
+        st = load_library().rn_plan_run(self._h, off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                        status.ctypes.data_as(C.POINTER(C.c_int32)),
+                                        C.c_void_p(stream.cuda_stream))
+        if st != RN_OK and not (st == RN_ERR_ARG and not check and status.any()):
+            _check(st, int(off[nq]))
+        return self.out[: int(off[nq])], off, status
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().rn_plan_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def split_batch(out, off) -> list[np.ndarray]:
+    """Pairs tensor + offsets -> one structured numpy array per query."""
+    a = pairs_to_numpy(out)
+    return [a[int(off[i]):int(off[i + 1])] for i in range(len(off) - 1)]

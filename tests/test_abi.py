@@ -83,3 +83,41 @@ def test_partition_host_argument_checks(rn, rg):
 
 def test_version(rn):
     assert rn.load_library().rn_version().startswith(b"rn ")
+
+
+def test_batch_calls_reject_bad_arguments_before_device(rn):
+    lib = rn.load_library()
+    off = np.ones(3, dtype=np.int64)
+    i64 = C.POINTER(C.c_int64)
+    q = (rn.Query * 2)()
+    st = lib.rn_join_batch(None, q, 2, None, 0, off.ctypes.data_as(i64), None, None)
+    assert st == rn.RN_ERR_ARG
+    assert lib.rn_join_batch(None, q, 2, None, 0, None, None, None) == rn.RN_ERR_ARG
+    assert lib.rn_autotune(None, q, 2, 64, None) == rn.RN_ERR_ARG
+    h = C.c_void_p(1)
+    assert lib.rn_plan_create(None, q, 2, None, 0, None, C.byref(h)) == rn.RN_ERR_ARG and not h.value
+    assert lib.rn_plan_run(None, off.ctypes.data_as(i64), None, None) == rn.RN_ERR_ARG
+    lib.rn_plan_free(None)
+    assert lib.rn_graph_count(None) == 0
+    assert lib.rn_graph_size(None, 0, None, None) == rn.RN_ERR_ARG
+
+
+def test_graph_load_many_names_the_bad_graph(rn, rg):
+    lib = rn.load_library()
+    good = rg.road_graph(8, 0)
+    bad_col = good.col.copy()
+    bad_col[0] = good.V + 3
+    graphs = [(good.row_ptr, good.col, good.w), (good.row_ptr, bad_col, good.w)]
+    V = np.array([good.V, good.V], dtype=np.int32)
+    A = np.array([good.A, good.A], dtype=np.int64)
+    ptrs = [(C.c_void_p * 2)(*[np.ascontiguousarray(x[j]).ctypes.data for x in graphs]) for j in range(3)]
+    h = C.c_void_p()
+    st = lib.rn_graph_load_many(2, V.ctypes.data_as(C.POINTER(C.c_int32)), A.ctypes.data_as(C.POINTER(C.c_int64)),
+                                *ptrs, C.byref(h))
+    assert st == rn.RN_ERR_ARG and not h.value
+    assert lib.rn_last_error().startswith(b"graph 1:")
+
+
+def test_query_struct_layout(rn):
+    assert C.sizeof(rn.Query) == 48
+    assert rn.Query.nR.offset == 16 and rn.Query.hash_log2.offset == 40
