@@ -127,6 +127,98 @@ def kcp_leg(torch, rn, steps):
             "candidates": int(st["pairs"]), "arcs_scanned": int(st["arcs"])}
 
 
+def batch_leg(torch, rn, steps):
+    """128 independent graph + join instances: one batched call against the
+    same queries through the plain single-query calls, one after the other."""
+    from paper_1607_07696_amd import roadgen
+    MAX = rn.MAX_DIST
+    t0 = time.perf_counter()
+    inst = roadgen.batched_instances(128)
+    log(f"batch: 128 instances generated in {time.perf_counter() - t0:.1f} s")
+    net = rn.RoadNetwork.from_graphs([x.graph for x in inst])
+    specs = [{"R": x.R, "S": x.S, "graph": i, "k": x.k, "theta": x.theta if x.k == 0 else MAX}
+             for i, x in enumerate(inst)]
+    q, keep = net.make_queries(specs)
+    out, off, _ = net.join_batch(q)
+    a = rn.pairs_to_numpy(out)
+    total_pairs = int(off[-1])
+    # work: arcs out of every vertex within theta (theta-joins) or within the
+    # k-th distance (k-closest pairs) of each source
+    wspecs = []
+    for i, x in enumerate(inst):
+        sp = dict(specs[i])
+        if x.k:
+            seg = a[off[i]:off[i + 1]]
+            sp["k"], sp["theta"] = 0, int(seg["dist"][-1]) if len(seg) else 0
+        wspecs.append(sp)
+    net.set_profiling(times=True, work=True)
+    net.join_batch(wspecs)
+    arcs = int(net.stats()["arcs"])
+    net.set_profiling(times=False, work=False)
+
+    def timed(fn, n):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        lat = []
+        for _ in range(n):
+            t = time.perf_counter()
+            fn()
+            lat.append(time.perf_counter() - t)
+        return float(np.median(lat)) * 1e3
+
+    res = {"workload": ("128 independent instances (seeds 1000..1127): road graphs of side log-uniform "
+                        "in [32, 512], |R|, |S| log-uniform in [16, 4096], theta uniform in [500, 5000]; "
+                        "odd instances ask for the k closest pairs, k log-uniform in [1, 1024]"),
+           "vertices": int(net.V), "arcs_resident": int(net.A), "pairs": total_pairs, "work_arcs": arcs}
+    res["eager_ms"] = round(timed(lambda: net.join_batch(q), steps), 4)
+    plan = net.plan(q)
+    res["plan_ms"] = round(timed(plan.run, steps), 4)
+    plan.close()
+    t0 = time.perf_counter()
+    net.autotune(q, sample=256)
+    res["autotune_s"] = round(time.perf_counter() - t0, 2)
+    plan = net.plan(q)
+    res["plan_tuned_ms"] = round(timed(plan.run, steps), 4)
+    plan.close()
+    best = min(res["plan_ms"], res["plan_tuned_ms"])
+    # the plain path: one handle per graph, single-query calls in sequence
+    nets = [rn.RoadNetwork.from_graph(x.graph) for x in inst]
+    dev = [(torch.as_tensor(x.R, device="cuda"), torch.as_tensor(x.S, device="cuda")) for x in inst]
+
+    def plain_all(lat=None):
+        for n, x, (Rd, Sd) in zip(nets, inst, dev):
+            t = time.perf_counter()
+            if x.k:
+                n.kcp_join(Rd, Sd, x.k)
+            else:
+                n.dist_join(Rd, Sd, x.theta)
+            if lat is not None:
+                lat.append(time.perf_counter() - t)
+    plain_all()
+    torch.cuda.synchronize()
+    tot, per = [], []
+    for _ in range(max(3, steps // 4)):
+        t = time.perf_counter()
+        plain_all(per)
+        tot.append(time.perf_counter() - t)
+    plain_ms = float(np.median(tot)) * 1e3
+    for n in nets:
+        n.close()
+    res["plain_total_ms"] = round(plain_ms, 4)
+    res["plain_call_ms"] = {"p50": round(float(np.percentile(per, 50)) * 1e3, 4),
+                            "p99": round(float(np.percentile(per, 99)) * 1e3, 4)}
+    # all 128 queries arrive at once: a query's completion time is the batch's
+    # time (batched) or the sum of the calls before and including it (plain)
+    done = np.cumsum(per[-len(inst):]) * 1e3
+    res["completion_p99_ms"] = {"batched": round(best, 4), "plain": round(float(np.percentile(done, 99)), 4)}
+    res["gteps"] = {"batched": round(arcs / (best / 1e3) / 1e9, 3),
+                    "plain": round(arcs / (plain_ms / 1e3) / 1e9, 3)}
+    res["speedup"] = round(plain_ms / best, 2)
+    net.close()
+    return res
+
+
 def cpu_baseline(g, R, S, theta, arcs_total, budget_s):
     from oracle import oracle
     times = []
@@ -157,6 +249,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=8.0, help="seconds of oracle timing")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kcp", action="store_true", help="skip the k-closest-pairs leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run one 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -256,6 +349,9 @@ def main():
     if not args.no_kcp:
         log("k-closest-pairs leg")
         result["kcp"] = kcp_leg(torch, rn, max(5, args.steps))
+    if not args.no_batch:
+        log("batched-instances leg")
+        result["batch"] = batch_leg(torch, rn, max(10, args.steps))
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(g, R, S, theta, arcs, args.cpu_budget)

@@ -296,7 +296,7 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         d.delta = x.delta == RN_DELTA_DEFAULT ? g->delta : x.delta;
         d.sbits = static_cast<uint32_t>(sw);
         d.rbits = static_cast<uint32_t>(rw);
-        d.hist = x.k ? nkcp * 2 * kDistBins : 0;
+        d.hist = x.k ? nkcp * kHistWords : 0;
         nkcp += x.k ? 1 : 0;
         p.rbase[s] = static_cast<uint32_t>(rw);
         p.ebase[s + 1] = p.ebase[s] + static_cast<unsigned long long>(x.nS) + static_cast<unsigned long long>(x.nR);
@@ -323,7 +323,7 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
     p.off_sbits = round_up(p.off_qs + static_cast<size_t>(nq) * (sizeof(QueryState) / 4), 64);
     p.off_rbits = round_up(p.off_sbits + sw, 64);
     p.off_hists = round_up(p.off_rbits + rw, 64);
-    p.off_sort = round_up(p.off_hists + static_cast<size_t>(nkcp) * 2 * kDistBins, 64);
+    p.off_sort = round_up(p.off_hists + static_cast<size_t>(nkcp) * kHistWords, 64);
     p.block_words = p.off_sort + sort_hist_words();
     // the pass-0 histogram is written whole and the digit totals before use;
     // the histograms later passes accumulate start at zero
@@ -522,6 +522,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.ovfq = b.listq[li];
         t.novf = &b.ctl->nlist[li];
         t.first_tier = 1;
+        t.tier = 0;
         RN_HIP(launch_join(t, gr.hb, static_cast<uint32_t>(gr.sources), st), "launching the relaxation");
         if (gi > 0) RN_HIP(hipEventRecord(ws.join[gi - 1], st), "joining streams");
     }
@@ -541,6 +542,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.ovfq = b.listq[li + 1];
         t.novf = &b.ctl->nlist[li + 1];
         t.first_tier = 0;
+        t.tier = 1 + li;
         RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, maxs, s), "launching the relaxation");
     }
     {
@@ -550,6 +552,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.srcq = b.listq[2];
         t.sbeg = nullptr;
         t.send = &b.ctl->nlist[2];
+        t.tier = 3;
         RN_HIP(launch_join_global(t, g->d_gslots, g->n_gslots, g->Vmax, maxs, s), "launching the global relaxation");
     }
     record(g, ws, timed, EV_RELAXED, s);

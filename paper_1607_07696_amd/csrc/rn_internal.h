@@ -35,6 +35,18 @@ inline int retry_list_after(int hb) { return hb < kRetryHB1 ? 0 : (hb < kMaxHB ?
 // holding the k-th count bounds the k-th smallest distance from above.
 constexpr uint32_t kDistBins = 512;   // 464 used
 
+// Histogram region of one k-closest-pairs query (words): the weights of direct
+// R-S arcs | the distances of emitted pairs | for each search tier, the first
+// tentative distance of every (source, S member) pair its searches discovered |
+// the four discovery counts.  Each histogram counts a pair at most once, and
+// every value counted is the length of a real path, so each one alone bounds
+// the k-th smallest distance from above once it holds k counts.
+constexpr uint32_t kHistSeed = 0;
+constexpr uint32_t kHistEmit = kDistBins;
+constexpr uint32_t kHistProbe = 2 * kDistBins;      // + tier * kDistBins
+constexpr uint32_t kHistCount = 6 * kDistBins;      // + tier
+constexpr uint32_t kHistWords = 6 * kDistBins + 64;
+
 // One query of a call as the kernels read it (uploaded per call).  Ids in R
 // and S are local to the query's graph; the graph's vertices are the global
 // ids voff .. voff + V - 1 of the resident CSR.
@@ -48,7 +60,7 @@ struct QueryDesc {
     uint32_t delta;             // bucket width (0 = one bucket)
     uint32_t sbits;             // word offset of the query's S bitmap in the S-bitmap pool
     uint32_t rbits;             // word offset of the query's rank bitmap in the rank-bitmap pool
-    uint32_t hist;              // k > 0: word offset of its two histograms in the histogram pool
+    uint32_t hist;              // k > 0: word offset of its histogram region in the histogram pool
     uint32_t pad[2];
 };
 static_assert(sizeof(QueryDesc) == 64, "QueryDesc is 64 bytes");
@@ -123,6 +135,7 @@ struct JoinArgs {
     uint32_t *ovfq;
     uint32_t *novf;
     int32_t first_tier;         // 1: count re-queued searches in ctl->nretry
+    int32_t tier;               // 0 first table, 1 and 2 the re-run tables, 3 the global tier
     int32_t count_work;         // 1: accumulate ctl->arcs / ctl->settled
 };
 

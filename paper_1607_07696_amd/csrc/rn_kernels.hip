@@ -179,7 +179,9 @@ struct WaveState {
     uint32_t np;    // entries in the pending list
     uint32_t nins;  // table entries in use
     uint32_t imin;  // per-lane min of the distances improved this phase
+    uint32_t pnew;  // k-closest pairs: discoveries counted this phase, not yet published
     bool ovf;       // the search outgrew this tier
+    bool probing;   // k-closest pairs: count discoveries of S members
 };
 
 // What a search needs to know about its query (read once per source; uniform
@@ -190,10 +192,10 @@ struct SrcCtx {
     uint32_t delta;
     int32_t voff;                   // first global id of the query's graph
     uint32_t q;
+    uint32_t tier;
     const uint32_t *sbits;          // the query's S bitmap (local ids)
-    uint32_t *cand_hist;            // k > 0: emitted-distance histogram
-    uint32_t *bound;                // k > 0: the shared, shrinking bound
-    unsigned long long *npairs;     // records the query emitted so far
+    uint32_t *hist;                 // k > 0: the query's histogram region (else null)
+    QueryState *qs;                 // the query's state
 };
 
 __device__ __forceinline__ SrcCtx load_ctx(const JoinArgs &a, uint32_t q) {
@@ -204,22 +206,47 @@ __device__ __forceinline__ SrcCtx load_ctx(const JoinArgs &a, uint32_t q) {
     c.delta = d.delta;
     c.voff = d.voff;
     c.q = q;
+    c.tier = static_cast<uint32_t>(a.tier);
     c.sbits = a.sbits + d.sbits;
-    c.cand_hist = a.hists + d.hist + kDistBins;
-    c.bound = &a.qs[q].bound;
-    c.npairs = &a.qs[q].npairs;
+    c.hist = d.k ? a.hists + d.hist : nullptr;
+    c.qs = a.qs + q;
     return c;
 }
 
+__device__ __forceinline__ uint32_t *probe_hist(const SrcCtx &c) { return c.hist + kHistProbe + c.tier * kDistBins; }
+__device__ __forceinline__ uint32_t *probe_count(const SrcCtx &c) { return c.hist + kHistCount + c.tier; }
+
 __device__ __forceinline__ uint32_t current_bound(const SrcCtx &c) {
     if (c.k == 0) return c.theta;
-    const uint32_t t = __hip_atomic_load(c.bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t t = __hip_atomic_load(&c.qs->bound, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return min(t, c.theta);
 }
 
 __device__ __forceinline__ bool in_s(const SrcCtx &c, uint32_t y) {
     const uint32_t yl = y - static_cast<uint32_t>(c.voff);
     return (c.sbits[yl >> 5] >> (yl & 31u)) & 1u;
+}
+
+// Discoveries a query's searches count per tier before they stop: enough for
+// a close bound, few enough to keep the histogram atomics cheap.
+__device__ __forceinline__ uint32_t probe_cap(const SrcCtx &c) { return max(4u * c.k, 256u); }
+
+// k-closest pairs, at the start of a phase: publish the discoveries of the
+// last phase, lower the shared bound from this tier's discovery histogram
+// once it holds k pairs (and again each time it has grown by an eighth), and
+// decide whether to keep counting.  Whole wave; the result is wave-uniform.
+__device__ __forceinline__ void probe_phase(const SrcCtx &c, uint32_t &pnew, bool &probing, uint32_t &seen) {
+    uint32_t *cnt = probe_count(c);
+    uint32_t n = 0;
+    if (lane_id() == 0)
+        n = pnew ? atomicAdd(cnt, pnew) + pnew : __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    n = readlane(n, 0);
+    pnew = 0;
+    probing = n < probe_cap(c);
+    if (n < c.k || n < seen + (seen >> 3) + 1u) return;
+    seen = n;
+    const uint32_t b = wave_bound_from_hist(probe_hist(c), c.k);
+    if (lane_id() == 0) atomicMin(&c.qs->bound, b);
 }
 
 // Relax NJ window arcs per lane (slot j holds window arc j*64 + lane) and
@@ -229,7 +256,7 @@ __device__ __forceinline__ bool in_s(const SrcCtx &c, uint32_t y) {
 // the packed atomicMin.  Idle lanes issue no-op atomics instead of branching.
 // Called by all 64 lanes; st.ovf is wave-uniform afterwards.
 template <int HB, int NJ>
-__device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, uint32_t P,
+__device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, uint32_t P, const SrcCtx &c,
                                              const ArcRec *r, const uint32_t *nd, uint32_t bound) {
     constexpr uint32_t H = Tier<HB>::H;
     constexpr uint32_t PC = Tier<HB>::PC;
@@ -292,6 +319,17 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, ui
 #pragma unroll
     for (int j = 0; j < NJ; ++j) ins += popc(__ballot(old[j] == kWordNone && stt[j] >= 4u));
     st.nins += ins;
+    if (st.probing && ins != 0) {
+        // k-closest pairs: a first discovery of an S member is a pair with a
+        // path of length nd
+        uint32_t *ph = probe_hist(c);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const bool fresh = old[j] == kWordNone && stt[j] >= 4u && in_s(c, static_cast<uint32_t>(r[j].y));
+            if (fresh) atomicAdd(&ph[dist_bin(nd[j])], 1u);
+            st.pnew += popc(__ballot(fresh));
+        }
+    }
     if (__ballot(lost) != 0 || st.nins > (3u * H) / 4u || st.np + nadd > PC) {
         st.ovf = true;
         return;
@@ -311,7 +349,7 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, ui
 // Load window arcs j*64 + lane (j < NJ) and relax them.  Every load is issued
 // before any is used; lanes past the window's end load arc 0 and stay idle.
 template <int HB, int NJ>
-__device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, uint32_t P,
+__device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, uint32_t P, const SrcCtx &c,
                                             const ArcRec *__restrict__ arcs, uint32_t cnt,
                                             uint32_t bound) {
     const uint32_t lane = lane_id();
@@ -331,17 +369,17 @@ __device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, uin
 #pragma unroll
     for (int j = 0; j < NJ; ++j) nd[j] = (j * 64 + lane < cnt) ? sat_add(od[j], r[j].w) : kInf;
     wave_sync();  // window map fully read before the next window rewrites it
-    relax_window<HB, NJ>(L, st, P, r, nd, bound);
+    relax_window<HB, NJ>(L, st, P, c, r, nd, bound);
 }
 
 // k-closest pairs: once the query has emitted k records, bound its k-th
 // distance by its emitted-distance histogram and lower the shared bound.
 // Whole wave.
 __device__ __forceinline__ void tighten_bound(const SrcCtx &c) {
-    const unsigned long long n = __hip_atomic_load(c.npairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long n = __hip_atomic_load(&c.qs->npairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (n < c.k) return;
-    const uint32_t b = wave_bound_from_hist(c.cand_hist, c.k);
-    if ((threadIdx.x & 63u) == 0) atomicMin(c.bound, b);
+    const uint32_t b = wave_bound_from_hist(c.hist + kHistEmit, c.k);
+    if ((threadIdx.x & 63u) == 0) atomicMin(&c.qs->bound, b);
 }
 
 // Reserve n record slots for query c (one atomic per wave); the base is
@@ -350,7 +388,7 @@ __device__ __forceinline__ unsigned long long reserve_recs(const JoinArgs &a, co
     unsigned long long base = 0;
     if (lane_id() == 0) {
         base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(n));
-        atomicAdd(c.npairs, static_cast<unsigned long long>(n));
+        atomicAdd(&c.qs->npairs, static_cast<unsigned long long>(n));
     }
     return (static_cast<unsigned long long>(readlane(static_cast<uint32_t>(base >> 32), 0)) << 32) |
            readlane(static_cast<uint32_t>(base), 0);
@@ -407,12 +445,18 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
     WaveState st;
     st.np = 1;
     st.nins = 1;
+    st.pnew = 0;
     st.ovf = (ue - ub) > 0xFFFF;
+    st.probing = false;
     uint32_t P = 0;      // list receiving appends (the pending list)
     uint32_t pmin = 0;
     uint32_t bound = c.theta;
+    uint32_t seen = 0, phase = 0;
 
     while (st.np > 0 && !st.ovf) {
+        // small searches (the first two phases) never count discoveries
+        if (c.hist != nullptr && phase >= 2) probe_phase(c, st.pnew, st.probing, seen);
+        ++phase;
         bound = current_bound(c);
         uint32_t F, nf;
         uint32_t kmin = kInf;
@@ -477,10 +521,10 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 wave_sync();
                 const uint32_t cnt = min(kWin, total - wb);
                 switch ((cnt + 63u) / 64u) {
-                    case 1: window_step<HB, 1>(L, st, P, a.arcs, cnt, bound); break;
-                    case 2: window_step<HB, 2>(L, st, P, a.arcs, cnt, bound); break;
-                    case 3: window_step<HB, 3>(L, st, P, a.arcs, cnt, bound); break;
-                    default: window_step<HB, 4>(L, st, P, a.arcs, cnt, bound); break;
+                    case 1: window_step<HB, 1>(L, st, P, c, a.arcs, cnt, bound); break;
+                    case 2: window_step<HB, 2>(L, st, P, c, a.arcs, cnt, bound); break;
+                    case 3: window_step<HB, 3>(L, st, P, c, a.arcs, cnt, bound); break;
+                    default: window_step<HB, 4>(L, st, P, c, a.arcs, cnt, bound); break;
                 }
                 wave_sync();
             }
@@ -522,7 +566,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
         for (int j = 0; j < U; ++j) {
             const bool m = sb[j] && d[j] <= bound;
             const uint64_t mM = __ballot(m);
-            if (c.k && m) atomicAdd(&c.cand_hist[dist_bin(d[j])], 1u);
+            if (c.k && m) atomicAdd(&c.hist[kHistEmit + dist_bin(d[j])], 1u);
             emitted += popc(mM);
             const uint32_t idx = m ? nst + mbcnt(mM) : static_cast<uint32_t>(PC);
             L.beg[0][idx] = static_cast<int32_t>(k[j]);
@@ -604,7 +648,7 @@ __device__ __forceinline__ void gstore(uint32_t *p, uint32_t v) {
 
 __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots, size_t slot_words,
                                                      int32_t Vmax) {
-    __shared__ uint32_t s_nf, s_nfn, s_ntouched, s_bound;
+    __shared__ uint32_t s_nf, s_nfn, s_ntouched, s_bound, s_probing;
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     uint32_t sb, n;
     launch_range(a, sb, n);
@@ -627,13 +671,17 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
         }
         __syncthreads();
         uint32_t *F = fa, *Fn = fb;
+        uint32_t seen = 0, pnew = 0;
+        bool probing = false;
         while (true) {
             const uint32_t nf = s_nf;
             if (nf == 0) break;
             __syncthreads();
+            if (tid < 64 && c.hist != nullptr) probe_phase(c, pnew, probing, seen);
             if (tid == 0) {
                 s_nfn = 0;
                 s_bound = current_bound(c);
+                s_probing = probing ? 1u : 0u;
             }
             for (uint32_t j = tid; j < nf; j += 256) {
                 const uint32_t x = F[j] - voff;
@@ -653,7 +701,13 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
                     const uint32_t yl = static_cast<uint32_t>(r.y) - voff;
                     const uint32_t old = atomicMin(&dist[yl], nd);
                     if (nd >= old) continue;
-                    if (old == kInf) touched[atomicAdd(&s_ntouched, 1u)] = yl;
+                    if (old == kInf) {
+                        touched[atomicAdd(&s_ntouched, 1u)] = yl;
+                        if (s_probing && ((c.sbits[yl >> 5] >> (yl & 31u)) & 1u)) {
+                            atomicAdd(&probe_hist(c)[dist_bin(nd)], 1u);
+                            atomicAdd(probe_count(c), 1u);
+                        }
+                    }
                     const uint32_t bit = 1u << (yl & 31u);
                     if ((atomicOr(&inq[yl >> 5], bit) & bit) == 0) Fn[atomicAdd(&s_nfn, 1u)] = static_cast<uint32_t>(r.y);
                 }
@@ -687,12 +741,12 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
                 }
             }
             const uint64_t mm = __ballot(m);
-            if (c.k && m) atomicAdd(&c.cand_hist[dist_bin(d)], 1u);
+            if (c.k && m) atomicAdd(&c.hist[kHistEmit + dist_bin(d)], 1u);
             if (mm != 0) {
                 unsigned long long base = 0;
                 if (lane == 0) {
                     base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(popc(mm)));
-                    atomicAdd(c.npairs, static_cast<unsigned long long>(popc(mm)));
+                    atomicAdd(&c.qs->npairs, static_cast<unsigned long long>(popc(mm)));
                 }
                 const uint32_t lo = static_cast<uint32_t>(__shfl(static_cast<int>(base & 0xFFFFFFFFull), 0));
                 const uint32_t hi = static_cast<uint32_t>(__shfl(static_cast<int>(base >> 32), 0));
@@ -865,7 +919,7 @@ __global__ void k_kcp_seed_hist(JoinArgs a) {
     if (i >= *a.send) return;
     const SrcCtx c = load_ctx(a, a.srcq[i]);
     if (c.k == 0) return;
-    uint32_t *seed = c.cand_hist - kDistBins;
+    uint32_t *seed = c.hist + kHistSeed;
     const int32_t u = a.src[i];
     const int32_t b = a.row_ptr[u], e = a.row_ptr[u + 1];
     for (int32_t x = b; x < e; ++x) {
@@ -884,7 +938,7 @@ __global__ void k_kcp_seed_hist(JoinArgs a) {
 __global__ __launch_bounds__(64) void k_kcp_seed_bound(const QueryDesc *qd, QueryState *qs, const uint32_t *hists) {
     const QueryDesc &d = qd[blockIdx.x];
     if (d.k == 0) return;
-    const uint32_t b = wave_bound_from_hist(hists + d.hist, d.k);
+    const uint32_t b = wave_bound_from_hist(hists + d.hist + kHistSeed, d.k);
     if (threadIdx.x == 0) qs[blockIdx.x].bound = min(b, d.theta);
 }
 

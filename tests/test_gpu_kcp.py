@@ -124,3 +124,15 @@ def test_kcp_argument_errors(rnmod, rg, g64):
     with pytest.raises(rnmod.RnError) as ei:
         net.kcp_join(R, S2, 5)
     assert ei.value.status == rnmod.RN_ERR_ARG
+
+
+def test_bound_tightens_while_searches_run(rnmod, orc, rg):
+    # 4096 pairs, k = 100: the 100th distance is reached inside a small ball
+    # around each source, but no search can finish before the others have
+    # found their first pairs, so the bound must drop while they run for
+    # every search to stay on chip
+    g = rg.road_graph(200, 9)
+    R, S = rg.sample_disjoint(g.V, 64, 64, 61)
+    net = rnmod.RoadNetwork.from_graph(g)
+    assert_same(gpu_kcp(rnmod, net, R, S, 100), orc.kcp_join(g, R, S, 100))
+    assert net.stats()["global_searches"] == 0
