@@ -346,7 +346,7 @@ rn_status ensure_gslots(rn_graph *g) {
     const size_t V = static_cast<size_t>(g->Vmax);
     for (size_t i = 0; i < n; ++i) {
         RN_HIP(launch_fill_u32(g->d_gslots + i * words, V, kInf, nullptr), "clearing search slots");
-        RN_HIP(launch_fill_u32(g->d_gslots + i * words + V, (V + 31) / 32, 0u, nullptr), "clearing search slots");
+        RN_HIP(launch_fill_u32(g->d_gslots + i * words + V, V, 0u, nullptr), "clearing search slots");
     }
     RN_HIP(hipDeviceSynchronize(), "clearing search slots");
     return RN_OK;

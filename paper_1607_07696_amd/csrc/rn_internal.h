@@ -140,12 +140,10 @@ struct JoinArgs {
 };
 
 // Per-source state of the global-memory tier, one slot per concurrent block:
-// dist[V] | queued bitmap[ceil(V/32)] | frontier[V] | next frontier[V] | touched[V],
-// V the largest graph's vertex count.  Between searches dist is all kInf and
-// the bitmap all zero.
-inline size_t global_slot_words(int32_t V) {
-    return 4 * static_cast<size_t>(V) + (static_cast<size_t>(V) + 31) / 32;
-}
+// dist[V] | queue stamp[V] | frontier[V] | next frontier[V] | touched[V], V the
+// largest graph's vertex count.  Between searches dist is all kInf and every
+// stamp zero.
+inline size_t global_slot_words(int32_t V) { return 5 * static_cast<size_t>(V); }
 
 // Host-side description of the call buffers the launch sequence uses.
 struct CallBuffers {

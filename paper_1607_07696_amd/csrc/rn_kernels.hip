@@ -634,11 +634,19 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
 }
 
 // ------------------------------------------------------------------ global-memory tier
-// A search that outgrows every on-chip table runs here: one 256-thread block
-// per source, its distances in a dense per-slot array indexed by the local id,
+// A search that outgrows every on-chip table runs here: one 1024-thread block
+// per source, its state in a dense per-slot area indexed by the local id,
 // frontier-synchronous (every vertex improved in a round is expanded in the
-// next).  Only rare, very large searches (huge balls, expander graphs,
+// next).  Each round's arcs are flattened into windows of kGWin arcs, kGJ per
+// thread, whose loads and atomics are all issued before any result is used.
+// A vertex is queued for round r + 1 by raising its stamp to r + 1, so a
+// vertex improved while it is being expanded is queued again without a
+// clearing pass.  Only rare, very large searches (huge balls, expander graphs,
 // unbounded k-closest-pairs searches) take this path.
+constexpr uint32_t kGT = 1024;
+constexpr uint32_t kGJ = 4;
+constexpr uint32_t kGWin = kGT * kGJ;
+
 __device__ __forceinline__ uint32_t gload(const uint32_t *p) {
     return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -646,24 +654,55 @@ __device__ __forceinline__ void gstore(uint32_t *p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots, size_t slot_words,
-                                                     int32_t Vmax) {
+// Slot of a block-wide list append: one LDS atomic per wave.
+__device__ __forceinline__ uint32_t block_append(bool want, uint32_t *counter) {
+    const uint64_t m = __ballot(want);
+    if (m == 0) return 0;
+    const int leader = __ffsll(static_cast<long long>(m)) - 1;
+    uint32_t base = 0;
+    if (static_cast<int>(lane_id()) == leader) base = atomicAdd(counter, popc(m));
+    return readlane(base, leader) + mbcnt(m);
+}
+
+// Exclusive scan over a 1024-thread block (ws: 16 words of LDS); *total gets the sum.
+__device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t *ws, uint32_t *total) {
+    const uint32_t tid = threadIdx.x;
+    const uint32_t incl = wave_incl_scan(v);
+    if ((tid & 63u) == 63u) ws[tid >> 6] = incl;
+    __syncthreads();
+    uint32_t off = 0, all = 0;
+    for (uint32_t w = 0; w < kGT / 64; ++w) {
+        const uint32_t x = ws[w];
+        off += w < (tid >> 6) ? x : 0u;
+        all += x;
+    }
+    __syncthreads();
+    *total = all;
+    return off + incl - v;
+}
+
+__global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slots, size_t slot_words,
+                                                      int32_t Vmax) {
+    __shared__ int32_t s_widx[kGWin];
+    __shared__ uint32_t s_wd[kGWin];
+    __shared__ uint32_t s_ws[kGT / 64];
     __shared__ uint32_t s_nf, s_nfn, s_ntouched, s_bound, s_probing;
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     uint32_t sb, n;
     launch_range(a, sb, n);
-    const size_t nw = (static_cast<size_t>(Vmax) + 31) / 32;
-    uint32_t *dist = slots + blockIdx.x * slot_words;   // local ids
-    uint32_t *inq = dist + Vmax;                         // local ids
-    uint32_t *fa = inq + nw;                             // global ids
-    uint32_t *fb = fa + Vmax;
-    uint32_t *touched = fb + Vmax;                       // local ids
+    const size_t V = static_cast<size_t>(Vmax);
+    uint32_t *dist = slots + blockIdx.x * slot_words;    // local ids
+    uint32_t *stamp = dist + V;                          // local ids: round a vertex is queued for
+    uint32_t *fa = stamp + V;                            // global ids
+    uint32_t *fb = fa + V;
+    uint32_t *touched = fb + V;                          // local ids
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const int32_t u = a.src[sb + i];
         const SrcCtx c = load_ctx(a, a.srcq[sb + i]);
         const uint32_t voff = static_cast<uint32_t>(c.voff);
         if (tid == 0) {
             gstore(&dist[u - c.voff], 0u);
+            gstore(&stamp[u - c.voff], 1u);
             fa[0] = static_cast<uint32_t>(u);
             touched[0] = static_cast<uint32_t>(u - c.voff);
             s_nf = 1;
@@ -671,53 +710,83 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
         }
         __syncthreads();
         uint32_t *F = fa, *Fn = fb;
-        uint32_t seen = 0, pnew = 0;
+        uint32_t seen = 0, pnew = 0, round = 1;
         bool probing = false;
         while (true) {
             const uint32_t nf = s_nf;
             if (nf == 0) break;
-            __syncthreads();
+            __syncthreads();   // every thread has read s_nf
             if (tid < 64 && c.hist != nullptr) probe_phase(c, pnew, probing, seen);
             if (tid == 0) {
                 s_nfn = 0;
                 s_bound = current_bound(c);
                 s_probing = probing ? 1u : 0u;
             }
-            for (uint32_t j = tid; j < nf; j += 256) {
-                const uint32_t x = F[j] - voff;
-                atomicAnd(&inq[x >> 5], ~(1u << (x & 31u)));
-            }
             __syncthreads();
             const uint32_t bound = s_bound;
-            for (uint32_t j = tid; j < nf; j += 256) {
-                const uint32_t x = F[j];
-                const uint32_t dx = gload(&dist[x - voff]);
-                if (dx > bound) continue;
-                const int32_t e = a.row_ptr[x + 1];
-                for (int32_t arc = a.row_ptr[x]; arc < e; ++arc) {
-                    const ArcRec r = a.arcs[arc];
-                    const uint32_t nd = sat_add(dx, r.w);
-                    if (nd > bound) continue;
-                    const uint32_t yl = static_cast<uint32_t>(r.y) - voff;
-                    const uint32_t old = atomicMin(&dist[yl], nd);
-                    if (nd >= old) continue;
-                    if (old == kInf) {
-                        touched[atomicAdd(&s_ntouched, 1u)] = yl;
-                        if (s_probing && ((c.sbits[yl >> 5] >> (yl & 31u)) & 1u)) {
-                            atomicAdd(&probe_hist(c)[dist_bin(nd)], 1u);
-                            atomicAdd(probe_count(c), 1u);
-                        }
+            const bool probe_on = s_probing != 0;
+            for (uint32_t cb = 0; cb < nf; cb += kGT) {
+                const uint32_t t = cb + tid;
+                const bool valid = t < nf;
+                const uint32_t x = valid ? F[t] : 0u;
+                const uint32_t dx = valid ? gload(&dist[x - voff]) : kInf;
+                const int32_t beg = valid ? a.row_ptr[x] : 0;
+                const uint32_t deg = (valid && dx <= bound) ? static_cast<uint32_t>(a.row_ptr[x + 1] - beg) : 0u;
+                uint32_t total;
+                const uint32_t excl = block_scan_1024(deg, s_ws, &total);
+                for (uint32_t wb = 0; wb < total; wb += kGWin) {
+                    const uint32_t lo = max(excl, wb), hi = min(excl + deg, wb + kGWin);
+                    for (uint32_t p = lo; p < hi; ++p) {
+                        s_widx[p - wb] = beg + static_cast<int32_t>(p - excl);
+                        s_wd[p - wb] = dx;
                     }
-                    const uint32_t bit = 1u << (yl & 31u);
-                    if ((atomicOr(&inq[yl >> 5], bit) & bit) == 0) Fn[atomicAdd(&s_nfn, 1u)] = static_cast<uint32_t>(r.y);
+                    __syncthreads();
+                    const uint32_t cnt = min(kGWin, total - wb);
+                    ArcRec r[kGJ];
+                    uint32_t nd[kGJ], old[kGJ];
+#pragma unroll
+                    for (uint32_t j = 0; j < kGJ; ++j) {
+                        const uint32_t e = j * kGT + tid;
+                        r[j] = a.arcs[e < cnt ? s_widx[e] : 0];
+                        nd[j] = e < cnt ? sat_add(s_wd[e], r[j].w) : kInf;
+                    }
+                    __syncthreads();   // window map read before the next window rewrites it
+#pragma unroll
+                    for (uint32_t j = 0; j < kGJ; ++j) {
+                        const uint32_t yl = static_cast<uint32_t>(r[j].y) - voff;
+                        old[j] = nd[j] <= bound ? atomicMin(&dist[yl], nd[j]) : 0u;
+                    }
+                    uint32_t qs[kGJ];
+#pragma unroll
+                    for (uint32_t j = 0; j < kGJ; ++j) {
+                        const uint32_t yl = static_cast<uint32_t>(r[j].y) - voff;
+                        qs[j] = nd[j] < old[j] ? atomicMax(&stamp[yl], round + 1u) : round + 1u;
+                    }
+#pragma unroll
+                    for (uint32_t j = 0; j < kGJ; ++j) {
+                        const uint32_t yl = static_cast<uint32_t>(r[j].y) - voff;
+                        const bool fresh = nd[j] < old[j] && old[j] == kInf;
+                        const uint32_t ti = block_append(fresh, &s_ntouched);
+                        if (fresh) {
+                            touched[ti] = yl;
+                            if (probe_on && ((c.sbits[yl >> 5] >> (yl & 31u)) & 1u)) {
+                                atomicAdd(&probe_hist(c)[dist_bin(nd[j])], 1u);
+                                atomicAdd(probe_count(c), 1u);
+                            }
+                        }
+                        const bool queue = qs[j] < round + 1u;
+                        const uint32_t fi = block_append(queue, &s_nfn);
+                        if (queue) Fn[fi] = static_cast<uint32_t>(r[j].y);
+                    }
                 }
             }
             __syncthreads();
             if (tid == 0) s_nf = s_nfn;
+            ++round;
             __syncthreads();
-            uint32_t *t = F;
+            uint32_t *tmp = F;
             F = Fn;
-            Fn = t;
+            Fn = tmp;
         }
         // emit S members, count work, reset the slot
         if (tid == 0) s_bound = current_bound(c);
@@ -726,7 +795,7 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
         const uint32_t nt = s_ntouched;
         unsigned long long warcs = 0;
         uint32_t wsettled = 0;
-        for (uint32_t j0 = 0; j0 < nt; j0 += 256) {
+        for (uint32_t j0 = 0; j0 < nt; j0 += kGT) {
             const uint32_t j = j0 + tid;
             uint32_t yl = 0, d = kInf;
             bool m = false;
@@ -734,6 +803,7 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
                 yl = touched[j];
                 d = gload(&dist[yl]);
                 gstore(&dist[yl], kInf);
+                gstore(&stamp[yl], 0u);
                 m = d <= bound && ((c.sbits[yl >> 5] >> (yl & 31u)) & 1u);
                 if (a.count_work && d <= bound) {
                     warcs += static_cast<unsigned long long>(a.row_ptr[yl + voff + 1] - a.row_ptr[yl + voff]);
@@ -753,12 +823,12 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
                 base = (static_cast<unsigned long long>(hi) << 32) | lo;
                 const unsigned long long idx = base + mbcnt(mm);
                 if (m && idx < a.rec_cap) {
-                    Rec r;
-                    r.u = u - c.voff;
-                    r.v = static_cast<int32_t>(yl);
-                    r.d = d;
-                    r.q = c.q;
-                    a.recs[idx] = r;
+                    Rec rr;
+                    rr.u = u - c.voff;
+                    rr.v = static_cast<int32_t>(yl);
+                    rr.d = d;
+                    rr.q = c.q;
+                    a.recs[idx] = rr;
                 }
             }
         }
@@ -776,6 +846,7 @@ __global__ __launch_bounds__(256) void k_join_global(JoinArgs a, uint32_t *slots
         }
         __syncthreads();
         if (c.k && tid < 64) tighten_bound(c);
+        __syncthreads();   // the slot is clean before the next source starts
     }
 }
 
@@ -1254,7 +1325,7 @@ hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslot
                               uint32_t max_sources, hipStream_t s) {
     uint32_t grid = nslots < max_sources ? nslots : max_sources;
     if (grid == 0) grid = 1;
-    hipLaunchKernelGGL(k_join_global, dim3(grid), dim3(256), 0, s, a, slots, global_slot_words(Vmax), Vmax);
+    hipLaunchKernelGGL(k_join_global, dim3(grid), dim3(kGT), 0, s, a, slots, global_slot_words(Vmax), Vmax);
     return hipGetLastError();
 }
 
