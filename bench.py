@@ -219,6 +219,92 @@ def batch_leg(torch, rn, steps):
     return res
 
 
+def serve_leg(torch, rn, rate_hz=1000.0, count=2000):
+    """Poisson stream of joins on the resident 2048x2048 graph: the request
+    server (continuous batching) against the same requests served one at a
+    time, in arrival order, by the single-query calls."""
+    import threading
+    from paper_1607_07696_amd import roadgen
+    MAX = rn.MAX_DIST
+    g = roadgen.road_graph(2048, 0)
+    reqs = roadgen.serving_stream(g, count, rate_hz, 5)
+    log(f"serve: graph V={g.V} A={g.A}, {count} requests over {reqs[-1].arrival_s:.2f} s")
+    net = rn.RoadNetwork.from_graph(g)
+    theta_of = [r.theta if r.k == 0 else MAX for r in reqs]
+    # warm-up outside the timed stream
+    srv = rn.Server(net, lanes=4, max_batch=32, global_slots=16, hbm_budget=16 << 30)
+    for r, t in zip(reqs[:8], theta_of[:8]):
+        srv.wait(srv.submit(r.R, r.S, t, r.k))
+    ids = [None] * count
+    t0 = time.perf_counter()
+
+    def producer():
+        for i, (r, t) in enumerate(zip(reqs, theta_of)):
+            delay = r.arrival_s - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            ids[i] = srv.submit(r.R, r.S, t, r.k)
+    th = threading.Thread(target=producer)
+    th.start()
+    lat, dks, npairs = [], [], 0
+    for i in range(count):
+        while ids[i] is None:
+            time.sleep(0.0001)
+        out, ms = srv.wait(ids[i])
+        lat.append(ms)
+        if (i + 1) % 250 == 0:
+            log(f"serve: {i + 1} answered, {time.perf_counter() - t0:.2f} s")
+        npairs += out.shape[0]
+        dks.append(int(out["dist"][-1]) if (reqs[i].k and out.shape[0]) else 0)
+    makespan = time.perf_counter() - t0
+    th.join()
+    st = srv.stats()
+    srv.close()
+    log(f"serve: server done in {makespan:.2f} s; the same requests one at a time")
+    # the plain path: each request alone (upload, call, result to the host),
+    # queued first come first served
+    service = []
+    for i, (r, t) in enumerate(zip(reqs, theta_of)):
+        if (i + 1) % 250 == 0:
+            log(f"serve: plain {i + 1} done, {sum(service):.2f} s")
+        a = time.perf_counter()
+        Rd = torch.as_tensor(r.R, device="cuda")
+        Sd = torch.as_tensor(r.S, device="cuda")
+        out = net.kcp_join(Rd, Sd, r.k) if r.k else net.dist_join(Rd, Sd, t)
+        rn.pairs_to_numpy(out)
+        service.append(time.perf_counter() - a)
+    done, plat = 0.0, []
+    for r, s_ in zip(reqs, service):
+        done = max(done, r.arrival_s) + s_
+        plat.append((done - r.arrival_s) * 1e3)
+    # work: arcs out of every vertex within theta (theta-joins) or within the
+    # k-th distance (k-closest pairs) of each source
+    log("serve: counting work")
+    net.set_profiling(times=False, work=True)
+    arcs = 0
+    for c0 in range(0, count, 64):
+        specs = [{"R": r.R, "S": r.S, "k": 0, "theta": (dk if r.k else r.theta)}
+                 for r, dk in zip(reqs[c0:c0 + 64], dks[c0:c0 + 64])]
+        net.join_batch(specs)
+        arcs += int(net.stats()["arcs"])
+    net.set_profiling(times=False, work=False)
+    net.close()
+    pct = lambda a, q: round(float(np.percentile(a, q)), 3)
+    return {"workload": (f"{count} requests, Poisson arrivals at {rate_hz:g}/s (seed 5), on the 2048x2048 road "
+                         "graph (seed 0): 60% theta-joins with theta uniform in [500, 8000], 40% k closest "
+                         "pairs with k log-uniform in [1, 4096]; |R|, |S| log-uniform in [64, 32768]"),
+            "V": g.V, "A": g.A, "pairs": int(npairs), "work_arcs": arcs,
+            "server": {"lanes": 4, "max_batch": 32, "hbm_budget_gib": 16,
+                       "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": pct(lat, 100)},
+                       "throughput_rps": round(count / makespan, 1), "makespan_s": round(makespan, 3),
+                       "gteps": round(arcs / makespan / 1e9, 3), "stats": st},
+            "plain_fifo": {"latency_ms": {"p50": pct(plat, 50), "p99": pct(plat, 99), "max": pct(plat, 100)},
+                           "service_ms": {"p50": pct(np.array(service) * 1e3, 50),
+                                          "p99": pct(np.array(service) * 1e3, 99)},
+                           "throughput_rps": round(count / done, 1), "makespan_s": round(done, 3),
+                           "gteps": round(arcs / done / 1e9, 3)}}
+
+
 def cpu_baseline(g, R, S, theta, arcs_total, budget_s):
     from oracle import oracle
     times = []
@@ -250,6 +336,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kcp", action="store_true", help="skip the k-closest-pairs leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run one 256 MiB device copy (counter calibration)")
     args = ap.parse_args()
@@ -352,6 +439,9 @@ def main():
     if not args.no_batch:
         log("batched-instances leg")
         result["batch"] = batch_leg(torch, rn, max(10, args.steps))
+    if not args.no_serve:
+        log("serving leg")
+        result["serve"] = serve_leg(torch, rn)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         result["cpu_baseline"] = cpu_baseline(g, R, S, theta, arcs, args.cpu_budget)

@@ -261,6 +261,73 @@ rn_status rn_plan_create(rn_graph *g, const rn_query *q, int32_t nq, rn_pair *ou
 rn_status rn_plan_run(rn_plan *p, int64_t *offsets, int32_t *status, void *stream);
 void rn_plan_free(rn_plan *p);
 
+/*
+ * ---- Serving: a request server with continuous batching.
+ *
+ * A server keeps one graph of a handle resident and answers join requests
+ * as they arrive.  A host thread of the library admits waiting requests, in
+ * arrival order, into free lanes whenever the estimated device footprint of
+ * the requests in flight stays within hbm_budget (one request is admitted
+ * whenever nothing is in flight, however large), and runs each lane's
+ * requests as one batch (the launch sequence of rn_join_batch) on the lane's
+ * own stream and buffers.  Requests that arrive while others are on the
+ * device are admitted as lanes and budget free up, and their work overlaps
+ * with the batches already running.  Each request's result is exactly the
+ * result of the same query run alone.  The server holds the handle for its
+ * lifetime: other calls on it return RN_ERR_BUSY until rn_server_free.
+ */
+typedef struct rn_server rn_server;
+
+typedef struct rn_server_config {
+    int32_t graph;          /* graph of the handle the requests address */
+    int32_t lanes;          /* batches in flight at once, 1..16 */
+    int32_t max_batch;      /* most requests in one batch, 1..65536 */
+    int32_t global_slots;   /* global-tier searches each lane runs at once, 1..256 */
+    int64_t hbm_budget;     /* bytes of estimated device footprint in flight, > 0 */
+} rn_server_config;
+
+typedef struct rn_server_stats {
+    int64_t submitted;      /* requests accepted */
+    int64_t completed;      /* requests answered (including argument errors) */
+    int64_t batches;        /* batches launched */
+    int64_t reruns;         /* batches re-run with larger buffers */
+    int64_t peak_budget;    /* largest estimated footprint in flight, bytes */
+    int64_t device_bytes;   /* device memory held by the lanes, bytes */
+    int32_t max_in_flight;  /* most requests in flight at once */
+    int32_t max_lanes_busy; /* most lanes busy at once */
+    int32_t max_batch_seen; /* largest batch launched */
+    int32_t reserved;
+} rn_server_stats;
+
+/* Start a server on graph cfg->graph of g (device work runs on lane streams
+ * the server creates).  RN_ERR_ARG on a bad configuration, RN_ERR_BUSY if the
+ * handle is in use. */
+rn_status rn_server_create(rn_graph *g, const rn_server_config *cfg, rn_server **out);
+
+/*
+ * Submit a request; returns at once with its id.  R, S are HOST arrays (copied
+ * before the call returns) with the rules of rn_dist_join; k = 0 asks for the
+ * theta-join, k >= 1 for the k closest pairs within theta (theta = 2^32 - 2:
+ * unbounded).  RN_ERR_ARG for counts, k or theta out of range; invalid ids,
+ * duplicates or overlaps are reported by rn_server_wait.
+ */
+rn_status rn_server_submit(rn_server *s, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS, uint32_t theta,
+                           int32_t k, int64_t *id);
+
+/*
+ * Wait for request id, then copy its pairs (sorted by (dist, u, v)) to the
+ * HOST buffer out[0 .. *n_out) and release the request.  latency_ms (may be
+ * NULL) receives the time from submission to the result reaching the host.
+ * RN_ERR_CAPACITY (request kept, *n_out set) if cap is too small; the
+ * request's own error (RN_ERR_ARG for invalid node sets, ...) otherwise.
+ */
+rn_status rn_server_wait(rn_server *s, int64_t id, rn_pair *out, int64_t cap, int64_t *n_out, double *latency_ms);
+
+rn_status rn_server_get_stats(rn_server *s, rn_server_stats *out);
+
+/* Finish every submitted request, stop the server and free it (NULL accepted). */
+void rn_server_free(rn_server *s);
+
 /* Per-call statistics of the most recent join on a handle. */
 typedef struct rn_stats {
     float stage_ms;      /* validation and source staging kernels */

@@ -16,14 +16,19 @@
 #include <vector>
 
 #include "rn.h"
+#include "rn_host.h"
 #include "rn_internal.h"
 #include "rn_partition.h"
 
 using namespace rn;
+using namespace rn::host;
+
+namespace rn {
+namespace host {
 
 namespace {
-
 thread_local std::string t_err;
+}
 
 rn_status fail(rn_status st, const std::string &msg) {
     t_err = msg;
@@ -34,189 +39,7 @@ rn_status hip_fail(hipError_t e, const char *what) {
     return fail(RN_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define RN_HIP(call, what)                                  \
-    do {                                                    \
-        hipError_t _e = (call);                             \
-        if (_e != hipSuccess) return hip_fail(_e, what);    \
-    } while (0)
-
-#define RN_TRY(call)                          \
-    do {                                      \
-        rn_status _s = (call);                \
-        if (_s != RN_OK) return _s;           \
-    } while (0)
-
-template <typename T>
-hipError_t dev_alloc(T **p, size_t count) {
-    *p = nullptr;
-    if (count == 0) count = 1;
-    return hipMalloc(reinterpret_cast<void **>(p), count * sizeof(T));
-}
-
-template <typename T>
-void dev_free(T *&p) {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-}
-
-template <typename T>
-void host_free(T *&p) {
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-}
-
-// Stage timing events (used when profiling is on).
-enum { EV_START, EV_STAGED, EV_TIER0, EV_RELAXED, EV_SELECTED, EV_DONE, EV_COUNT };
-
-constexpr int kSide = kMaxHB - kMinHB;   // side streams for concurrent first-tier launches
-constexpr int32_t kMaxQueries = 65536;
-constexpr unsigned long long kRecCapMax = 1ull << 31;
-
-size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }
-
-uint32_t bitlen(uint64_t x) {
-    uint32_t b = 0;
-    while (x) { ++b; x >>= 1; }
-    return b;
-}
-
-// Device and pinned host buffers of calls; a handle owns one for its eager
-// calls, every plan owns its own.
-struct Workspace {
-    uint32_t *d_block = nullptr;    // CallCtl | QueryState[nq] | S bitmaps | rank bitmaps | histograms | sort
-    size_t block_words = 0;
-    uint8_t *d_desc = nullptr;      // QueryDesc[nq] | ebase[nq+1] | rbase[nq+1] | perm[nq]
-    size_t desc_bytes = 0;
-    uint8_t *h_desc = nullptr;      // pinned staging of the same
-    size_t h_desc_bytes = 0;
-    uint8_t *h_state = nullptr;     // pinned read-back of CallCtl | QueryState[nq]
-    size_t h_state_bytes = 0;
-    uint32_t *d_stage = nullptr;
-    size_t stage_words = 0;
-    int32_t *d_src = nullptr;
-    uint32_t *d_srcq = nullptr;
-    int32_t *d_list[kLists] = {};
-    uint32_t *d_listq[kLists] = {};
-    size_t src_cap = 0;
-    Rec *d_recs[2] = {};
-    unsigned long long rec_cap = 0;
-    hipStream_t side[kSide] = {};
-    hipEvent_t fork = nullptr;
-    hipEvent_t join[kSide] = {};
-    hipEvent_t ev[EV_COUNT] = {};
-
-    void release() {
-        dev_free(d_block);
-        dev_free(d_desc);
-        host_free(h_desc);
-        host_free(h_state);
-        dev_free(d_stage);
-        dev_free(d_src);
-        dev_free(d_srcq);
-        for (int i = 0; i < kLists; ++i) {
-            dev_free(d_list[i]);
-            dev_free(d_listq[i]);
-        }
-        dev_free(d_recs[0]);
-        dev_free(d_recs[1]);
-        block_words = desc_bytes = h_desc_bytes = h_state_bytes = stage_words = src_cap = 0;
-        rec_cap = 0;
-        for (auto &s : side)
-            if (s) (void)hipStreamDestroy(s), s = nullptr;
-        if (fork) (void)hipEventDestroy(fork), fork = nullptr;
-        for (auto &e : join)
-            if (e) (void)hipEventDestroy(e), e = nullptr;
-        for (auto &e : ev)
-            if (e) (void)hipEventDestroy(e), e = nullptr;
-    }
-};
-
-// One group of queries whose searches start with the same table size.
-struct Group {
-    int hb;
-    int32_t first;          // staging positions [first, end)
-    int32_t end;
-    uint64_t sources;       // sum of nR
-};
-
-// Host-side plan of one call: descriptors, pools and launch shapes.
-struct Prepared {
-    int32_t nq = 0;
-    std::vector<QueryDesc> qd;
-    std::vector<unsigned long long> ebase;
-    std::vector<uint32_t> rbase;
-    std::vector<uint32_t> perm;
-    std::vector<Group> groups;
-    bool any_kcp = false;
-    bool need_list0 = false;
-    bool need_list1 = false;
-    uint32_t qb = 0, vb = 1, max_passes = 1;
-    uint64_t total_R = 0;
-    unsigned long long total_elems = 0;
-    // word offsets in the call block
-    size_t off_qs = 0, off_sbits = 0, off_rbits = 0, off_hists = 0, off_sort = 0, block_words = 0;
-    size_t zero_words = 0;
-    uint32_t sbits_words = 0, rbits_words = 0;
-    size_t desc_bytes = 0, off_ebase = 0, off_rbase = 0, off_perm = 0;
-};
-
-}  // namespace
-
-struct rn_graph {
-    int device = 0;
-    int32_t ngraphs = 0;
-    std::vector<int32_t> voff;      // [ngraphs + 1] vertex offsets
-    std::vector<int64_t> aoff;      // [ngraphs + 1] arc offsets
-    std::vector<uint32_t> w_min;    // per graph (0 when it has no arcs)
-    int32_t V = 0;                  // total vertices
-    int64_t A = 0;                  // total arcs
-    int32_t Vmax = 0;
-    std::vector<int32_t> row_ptr, col;   // concatenated, global ids
-    std::vector<uint32_t> w;
-
-    int32_t *d_row_ptr = nullptr;
-    ArcRec *d_arcs = nullptr;
-    int32_t *d_rank = nullptr;      // global vertex -> rank within its graph (nullptr = identity)
-    int32_t *d_order = nullptr;     // voff + rank -> local vertex
-
-    uint32_t delta = 0;
-    int hash_log2 = 11;
-
-    Workspace ws;
-    uint32_t *d_gslots = nullptr;   // global-memory tier state (global_slot_words(Vmax) per slot)
-    uint32_t n_gslots = 0;
-
-    std::atomic<int> busy{0};
-    bool profiling = false;
-    bool count_work = false;
-    rn_stats stats{};
-};
-
-struct rn_plan {
-    rn_graph *g = nullptr;
-    Workspace ws;
-    std::vector<rn_query> q;
-    Prepared prep;
-    rn_pair *out = nullptr;
-    int64_t cap = 0;
-    hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-};
-
-namespace {
-
-struct BusyGuard {
-    rn_graph *g;
-    bool ok;
-    explicit BusyGuard(rn_graph *gg) : g(gg) {
-        int expect = 0;
-        ok = g->busy.compare_exchange_strong(expect, 1);
-    }
-    ~BusyGuard() {
-        if (ok) g->busy.store(0);
-    }
-};
+const std::string &last_error() { return t_err; }
 
 std::string describe_err(uint32_t err) {
     std::string m;
@@ -273,9 +96,10 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         dmax = std::max(dmax, x.theta);
         p.total_R += static_cast<uint64_t>(x.nR);
     }
-    // staging order: grouped by first table size, query order within a group
+    // staging order: grouped by first table size and kind, query order within a group
     for (int32_t i = 0; i < nq; ++i) p.perm[i] = static_cast<uint32_t>(i);
-    std::stable_sort(p.perm.begin(), p.perm.end(), [&](uint32_t a, uint32_t b) { return hb[a] < hb[b]; });
+    auto key = [&](uint32_t i) { return 2 * hb[i] + (q[i].k > 0 ? 1 : 0); };
+    std::stable_sort(p.perm.begin(), p.perm.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
     uint64_t sw = 0, rw = 0;
     uint32_t nkcp = 0;
     for (int32_t s = 0; s < nq; ++s) {
@@ -294,6 +118,7 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         d.theta = x.theta;
         d.k = static_cast<uint32_t>(x.k);
         d.delta = x.delta == RN_DELTA_DEFAULT ? g->delta : x.delta;
+        d.gdelta = g->gdelta[x.graph];
         d.sbits = static_cast<uint32_t>(sw);
         d.rbits = static_cast<uint32_t>(rw);
         d.hist = x.k ? nkcp * kHistWords : 0;
@@ -303,7 +128,8 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         sw += round_up(words, 4);
         rw += words;
         if (sw >= 0xFFFFFFFFull || rw >= 0xFFFFFFFFull) return fail(RN_ERR_ARG, "too many vertices in one call");
-        if (p.groups.empty() || p.groups.back().hb != hb[i]) p.groups.push_back(Group{hb[i], s, s + 1, 0});
+        if (p.groups.empty() || p.groups.back().hb != hb[i] || p.groups.back().kcp != (x.k > 0))
+            p.groups.push_back(Group{hb[i], x.k > 0, s, s + 1, 0});
         p.groups.back().end = s + 1;
         p.groups.back().sources += static_cast<uint64_t>(x.nR);
     }
@@ -335,18 +161,20 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
     return RN_OK;
 }
 
-rn_status ensure_gslots(rn_graph *g) {
-    if (g->d_gslots) return RN_OK;
-    // up to 64 concurrent global-tier searches, within 8 GiB
-    const size_t words = global_slot_words(g->Vmax);
+rn_status ensure_gslots(Workspace &ws, int32_t Vmax, uint32_t nslots) {
+    if (ws.d_gslots) return RN_OK;
+    // at most nslots concurrent global-tier searches, within 8 GiB
+    const size_t words = global_slot_words(Vmax);
     size_t n = (size_t{8} << 30) / (4 * words);
-    n = std::max<size_t>(1, std::min<size_t>(n, 64));
-    RN_HIP(dev_alloc(&g->d_gslots, n * words), "allocating global search slots");
-    g->n_gslots = static_cast<uint32_t>(n);
-    const size_t V = static_cast<size_t>(g->Vmax);
+    n = std::max<size_t>(1, std::min<size_t>(n, nslots));
+    RN_HIP(dev_alloc(&ws.d_gslots, n * words), "allocating global search slots");
+    ws.n_gslots = static_cast<uint32_t>(n);
+    const size_t V = static_cast<size_t>(Vmax);
     for (size_t i = 0; i < n; ++i) {
-        RN_HIP(launch_fill_u32(g->d_gslots + i * words, V, kInf, nullptr), "clearing search slots");
-        RN_HIP(launch_fill_u32(g->d_gslots + i * words + V, V, 0u, nullptr), "clearing search slots");
+        uint32_t *slot = ws.d_gslots + i * words;
+        RN_HIP(launch_fill_u32(slot, V, kInf, nullptr), "clearing search slots");
+        RN_HIP(launch_fill_u32(slot + V, V, 0u, nullptr), "clearing search slots");
+        RN_HIP(launch_fill_u32(slot + 6 * V, (V + 31) / 32, 0u, nullptr), "clearing search slots");
     }
     RN_HIP(hipDeviceSynchronize(), "clearing search slots");
     return RN_OK;
@@ -462,11 +290,11 @@ CallBuffers call_buffers(const Workspace &ws, const Prepared &p) {
 }
 
 // ------------------------------------------------------------------ launch sequence
-void record(const rn_graph *g, Workspace &ws, bool timed, int which, hipStream_t s) {
+static void record(const rn_graph *g, Workspace &ws, bool timed, int which, hipStream_t s) {
     if (timed && g->profiling) (void)hipEventRecord(ws.ev[which], s);
 }
 
-rn_status ensure_side_streams(Workspace &ws, size_t n) {
+static rn_status ensure_side_streams(Workspace &ws, size_t n) {
     for (size_t i = 0; i < n && i < static_cast<size_t>(kSide); ++i)
         if (!ws.side[i]) RN_HIP(hipStreamCreateWithFlags(&ws.side[i], hipStreamNonBlocking), "creating streams");
     return RN_OK;
@@ -504,6 +332,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     }
     // first tiers, one launch per table size; several run side by side
     const size_t ng = p.groups.size();
+    if (ng > static_cast<size_t>(kSide) + 1) return fail(RN_ERR_DEVICE, "too many first-tier groups");
     if (ng > 1) {
         RN_TRY(ensure_side_streams(ws, ng - 1));
         RN_HIP(hipEventRecord(ws.fork, s), "forking streams");
@@ -523,7 +352,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.novf = &b.ctl->nlist[li];
         t.first_tier = 1;
         t.tier = 0;
-        RN_HIP(launch_join(t, gr.hb, static_cast<uint32_t>(gr.sources), st), "launching the relaxation");
+        RN_HIP(launch_join(t, gr.hb, gr.kcp, static_cast<uint32_t>(gr.sources), st), "launching the relaxation");
         if (gi > 0) RN_HIP(hipEventRecord(ws.join[gi - 1], st), "joining streams");
     }
     for (size_t gi = 1; gi < ng; ++gi) RN_HIP(hipStreamWaitEvent(s, ws.join[gi - 1], 0), "joining streams");
@@ -543,17 +372,17 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.novf = &b.ctl->nlist[li + 1];
         t.first_tier = 0;
         t.tier = 1 + li;
-        RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, maxs, s), "launching the relaxation");
+        RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, true, maxs, s), "launching the relaxation");
     }
     {
-        RN_TRY(ensure_gslots(g));
+        if (!ws.d_gslots) return fail(RN_ERR_DEVICE, "global search slots missing");
         JoinArgs t = a;
         t.src = b.list[2];
         t.srcq = b.listq[2];
         t.sbeg = nullptr;
         t.send = &b.ctl->nlist[2];
         t.tier = 3;
-        RN_HIP(launch_join_global(t, g->d_gslots, g->n_gslots, g->Vmax, maxs, s), "launching the global relaxation");
+        RN_HIP(launch_join_global(t, ws.d_gslots, ws.n_gslots, g->Vmax, maxs, s), "launching the global relaxation");
     }
     record(g, ws, timed, EV_RELAXED, s);
     if (p.any_kcp) RN_HIP(launch_select(b, s), "selecting candidates");
@@ -564,6 +393,13 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     record(g, ws, timed, EV_DONE, s);
     return RN_OK;
 }
+
+}  // namespace host
+}  // namespace rn
+
+namespace {
+
+constexpr uint32_t kDefaultSlots = 64;   // global-tier slots of a handle's calls and of a plan
 
 rn_status read_back(Workspace &ws, const Prepared &p, hipStream_t s) {
     const size_t bytes = sizeof(CallCtl) + static_cast<size_t>(p.nq) * sizeof(QueryState);
@@ -645,6 +481,7 @@ rn_status run_batch(rn_graph *g, const rn_query *q, int32_t nq, rn_pair *out, in
     RN_HIP(hipSetDevice(g->device), "selecting the device");
     Prepared p;
     RN_TRY(prepare(g, q, nq, p));
+    RN_TRY(ensure_gslots(g->ws, g->Vmax, kDefaultSlots));
     return run_eager(g, g->ws, p, out, cap, offsets, status, s, true);
 }
 
@@ -689,7 +526,7 @@ rn_status validate_csr(int32_t V, int64_t A, const int32_t *row_ptr, const int32
 
 extern "C" {
 
-const char *rn_last_error(void) { return t_err.c_str(); }
+const char *rn_last_error(void) { return last_error().c_str(); }
 
 const char *rn_version(void) { return "rn 0.2 (gfx950)"; }
 
@@ -723,6 +560,7 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
         g->voff.assign(n + 1, 0);
         g->aoff.assign(n + 1, 0);
         g->w_min.assign(n, 0);
+        g->gdelta.assign(n, 1);
         g->row_ptr.resize(static_cast<size_t>(totV) + 1);
         g->col.resize(static_cast<size_t>(totA));
         g->w.resize(static_cast<size_t>(totA));
@@ -745,6 +583,12 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
             wm = std::min(wm, w[i][a]);
         }
         g->w_min[i] = wm;
+        // the global tier's buckets: 8 mean arc weights keep relaxations near
+        // one per arc on road graphs at a few thousand rounds for a whole graph
+        double wsum = 0;
+        for (int64_t a = 0; a < A[i]; ++a) wsum += w[i][a];
+        const double gd = A[i] ? 8.0 * wsum / static_cast<double>(A[i]) : 1.0;
+        g->gdelta[i] = static_cast<uint32_t>(std::min(std::max(gd, 1.0), 2147483648.0));
     }
     g->row_ptr[totV] = static_cast<int32_t>(totA);
     for (int64_t a = 0; a < totA; ++a) {
@@ -780,7 +624,6 @@ void rn_graph_free(rn_graph *g) {
     (void)hipSetDevice(g->device);
     (void)hipDeviceSynchronize();
     g->ws.release();
-    dev_free(g->d_gslots);
     dev_free(g->d_row_ptr);
     dev_free(g->d_arcs);
     dev_free(g->d_rank);
@@ -951,6 +794,7 @@ rn_status rn_autotune(rn_graph *g, rn_query *q, int32_t nq, int32_t sample, void
                 t.hash_log2 = hbs[hi];
                 Prepared p;
                 result = prepare(g, &t, 1, p);
+                if (result == RN_OK) result = ensure_gslots(g->ws, g->Vmax, kDefaultSlots);
                 if (result != RN_OK) break;
                 float ms = 3.4e38f;
                 for (int rep = 0; rep < 3 && result == RN_OK; ++rep) {
@@ -997,8 +841,7 @@ rn_status capture_plan(rn_plan *pl, const Prepared &p) {
     rn_graph *g = pl->g;
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec), pl->exec = nullptr;
     if (pl->graph) (void)hipGraphDestroy(pl->graph), pl->graph = nullptr;
-    RN_TRY(ensure_gslots(g));
-    RN_TRY(ensure_side_streams(pl->ws, p.groups.size()));
+    RN_TRY(ensure_gslots(pl->ws, g->Vmax, kDefaultSlots));
     RN_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal), "starting the capture");
     const rn_status st = enqueue_call(g, pl->ws, p, pl->out, pl->cap, pl->cap_stream, false);
     hipGraph_t graph = nullptr;
@@ -1015,6 +858,7 @@ rn_status capture_plan(rn_plan *pl, const Prepared &p) {
 
 // Eager run to size the buffers, then capture.
 rn_status plan_build(rn_plan *pl, const Prepared &p, hipStream_t s, int64_t *offsets, int32_t *status) {
+    RN_TRY(ensure_gslots(pl->ws, pl->g->Vmax, kDefaultSlots));
     const rn_status st = run_eager(pl->g, pl->ws, p, pl->out, pl->cap, offsets, status, s, false);
     if (st != RN_OK && st != RN_ERR_CAPACITY && st != RN_ERR_ARG) return st;
     RN_TRY(capture_plan(pl, p));

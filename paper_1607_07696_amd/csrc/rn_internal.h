@@ -61,7 +61,8 @@ struct QueryDesc {
     uint32_t sbits;             // word offset of the query's S bitmap in the S-bitmap pool
     uint32_t rbits;             // word offset of the query's rank bitmap in the rank-bitmap pool
     uint32_t hist;              // k > 0: word offset of its histogram region in the histogram pool
-    uint32_t pad[2];
+    uint32_t gdelta;            // bucket width of the global-memory tier (>= 1)
+    uint32_t pad;
 };
 static_assert(sizeof(QueryDesc) == 64, "QueryDesc is 64 bytes");
 
@@ -140,10 +141,12 @@ struct JoinArgs {
 };
 
 // Per-source state of the global-memory tier, one slot per concurrent block:
-// dist[V] | queue stamp[V] | frontier[V] | next frontier[V] | touched[V], V the
-// largest graph's vertex count.  Between searches dist is all kInf and every
-// stamp zero.
-inline size_t global_slot_words(int32_t V) { return 5 * static_cast<size_t>(V); }
+// dist[V] | queue stamp[V] | frontier[V] | next frontier[V] | touched[V] |
+// far list[V] | far bitmap[ceil(V/32)], V the largest graph's vertex count.
+// Between searches dist is all kInf, every stamp zero and the bitmap clear.
+inline size_t global_slot_words(int32_t V) {
+    return 6 * static_cast<size_t>(V) + (static_cast<size_t>(V) + 31) / 32;
+}
 
 // Host-side description of the call buffers the launch sequence uses.
 struct CallBuffers {
@@ -179,8 +182,10 @@ hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, cons
                         const int32_t *order, hipStream_t s);
 size_t stage_scratch_words(size_t rwords);
 
-// Relaxation at the on-chip tier with table size 2^hash_log2; grid chosen inside.
-hipError_t launch_join(const JoinArgs &a, int hash_log2, uint32_t max_sources, hipStream_t s);
+// Relaxation at the on-chip tier with table size 2^hash_log2; grid chosen
+// inside.  generic = false: every source belongs to a theta-join (the kernel
+// variant without the k-closest-pairs code).
+hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, uint32_t max_sources, hipStream_t s);
 int join_tier_supported(int hash_log2);
 // The global-memory tier: one block per source, nslots slots of
 // global_slot_words(Vmax) words each.

@@ -169,10 +169,9 @@ struct SearchLds {
     static constexpr int PC = Tier<HB>::PC;
     uint32_t key[H];            // vertex id, or kEmpty
     uint32_t dw[H];             // distance word, kWordNone when empty
-    uint32_t ent[2][PC + 1];    // two vertex lists: slot | (arc count << 16) and first arc;
-    int32_t beg[2][PC + 1];     //   entry PC of each is a write sink for lanes with nothing to store
-    int32_t widx[kWin];         // window arc -> arc index
-    uint32_t wd[kWin];          // window arc -> distance of the arc's tail
+    uint2 lst[2][PC + 1];       // two vertex lists of {slot | (arc count << 16), first arc};
+                                //   entry PC of each is a write sink for lanes with nothing to store
+    uint2 win[kWin];            // window arc -> {arc index, distance of the arc's tail}
 };
 
 struct WaveState {
@@ -339,8 +338,8 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, ui
     for (int j = 0; j < NJ; ++j) {
         const bool app = stt[j] == 5u;
         const uint32_t idx = app ? base + mbcnt(mA[j]) : PC;
-        L.ent[P][idx] = h[j] | (static_cast<uint32_t>(r[j].yend - r[j].ybeg) << 16);
-        L.beg[P][idx] = r[j].ybeg;
+        L.lst[P][idx] = make_uint2(h[j] | (static_cast<uint32_t>(r[j].yend - r[j].ybeg) << 16),
+                                   static_cast<uint32_t>(r[j].ybeg));
         base += popc(mA[j]);
     }
     st.np = base;
@@ -359,8 +358,9 @@ __device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, uin
     for (int j = 0; j < NJ; ++j) {
         const uint32_t t = j * 64 + lane;
         const uint32_t tc = t < cnt ? t : 0u;
-        idx[j] = t < cnt ? L.widx[tc] : 0;
-        od[j] = L.wd[tc];
+        const uint2 w = L.win[tc];
+        idx[j] = t < cnt ? static_cast<int32_t>(w.x) : 0;
+        od[j] = w.y;
     }
     ArcRec r[NJ];
     uint32_t nd[NJ];
@@ -394,7 +394,7 @@ __device__ __forceinline__ unsigned long long reserve_recs(const JoinArgs &a, co
            readlane(static_cast<uint32_t>(base), 0);
 }
 
-// Write this wave's staged pairs (v in L.beg[0], dist in L.ent[0]) for source u.
+// Write this wave's staged pairs ({dist, v} in list 0) for source u.
 template <int HB>
 __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
                                             uint32_t &nst) {
@@ -406,8 +406,9 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
         if (idx < a.rec_cap) {
             Rec r;
             r.u = u - c.voff;
-            r.v = L.beg[0][i] - c.voff;
-            r.d = L.ent[0][i];
+            const uint2 e = L.lst[0][i];
+            r.v = static_cast<int32_t>(e.y) - c.voff;
+            r.d = e.x;
             r.q = c.q;
             a.recs[idx] = r;
         }
@@ -438,8 +439,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
         const uint32_t h0 = slot_hash<HB>(static_cast<uint32_t>(u));   // table is empty
         lds_store(&L.key[h0], static_cast<uint32_t>(u));
         L.dw[h0] = 1u;                                                // distance 0, pending
-        L.ent[0][0] = h0 | (static_cast<uint32_t>(min(ue - ub, 0xFFFF)) << 16);
-        L.beg[0][0] = ub;
+        L.lst[0][0] = make_uint2(h0 | (static_cast<uint32_t>(min(ue - ub, 0xFFFF)) << 16), static_cast<uint32_t>(ub));
     }
     wave_sync();
     WaveState st;
@@ -475,8 +475,8 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 const uint32_t i = base + lane;
                 const bool valid = i < st.np;
                 const uint32_t ic = valid ? i : 0u;
-                const uint32_t e = L.ent[P][ic];
-                const int32_t b = L.beg[P][ic];
+                const uint2 eb = L.lst[P][ic];
+                const uint32_t e = eb.x;
                 const uint32_t d = L.dw[e & 0xFFFFu] >> 1;
                 const bool isF = valid && d < thr && d <= bound;
                 const bool isK = valid && d >= thr && d <= bound;
@@ -485,11 +485,9 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 wave_sync();  // every lane has read its entry before the in-place compaction
                 atomicAnd(&L.dw[valid ? (e & 0xFFFFu) : lane], drop ? ~1u : 0xFFFFFFFFu);  // dropped: not pending
                 const uint32_t fi = isF ? nf + mbcnt(mF) : static_cast<uint32_t>(PC);
-                L.ent[F][fi] = e;
-                L.beg[F][fi] = b;
+                L.lst[F][fi] = eb;
                 const uint32_t ki = isK ? nk + mbcnt(mK) : static_cast<uint32_t>(PC);
-                L.ent[P][ki] = e;
-                L.beg[P][ki] = b;
+                L.lst[P][ki] = eb;
                 kmin = min(kmin, isK ? d : kInf);
                 nf += popc(mF);
                 nk += popc(mK);
@@ -503,8 +501,9 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
             const uint32_t f = fb + lane;
             const bool valid = f < nf;
             const uint32_t fc = valid ? f : 0u;
-            const uint32_t e = L.ent[F][fc];
-            const int32_t b = L.beg[F][fc];
+            const uint2 eb = L.lst[F][fc];
+            const uint32_t e = eb.x;
+            const int32_t b = static_cast<int32_t>(eb.y);
             const uint32_t s = e & 0xFFFFu;
             const uint32_t d = L.dw[s] >> 1;
             atomicAnd(&L.dw[valid ? s : lane], valid ? ~1u : 0xFFFFFFFFu);  // expanded now: not pending
@@ -515,8 +514,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
             for (uint32_t wb = 0; wb < total && !st.ovf; wb += kWin) {
                 const uint32_t lo = max(excl, wb), hi = min(excl + deg, wb + kWin);
                 for (uint32_t p = lo; p < hi; ++p) {
-                    L.widx[p - wb] = b + static_cast<int32_t>(p - excl);
-                    L.wd[p - wb] = d;
+                    L.win[p - wb] = make_uint2(static_cast<uint32_t>(b) + (p - excl), d);
                 }
                 wave_sync();
                 const uint32_t cnt = min(kWin, total - wb);
@@ -569,8 +567,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
             if (c.k && m) atomicAdd(&c.hist[kHistEmit + dist_bin(d[j])], 1u);
             emitted += popc(mM);
             const uint32_t idx = m ? nst + mbcnt(mM) : static_cast<uint32_t>(PC);
-            L.beg[0][idx] = static_cast<int32_t>(k[j]);
-            L.ent[0][idx] = d[j];
+            L.lst[0][idx] = make_uint2(d[j], k[j]);
             nst += popc(mM);
             if (nst + 64 > static_cast<uint32_t>(PC)) {
                 wave_sync();
@@ -611,8 +608,10 @@ __device__ __forceinline__ void launch_range(const JoinArgs &a, uint32_t &b, uin
 // One wavefront per block; the launch's sources split into 8 contiguous
 // chunks, chunk c taken by the blocks with blockIdx % 8 == c so that each XCD
 // (blocks are dealt to the 8 XCDs round-robin) sweeps one region of the
-// source order and keeps its part of the graph in its own L2.
-template <int HB>
+// source order and keeps its part of the graph in its own L2.  GEN = false:
+// every source belongs to a theta-join, and the k-closest-pairs code is
+// compiled out.
+template <int HB, bool GEN>
 __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
     __shared__ SearchLds<HB> L;
     constexpr int H = Tier<HB>::H;
@@ -628,21 +627,30 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
     for (uint32_t t = blockIdx.x; t < 8u * per; t += gridDim.x) {
         const uint32_t si = (t & 7u) * per + (t >> 3);
         if (si >= n) continue;
-        const SrcCtx c = load_ctx(a, a.srcq[b + si]);
+        SrcCtx c = load_ctx(a, a.srcq[b + si]);
+        if (!GEN) {
+            c.k = 0;
+            c.hist = nullptr;
+        }
         search_source<HB>(L, a, c, a.src[b + si]);
     }
 }
 
 // ------------------------------------------------------------------ global-memory tier
 // A search that outgrows every on-chip table runs here: one 1024-thread block
-// per source, its state in a dense per-slot area indexed by the local id,
-// frontier-synchronous (every vertex improved in a round is expanded in the
-// next).  Each round's arcs are flattened into windows of kGWin arcs, kGJ per
-// thread, whose loads and atomics are all issued before any result is used.
-// A vertex is queued for round r + 1 by raising its stamp to r + 1, so a
-// vertex improved while it is being expanded is queued again without a
-// clearing pass.  Only rare, very large searches (huge balls, expander graphs,
-// unbounded k-closest-pairs searches) take this path.
+// per source, its state in a dense per-slot area indexed by the local id.
+// Distances are settled bucket by bucket (near-far delta-stepping with the
+// query's gdelta): a round expands the near frontier (tentative distance below
+// the bucket's end), improved vertices join the next near frontier or the far
+// list; when no near vertex is left, the bucket end moves past the smallest
+// far distance and the far list is split.  Without buckets, a frontier-
+// synchronous search on a large road graph improves each vertex dozens of
+// times; with them, close to once.  Each round's arcs are flattened into
+// windows of kGWin arcs, kGJ per thread, whose loads and atomics are all
+// issued before any result is used.  A vertex is queued for round r + 1 by
+// raising its stamp to r + 1, so one improved while it is being expanded is
+// queued again without a clearing pass.  Only rare, very large searches (huge
+// balls, expander graphs, unbounded k-closest-pairs searches) take this path.
 constexpr uint32_t kGT = 1024;
 constexpr uint32_t kGJ = 4;
 constexpr uint32_t kGWin = kGT * kGJ;
@@ -686,7 +694,7 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
     __shared__ int32_t s_widx[kGWin];
     __shared__ uint32_t s_wd[kGWin];
     __shared__ uint32_t s_ws[kGT / 64];
-    __shared__ uint32_t s_nf, s_nfn, s_ntouched, s_bound, s_probing;
+    __shared__ uint32_t s_nf, s_nfn, s_ntouched, s_bound, s_probing, s_nfar, s_kept, s_dmin;
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     uint32_t sb, n;
     launch_range(a, sb, n);
@@ -696,6 +704,8 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
     uint32_t *fa = stamp + V;                            // global ids
     uint32_t *fb = fa + V;
     uint32_t *touched = fb + V;                          // local ids
+    uint32_t *far = touched + V;                         // local ids
+    uint32_t *farbits = far + V;                         // local ids
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const int32_t u = a.src[sb + i];
         const SrcCtx c = load_ctx(a, a.srcq[sb + i]);
@@ -707,14 +717,61 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
             touched[0] = static_cast<uint32_t>(u - c.voff);
             s_nf = 1;
             s_ntouched = 1;
+            s_nfar = 0;
         }
         __syncthreads();
         uint32_t *F = fa, *Fn = fb;
         uint32_t seen = 0, pnew = 0, round = 1;
+        const uint32_t gdelta = a.qd[c.q].gdelta;
+        uint32_t thr = gdelta;   // end of the current bucket (exclusive)
         bool probing = false;
         while (true) {
+            if (s_nf == 0) {
+                // no near vertex left: everything below thr is settled
+                const uint32_t nfar = s_nfar;
+                if (nfar == 0) break;
+                if (tid == 0) {
+                    s_dmin = kInf;
+                    s_kept = 0;
+                    s_bound = current_bound(c);
+                }
+                __syncthreads();
+                const uint32_t bound = s_bound;
+                uint32_t dmin = kInf;
+                for (uint32_t j = tid; j < nfar; j += kGT) {
+                    const uint32_t d = gload(&dist[far[j]]);
+                    if (d >= thr && d <= bound) dmin = min(dmin, d);
+                }
+                dmin = wave_min(dmin);
+                if (lane == 0 && dmin != kInf) atomicMin(&s_dmin, dmin);
+                __syncthreads();
+                const uint32_t told = thr;
+                if (s_dmin != kInf) {
+                    const uint64_t t = (static_cast<uint64_t>(s_dmin) / gdelta + 1ull) * gdelta;
+                    thr = t > kInf ? kInf : static_cast<uint32_t>(t);
+                }
+                // split the far list in place: settled or out of bound -> dropped,
+                // inside the new bucket -> near frontier, beyond it -> kept
+                for (uint32_t cb = 0; cb < nfar; cb += kGT) {
+                    const uint32_t j = cb + tid;
+                    const bool valid = j < nfar;
+                    const uint32_t yl = valid ? far[j] : 0u;
+                    const uint32_t d = valid ? gload(&dist[yl]) : kInf;
+                    __syncthreads();   // the chunk is read before kept entries overwrite it
+                    const bool near = valid && d >= told && d < thr && d <= bound;
+                    const bool keep = valid && d >= thr && d <= bound;
+                    if (valid && !keep) atomicAnd(&farbits[yl >> 5], ~(1u << (yl & 31u)));
+                    const uint32_t fi = block_append(near, &s_nf);
+                    if (near) F[fi] = yl + voff;
+                    const uint32_t ki = block_append(keep, &s_kept);
+                    if (keep) far[ki] = yl;
+                    __syncthreads();
+                }
+                if (tid == 0) s_nfar = s_kept;
+                __syncthreads();
+                continue;
+            }
             const uint32_t nf = s_nf;
-            if (nf == 0) break;
             __syncthreads();   // every thread has read s_nf
             if (tid < 64 && c.hist != nullptr) probe_phase(c, pnew, probing, seen);
             if (tid == 0) {
@@ -756,11 +813,13 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                         const uint32_t yl = static_cast<uint32_t>(r[j].y) - voff;
                         old[j] = nd[j] <= bound ? atomicMin(&dist[yl], nd[j]) : 0u;
                     }
-                    uint32_t qs[kGJ];
+                    uint32_t qs[kGJ], fo[kGJ];
 #pragma unroll
                     for (uint32_t j = 0; j < kGJ; ++j) {
                         const uint32_t yl = static_cast<uint32_t>(r[j].y) - voff;
-                        qs[j] = nd[j] < old[j] ? atomicMax(&stamp[yl], round + 1u) : round + 1u;
+                        const bool imp = nd[j] < old[j];
+                        qs[j] = imp && nd[j] < thr ? atomicMax(&stamp[yl], round + 1u) : round + 1u;
+                        fo[j] = imp && nd[j] >= thr ? atomicOr(&farbits[yl >> 5], 1u << (yl & 31u)) : ~0u;
                     }
 #pragma unroll
                     for (uint32_t j = 0; j < kGJ; ++j) {
@@ -777,6 +836,9 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                         const bool queue = qs[j] < round + 1u;
                         const uint32_t fi = block_append(queue, &s_nfn);
                         if (queue) Fn[fi] = static_cast<uint32_t>(r[j].y);
+                        const bool tofar = ((fo[j] >> (yl & 31u)) & 1u) == 0u;
+                        const uint32_t ri = block_append(tofar, &s_nfar);
+                        if (tofar) far[ri] = yl;
                     }
                 }
             }
@@ -1256,7 +1318,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const Rec *in, Rec *out, Call
     }
 }
 
-template <int HB>
+template <int HB, bool GEN>
 hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, hipStream_t s) {
     static int resident = 0;  // blocks per CU, per device this process uses first
     static int cus = 0;
@@ -1268,7 +1330,7 @@ hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, hipStream_t
         e = hipGetDeviceProperties(&prop, dev);
         if (e != hipSuccess) return e;
         int occ = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_join<HB>, 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_join<HB, GEN>, 64, 0);
         if (e != hipSuccess) return e;
         cus = prop.multiProcessorCount;
         resident = occ > 0 ? occ : 1;
@@ -1278,7 +1340,7 @@ hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, hipStream_t
     const uint64_t want = (static_cast<uint64_t>(max_sources) + 7) / 8 * 8;
     if (want < grid) grid = want;
     if (grid == 0) grid = 8;
-    hipLaunchKernelGGL(k_join<HB>, dim3(static_cast<uint32_t>(grid)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_join<HB, GEN>), dim3(static_cast<uint32_t>(grid)), dim3(64), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1308,17 +1370,21 @@ hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, cons
 
 int join_tier_supported(int hash_log2) { return hash_log2 >= kMinHB && hash_log2 <= kMaxHB; }
 
-hipError_t launch_join(const JoinArgs &a, int hash_log2, uint32_t max_sources, hipStream_t s) {
+hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, uint32_t max_sources, hipStream_t s) {
+#define RN_TIER(HB) \
+    case HB:        \
+        return generic ? launch_join_tier<HB, true>(a, max_sources, s) : launch_join_tier<HB, false>(a, max_sources, s);
     switch (hash_log2) {
-        case 8: return launch_join_tier<8>(a, max_sources, s);
-        case 9: return launch_join_tier<9>(a, max_sources, s);
-        case 10: return launch_join_tier<10>(a, max_sources, s);
-        case 11: return launch_join_tier<11>(a, max_sources, s);
-        case 12: return launch_join_tier<12>(a, max_sources, s);
-        case 13: return launch_join_tier<13>(a, max_sources, s);
-        case 14: return launch_join_tier<14>(a, max_sources, s);
+        RN_TIER(8)
+        RN_TIER(9)
+        RN_TIER(10)
+        RN_TIER(11)
+        RN_TIER(12)
+        RN_TIER(13)
+        RN_TIER(14)
         default: return hipErrorInvalidValue;
     }
+#undef RN_TIER
 }
 
 hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslots, int32_t Vmax,

@@ -26,6 +26,7 @@ EXPORTS = (
     "rn_last_error", "rn_version",
     "rn_graph_load_many", "rn_graph_count", "rn_graph_size", "rn_join_batch", "rn_autotune",
     "rn_plan_create", "rn_plan_run", "rn_plan_free",
+    "rn_server_create", "rn_server_submit", "rn_server_wait", "rn_server_get_stats", "rn_server_free",
 )
 RN_DELTA_DEFAULT = 0xFFFFFFFF
 MAX_DIST = 0xFFFFFFFE
@@ -42,6 +43,23 @@ class Query(C.Structure):
     _fields_ = [("R", C.c_void_p), ("S", C.c_void_p), ("nR", C.c_int32), ("nS", C.c_int32),
                 ("graph", C.c_int32), ("k", C.c_int32), ("theta", C.c_uint32), ("delta", C.c_uint32),
                 ("hash_log2", C.c_int32), ("reserved", C.c_int32)]
+
+
+class ServerConfig(C.Structure):
+    """struct rn_server_config (include/rn.h)."""
+    _fields_ = [("graph", C.c_int32), ("lanes", C.c_int32), ("max_batch", C.c_int32),
+                ("global_slots", C.c_int32), ("hbm_budget", C.c_int64)]
+
+
+class ServerStats(C.Structure):
+    """struct rn_server_stats (include/rn.h)."""
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
+                ("reruns", C.c_int64), ("peak_budget", C.c_int64), ("device_bytes", C.c_int64),
+                ("max_in_flight", C.c_int32), ("max_lanes_busy", C.c_int32), ("max_batch_seen", C.c_int32),
+                ("reserved", C.c_int32)]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
 
 
 class Stats(C.Structure):
@@ -93,12 +111,19 @@ def load_library(path: str = LIB_PATH):
     lib.rn_plan_run.argtypes = [vp, i64p, i32p, vp]
     lib.rn_plan_free.argtypes = [vp]
     lib.rn_plan_free.restype = None
+    lib.rn_server_create.argtypes = [vp, C.POINTER(ServerConfig), C.POINTER(vp)]
+    lib.rn_server_submit.argtypes = [vp, i32p, C.c_int32, i32p, C.c_int32, C.c_uint32, C.c_int32, i64p]
+    lib.rn_server_wait.argtypes = [vp, C.c_int64, vp, C.c_int64, i64p, C.POINTER(C.c_double)]
+    lib.rn_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
+    lib.rn_server_free.argtypes = [vp]
+    lib.rn_server_free.restype = None
     lib.rn_last_error.restype = C.c_char_p
     lib.rn_version.restype = C.c_char_p
     for name in ("rn_graph_load", "rn_graph_num_vertices", "rn_partition_host", "rn_partition",
                  "rn_dist_join", "rn_kcp_join", "rn_set_tuning", "rn_get_tuning",
                  "rn_set_profiling", "rn_last_stats", "rn_graph_load_many", "rn_graph_count",
-                 "rn_graph_size", "rn_join_batch", "rn_autotune", "rn_plan_create", "rn_plan_run"):
+                 "rn_graph_size", "rn_join_batch", "rn_autotune", "rn_plan_create", "rn_plan_run",
+                 "rn_server_create", "rn_server_submit", "rn_server_wait", "rn_server_get_stats"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -378,3 +403,53 @@ def split_batch(out, off) -> list[np.ndarray]:
     """Pairs tensor + offsets -> one structured numpy array per query."""
     a = pairs_to_numpy(out)
     return [a[int(off[i]):int(off[i + 1])] for i in range(len(off) - 1)]
+
+
+class Server:
+    """A request server on one graph of a handle (rn_server_*): submit host
+    node sets, wait for host results; batching and overlap happen inside."""
+
+    def __init__(self, net: RoadNetwork, graph: int = 0, lanes: int = 3, max_batch: int = 64,
+                 global_slots: int = 16, hbm_budget: int = 8 << 30):
+        self.net = net
+        cfg = ServerConfig(int(graph), int(lanes), int(max_batch), int(global_slots), int(hbm_budget))
+        h = C.c_void_p()
+        self._h = None
+        _check(load_library().rn_server_create(net._h, C.byref(cfg), C.byref(h)))
+        self._h = h
+
+    def submit(self, R, S, theta: int = MAX_DIST, k: int = 0) -> int:
+        Rh, Rp = _host(R, np.int32)
+        Sh, Sp = _host(S, np.int32)
+        rid = C.c_int64()
+        _check(load_library().rn_server_submit(self._h, Rp, Rh.shape[0], Sp, Sh.shape[0], int(theta), int(k),
+                                               C.byref(rid)))
+        return rid.value
+
+    def wait(self, rid: int, guess: int = 4096):
+        """Block until request rid is answered: (structured pair array, latency in ms)."""
+        lib = load_library()
+        n, lat = C.c_int64(), C.c_double()
+        out = np.empty(max(int(guess), 1), dtype=PAIR_DTYPE)
+        st = lib.rn_server_wait(self._h, int(rid), out.ctypes.data, out.shape[0], C.byref(n), C.byref(lat))
+        if st == RN_ERR_CAPACITY:
+            out = np.empty(n.value, dtype=PAIR_DTYPE)
+            st = lib.rn_server_wait(self._h, int(rid), out.ctypes.data, out.shape[0], C.byref(n), C.byref(lat))
+        _check(st, n.value)
+        return out[: n.value], lat.value
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        _check(load_library().rn_server_get_stats(self._h, C.byref(s)))
+        return s.as_dict()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().rn_server_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -121,3 +121,21 @@ def test_graph_load_many_names_the_bad_graph(rn, rg):
 def test_query_struct_layout(rn):
     assert C.sizeof(rn.Query) == 48
     assert rn.Query.nR.offset == 16 and rn.Query.hash_log2.offset == 40
+
+
+def test_server_calls_reject_bad_arguments_before_device(rn):
+    lib = rn.load_library()
+    h = C.c_void_p(1)
+    cfg = rn.ServerConfig(0, 2, 8, 4, 1 << 30)
+    assert lib.rn_server_create(None, C.byref(cfg), C.byref(h)) == rn.RN_ERR_ARG and not h.value
+    rid = C.c_int64(5)
+    R = np.array([1, 2], dtype=np.int32)
+    i32 = C.POINTER(C.c_int32)
+    assert lib.rn_server_submit(None, R.ctypes.data_as(i32), 2, R.ctypes.data_as(i32), 2, 10, 0,
+                                C.byref(rid)) == rn.RN_ERR_ARG
+    assert rid.value == 0
+    n = C.c_int64(3)
+    assert lib.rn_server_wait(None, 1, None, 0, C.byref(n), None) == rn.RN_ERR_ARG and n.value == 0
+    assert lib.rn_server_get_stats(None, None) == rn.RN_ERR_ARG
+    lib.rn_server_free(None)
+    assert C.sizeof(rn.ServerConfig) == 24 and C.sizeof(rn.ServerStats) == 64

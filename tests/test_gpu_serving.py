@@ -1,0 +1,135 @@
+"""GPU tests of the request server (continuous batching).
+
+Each request's result must be the same, bit for bit, when it runs alone and
+when it runs in a mix of concurrent requests, and equal to the oracle's
+answer for that request (tolerance 0).
+"""
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+MAX_DIST = 0xFFFFFFFE
+
+
+@pytest.fixture(scope="module")
+def rnmod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_1607_07696_amd import rn
+    rn.load_library()
+    return rn
+
+
+@pytest.fixture(scope="module")
+def graph(rg):
+    return rg.road_graph(256, 11)
+
+
+def make_requests(g, n, seed):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(n):
+        nR = int(np.exp(rng.uniform(np.log(16), np.log(2000))))
+        nS = int(np.exp(rng.uniform(np.log(16), np.log(2000))))
+        idx = rng.choice(g.V, size=nR + nS, replace=False).astype(np.int32)
+        if rng.random() < 0.4:
+            k = int(np.exp(rng.uniform(0, np.log(2000))))
+            theta = MAX_DIST if rng.random() < 0.7 else int(rng.integers(500, 6001))
+        else:
+            k, theta = 0, int(rng.integers(500, 6001))
+        reqs.append((idx[:nR].copy(), idx[nR:].copy(), theta, k))
+    return reqs
+
+
+def oracle_answer(orc, g, R, S, theta, k):
+    if k == 0:
+        return orc.dist_join(g, R, S, theta).pairs
+    if theta >= MAX_DIST:
+        return orc.kcp_join(g, R, S, k)
+    return orc.dist_join(g, R, S, theta).pairs[:k]
+
+
+def assert_same(got, want, what=""):
+    assert got.shape == want.shape, (what, got.shape, want.shape)
+    assert np.array_equal(got, want), what
+
+
+def test_alone_equals_mixed_equals_oracle(rnmod, orc, graph):
+    reqs = make_requests(graph, 40, 71)
+    net = rnmod.RoadNetwork.from_graph(graph)
+    alone = []
+    srv = rnmod.Server(net, lanes=1, max_batch=1)
+    for R, S, theta, k in reqs:
+        alone.append(srv.wait(srv.submit(R, S, theta, k))[0])
+    st = srv.stats()
+    srv.close()
+    assert st["batches"] == 40 and st["max_in_flight"] == 1
+    srv = rnmod.Server(net, lanes=3, max_batch=16)
+    ids = [srv.submit(R, S, theta, k) for R, S, theta, k in reqs]
+    mixed = [srv.wait(i)[0] for i in ids]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == 40 and st["batches"] < 40 and st["max_in_flight"] > 1
+    for i, (R, S, theta, k) in enumerate(reqs):
+        assert_same(mixed[i], alone[i], f"request {i}: mixed vs alone")
+        assert_same(alone[i], oracle_answer(orc, graph, R, S, theta, k), f"request {i}: vs oracle")
+
+
+def test_requests_arriving_later_overtake_a_long_one(rnmod, orc, graph, rg):
+    net = rnmod.RoadNetwork.from_graph(graph)
+    srv = rnmod.Server(net, lanes=2, max_batch=8)
+    Rh, Sh = rg.sample_disjoint(graph.V, 1000, 1000, 72)
+    heavy = srv.submit(Rh, Sh, MAX_DIST, 0)          # every pair: whole-graph searches
+    time.sleep(0.002)
+    light = [rg.sample_disjoint(graph.V, 50, 50, 73 + i) for i in range(6)]
+    ids = [srv.submit(R, S, 800, 0) for R, S in light]
+    lat_light = []
+    for (R, S), i in zip(light, ids):
+        got, lat = srv.wait(i)
+        lat_light.append(lat)
+        assert_same(got, orc.dist_join(graph, R, S, 800).pairs)
+    got, lat_heavy = srv.wait(heavy, guess=len(Rh) * len(Sh))
+    assert got.shape[0] == len(Rh) * len(Sh)
+    st = srv.stats()
+    srv.close()
+    assert max(lat_light) < lat_heavy
+    assert st["max_lanes_busy"] == 2
+
+
+def test_budget_limits_admission(rnmod, orc, graph):
+    reqs = make_requests(graph, 12, 74)
+    net = rnmod.RoadNetwork.from_graph(graph)
+    srv = rnmod.Server(net, lanes=3, max_batch=16, hbm_budget=1)
+    ids = [srv.submit(R, S, theta, k) for R, S, theta, k in reqs]
+    got = [srv.wait(i)[0] for i in ids]
+    st = srv.stats()
+    srv.close()
+    assert st["max_in_flight"] == 1 and st["max_batch_seen"] == 1
+    for i, (R, S, theta, k) in enumerate(reqs):
+        assert_same(got[i], oracle_answer(orc, graph, R, S, theta, k), f"request {i}")
+
+
+def test_invalid_request_fails_alone(rnmod, orc, graph, rg):
+    net = rnmod.RoadNetwork.from_graph(graph)
+    srv = rnmod.Server(net, lanes=1, max_batch=8)
+    R, S = rg.sample_disjoint(graph.V, 40, 40, 75)
+    Rbad = R.copy()
+    Rbad[0] = R[1]
+    ids = [srv.submit(R, S, 1500, 0), srv.submit(Rbad, S, 1500, 0), srv.submit(R, S, MAX_DIST, 7)]
+    assert_same(srv.wait(ids[0])[0], orc.dist_join(graph, R, S, 1500).pairs)
+    with pytest.raises(rnmod.RnError) as ei:
+        srv.wait(ids[1])
+    assert ei.value.status == rnmod.RN_ERR_ARG
+    assert_same(srv.wait(ids[2])[0], orc.kcp_join(graph, R, S, 7))
+    with pytest.raises(rnmod.RnError):
+        srv.submit(R, S, 1500, -1)
+    # the handle is held by the server until it is freed
+    with pytest.raises(rnmod.RnError) as ei:
+        net.dist_join(R, S, 100)
+    assert ei.value.status == rnmod.RN_ERR_BUSY
+    srv.close()
+    assert_same(rnmod.pairs_to_numpy(net.dist_join(R, S, 1500)), orc.dist_join(graph, R, S, 1500).pairs)
