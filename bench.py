@@ -232,7 +232,7 @@ def serve_leg(torch, rn, rate_hz=1000.0, count=2000):
     net = rn.RoadNetwork.from_graph(g)
     theta_of = [r.theta if r.k == 0 else MAX for r in reqs]
     # warm-up outside the timed stream
-    srv = rn.Server(net, lanes=4, max_batch=32, global_slots=16, hbm_budget=16 << 30)
+    srv = rn.Server(net, lanes=2, max_batch=8, global_slots=128, hbm_budget=16 << 30)
     for r, t in zip(reqs[:8], theta_of[:8]):
         srv.wait(srv.submit(r.R, r.S, t, r.k))
     ids = [None] * count
@@ -294,7 +294,7 @@ def serve_leg(torch, rn, rate_hz=1000.0, count=2000):
                          "graph (seed 0): 60% theta-joins with theta uniform in [500, 8000], 40% k closest "
                          "pairs with k log-uniform in [1, 4096]; |R|, |S| log-uniform in [64, 32768]"),
             "V": g.V, "A": g.A, "pairs": int(npairs), "work_arcs": arcs,
-            "server": {"lanes": 4, "max_batch": 32, "hbm_budget_gib": 16,
+            "server": {"lanes": 2, "max_batch": 8, "global_slots": 128, "hbm_budget_gib": 16,
                        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": pct(lat, 100)},
                        "throughput_rps": round(count / makespan, 1), "makespan_s": round(makespan, 3),
                        "gteps": round(arcs / makespan / 1e9, 3), "stats": st},
@@ -393,6 +393,19 @@ def main():
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     assert out.shape[0] == npairs
+    # the same query captured once into a HIP graph and replayed
+    q, keep = net.make_queries([{"R": Rd, "S": Sd, "theta": theta}])
+    plan = net.plan(q, cap=int(npairs) + 1024)
+    for _ in range(args.warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(args.steps):
+        pout, poff, _ = plan.run()
+    torch.cuda.synchronize()
+    plan_ms = (time.perf_counter() - t1) / args.steps * 1e3
+    assert int(poff[-1]) == npairs
+    plan.close()
     ms_step = wall / args.steps * 1e3
     gteps = arcs / (ms_step / 1e3) / 1e9
     relax_ms = float(np.mean(relax))
@@ -429,6 +442,7 @@ def main():
                       "sort_copy": round(float(np.mean(sort)), 4),
                       "total": round(float(np.mean(total)), 4)},
         "relax_gteps": round(arcs / (relax_ms / 1e3) / 1e9, 3),
+        "captured_plan": {"ms_per_step": round(plan_ms, 4), "gteps": round(arcs / (plan_ms / 1e3) / 1e9, 3)},
         "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
                        "p99": round(float(np.percentile(lat, 99)) * 1e3, 4)},
         "partition_s": None if part_s is None else round(part_s, 3),

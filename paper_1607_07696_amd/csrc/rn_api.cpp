@@ -163,19 +163,16 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
 
 rn_status ensure_gslots(Workspace &ws, int32_t Vmax, uint32_t nslots) {
     if (ws.d_gslots) return RN_OK;
-    // at most nslots concurrent global-tier searches, within 8 GiB
+    // at most nslots concurrent global-tier searches, within 48 GiB
     const size_t words = global_slot_words(Vmax);
-    size_t n = (size_t{8} << 30) / (4 * words);
+    size_t n = (size_t{48} << 30) / (4 * words);
     n = std::max<size_t>(1, std::min<size_t>(n, nslots));
     RN_HIP(dev_alloc(&ws.d_gslots, n * words), "allocating global search slots");
     ws.n_gslots = static_cast<uint32_t>(n);
     const size_t V = static_cast<size_t>(Vmax);
-    for (size_t i = 0; i < n; ++i) {
-        uint32_t *slot = ws.d_gslots + i * words;
-        RN_HIP(launch_fill_u32(slot, V, kInf, nullptr), "clearing search slots");
-        RN_HIP(launch_fill_u32(slot + V, V, 0u, nullptr), "clearing search slots");
-        RN_HIP(launch_fill_u32(slot + 6 * V, (V + 31) / 32, 0u, nullptr), "clearing search slots");
-    }
+    RN_HIP(launch_fill_u32(ws.d_gslots, n * V, kInf, nullptr), "clearing search slots");
+    RN_HIP(launch_fill_u32(ws.d_gslots + n * V, n * V + n * global_bitmap_words(Vmax), 0u, nullptr),
+           "clearing search slots");
     RN_HIP(hipDeviceSynchronize(), "clearing search slots");
     return RN_OK;
 }
@@ -303,7 +300,7 @@ static rn_status ensure_side_streams(Workspace &ws, size_t n) {
 // Enqueue the whole call on s (descriptors already on the device).  timed:
 // record the profiling events (never during graph capture).
 rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *out, int64_t cap, hipStream_t s,
-                       bool timed) {
+                       bool timed, bool shared) {
     const CallBuffers b = call_buffers(ws, p);
     record(g, ws, timed, EV_START, s);
     RN_HIP(launch_fill_u32(ws.d_block, p.zero_words, 0u, s), "clearing call state");
@@ -333,14 +330,15 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     // first tiers, one launch per table size; several run side by side
     const size_t ng = p.groups.size();
     if (ng > static_cast<size_t>(kSide) + 1) return fail(RN_ERR_DEVICE, "too many first-tier groups");
-    if (ng > 1) {
+    const bool fork = !shared && ng > 1;
+    if (fork) {
         RN_TRY(ensure_side_streams(ws, ng - 1));
         RN_HIP(hipEventRecord(ws.fork, s), "forking streams");
     }
     for (size_t gi = 0; gi < ng; ++gi) {
         const Group &gr = p.groups[gi];
-        hipStream_t st = gi == 0 ? s : ws.side[gi - 1];
-        if (gi > 0) RN_HIP(hipStreamWaitEvent(st, ws.fork, 0), "forking streams");
+        hipStream_t st = gi == 0 || !fork ? s : ws.side[gi - 1];
+        if (gi > 0 && fork) RN_HIP(hipStreamWaitEvent(st, ws.fork, 0), "forking streams");
         JoinArgs t = a;
         t.src = b.src;
         t.srcq = b.srcq;
@@ -352,10 +350,11 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.novf = &b.ctl->nlist[li];
         t.first_tier = 1;
         t.tier = 0;
-        RN_HIP(launch_join(t, gr.hb, gr.kcp, static_cast<uint32_t>(gr.sources), st), "launching the relaxation");
-        if (gi > 0) RN_HIP(hipEventRecord(ws.join[gi - 1], st), "joining streams");
+        RN_HIP(launch_join(t, gr.hb, gr.kcp, static_cast<uint32_t>(gr.sources), !shared, st),
+               "launching the relaxation");
+        if (gi > 0 && fork) RN_HIP(hipEventRecord(ws.join[gi - 1], st), "joining streams");
     }
-    for (size_t gi = 1; gi < ng; ++gi) RN_HIP(hipStreamWaitEvent(s, ws.join[gi - 1], 0), "joining streams");
+    for (size_t gi = 1; fork && gi < ng; ++gi) RN_HIP(hipStreamWaitEvent(s, ws.join[gi - 1], 0), "joining streams");
     record(g, ws, timed, EV_TIER0, s);
     // re-runs: 2^11-slot tables, 2^14-slot tables, then the global tier
     const uint32_t maxs = static_cast<uint32_t>(p.total_R);
@@ -372,7 +371,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.novf = &b.ctl->nlist[li + 1];
         t.first_tier = 0;
         t.tier = 1 + li;
-        RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, true, maxs, s), "launching the relaxation");
+        RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, true, maxs, !shared, s), "launching the relaxation");
     }
     {
         if (!ws.d_gslots) return fail(RN_ERR_DEVICE, "global search slots missing");
@@ -399,7 +398,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
 
 namespace {
 
-constexpr uint32_t kDefaultSlots = 64;   // global-tier slots of a handle's calls and of a plan
+constexpr uint32_t kDefaultSlots = 256;  // global-tier slots of a handle's calls and of a plan (one per CU)
 
 rn_status read_back(Workspace &ws, const Prepared &p, hipStream_t s) {
     const size_t bytes = sizeof(CallCtl) + static_cast<size_t>(p.nq) * sizeof(QueryState);

@@ -162,9 +162,11 @@ rn_status ensure_buffers(Workspace &ws, const Prepared &p);
 rn_status grow_recs(Workspace &ws, unsigned long long need);
 void fill_host_desc(const Prepared &p, uint8_t *h);
 // Enqueue a whole call on s (descriptors already on the device); timed:
-// record the profiling events of the handle.
+// record the profiling events of the handle; shared: the device is shared with
+// other streams (no side streams for the first-tier launches, one block per
+// source so that other streams' kernels interleave).
 rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *out, int64_t cap, hipStream_t s,
-                       bool timed);
+                       bool timed, bool shared = false);
 
 }  // namespace host
 }  // namespace rn

@@ -140,13 +140,14 @@ struct JoinArgs {
     int32_t count_work;         // 1: accumulate ctl->arcs / ctl->settled
 };
 
-// Per-source state of the global-memory tier, one slot per concurrent block:
-// dist[V] | queue stamp[V] | frontier[V] | next frontier[V] | touched[V] |
-// far list[V] | far bitmap[ceil(V/32)], V the largest graph's vertex count.
-// Between searches dist is all kInf, every stamp zero and the bitmap clear.
-inline size_t global_slot_words(int32_t V) {
-    return 6 * static_cast<size_t>(V) + (static_cast<size_t>(V) + 31) / 32;
-}
+// State of the global-memory tier: n slots (one per concurrent block), V the
+// largest graph's vertex count, laid out array by array across the slots:
+// dist[n][V] | queue stamp[n][V] | far bitmap[n][ceil(V/32)] | frontier[n][V] |
+// next frontier[n][V] | touched[n][V] | far list[n][V].  Between searches dist
+// is all kInf, every stamp zero and every far bitmap clear (the first three
+// arrays, cleared once at allocation).
+__host__ __device__ inline size_t global_bitmap_words(int32_t V) { return (static_cast<size_t>(V) + 31) / 32; }
+inline size_t global_slot_words(int32_t V) { return 6 * static_cast<size_t>(V) + global_bitmap_words(V); }
 
 // Host-side description of the call buffers the launch sequence uses.
 struct CallBuffers {
@@ -182,13 +183,15 @@ hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, cons
                         const int32_t *order, hipStream_t s);
 size_t stage_scratch_words(size_t rwords);
 
-// Relaxation at the on-chip tier with table size 2^hash_log2; grid chosen
-// inside.  generic = false: every source belongs to a theta-join (the kernel
-// variant without the k-closest-pairs code).
-hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, uint32_t max_sources, hipStream_t s);
+// Relaxation at the on-chip tier with table size 2^hash_log2.  generic =
+// false: every source belongs to a theta-join (the kernel variant without the
+// k-closest-pairs code).  persistent: a device-filling grid of blocks that
+// loop over the sources; else one block per source.
+hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, uint32_t max_sources, bool persistent,
+                       hipStream_t s);
 int join_tier_supported(int hash_log2);
 // The global-memory tier: one block per source, nslots slots of
-// global_slot_words(Vmax) words each.
+// global_slot_words(Vmax) words in the layout above.
 hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslots, int32_t Vmax,
                               uint32_t max_sources, hipStream_t s);
 

@@ -169,13 +169,17 @@ struct SearchLds {
     static constexpr int PC = Tier<HB>::PC;
     uint32_t key[H];            // vertex id, or kEmpty
     uint32_t dw[H];             // distance word, kWordNone when empty
-    uint2 lst[2][PC + 1];       // two vertex lists of {slot | (arc count << 16), first arc};
-                                //   entry PC of each is a write sink for lanes with nothing to store
+    uint2 lst[2][PC + 1];       // two vertex lists of {slot | (arc count << 16), first arc} (with
+                                //   delta = 0, one ring of 2 PC entries over the same words);
+                                //   the last entry is a write sink for lanes with nothing to store
     uint2 win[kWin];            // window arc -> {arc index, distance of the arc's tail}
 };
 
 struct WaveState {
-    uint32_t np;    // entries in the pending list
+    uint32_t np;    // entries queued (pending list, or the ring between head and tail)
+    uint32_t tail;  // flat list index of the next append (ring: unwrapped counter)
+    uint32_t amask; // append index mask (ring: its size - 1; pending list: all ones)
+    uint32_t cap;   // most entries the queue may hold
     uint32_t nins;  // table entries in use
     uint32_t imin;  // per-lane min of the distances improved this phase
     uint32_t pnew;  // k-closest pairs: discoveries counted this phase, not yet published
@@ -255,7 +259,7 @@ __device__ __forceinline__ void probe_phase(const SrcCtx &c, uint32_t &pnew, boo
 // the packed atomicMin.  Idle lanes issue no-op atomics instead of branching.
 // Called by all 64 lanes; st.ovf is wave-uniform afterwards.
 template <int HB, int NJ>
-__device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, uint32_t P, const SrcCtx &c,
+__device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, const SrcCtx &c,
                                              const ArcRec *r, const uint32_t *nd, uint32_t bound) {
     constexpr uint32_t H = Tier<HB>::H;
     constexpr uint32_t PC = Tier<HB>::PC;
@@ -329,26 +333,28 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, ui
             st.pnew += popc(__ballot(fresh));
         }
     }
-    if (__ballot(lost) != 0 || st.nins > (3u * H) / 4u || st.np + nadd > PC) {
+    if (__ballot(lost) != 0 || st.nins > (3u * H) / 4u || st.np + nadd > st.cap) {
         st.ovf = true;
         return;
     }
-    uint32_t base = st.np;
+    uint2 *q = &L.lst[0][0];
+    uint32_t base = st.tail;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const bool app = stt[j] == 5u;
-        const uint32_t idx = app ? base + mbcnt(mA[j]) : PC;
-        L.lst[P][idx] = make_uint2(h[j] | (static_cast<uint32_t>(r[j].yend - r[j].ybeg) << 16),
-                                   static_cast<uint32_t>(r[j].ybeg));
+        const uint32_t idx = app ? ((base + mbcnt(mA[j])) & st.amask) : 2u * PC + 1u;
+        q[idx] = make_uint2(h[j] | (static_cast<uint32_t>(r[j].yend - r[j].ybeg) << 16),
+                            static_cast<uint32_t>(r[j].ybeg));
         base += popc(mA[j]);
     }
-    st.np = base;
+    st.np += base - st.tail;
+    st.tail = base;
 }
 
 // Load window arcs j*64 + lane (j < NJ) and relax them.  Every load is issued
 // before any is used; lanes past the window's end load arc 0 and stay idle.
 template <int HB, int NJ>
-__device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, uint32_t P, const SrcCtx &c,
+__device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, const SrcCtx &c,
                                             const ArcRec *__restrict__ arcs, uint32_t cnt,
                                             uint32_t bound) {
     const uint32_t lane = lane_id();
@@ -369,7 +375,7 @@ __device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, uin
 #pragma unroll
     for (int j = 0; j < NJ; ++j) nd[j] = (j * 64 + lane < cnt) ? sat_add(od[j], r[j].w) : kInf;
     wave_sync();  // window map fully read before the next window rewrites it
-    relax_window<HB, NJ>(L, st, P, c, r, nd, bound);
+    relax_window<HB, NJ>(L, st, c, r, nd, bound);
 }
 
 // k-closest pairs: once the query has emitted k records, bound its k-th
@@ -417,16 +423,48 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
     nst = 0;
 }
 
+// Expand up to 64 queued vertices (one per lane: its list entry eb, valid):
+// clear their pending flags, then relax their arcs kWin at a time.  A
+// vertex's distance is read here, so improvements made since it was queued
+// are used.  Whole wave.
+template <int HB>
+__device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, const SrcCtx &c, const JoinArgs &a,
+                                             uint2 eb, bool valid, uint32_t bound) {
+    const uint32_t lane = lane_id();
+    const uint32_t e = eb.x;
+    const int32_t b = static_cast<int32_t>(eb.y);
+    const uint32_t sl = e & 0xFFFFu;
+    const uint32_t d = L.dw[valid ? sl : lane] >> 1;
+    atomicAnd(&L.dw[valid ? sl : lane], valid ? ~1u : 0xFFFFFFFFu);  // expanded now: not pending
+    const uint32_t deg = (valid && d <= bound) ? (e >> 16) : 0u;
+    const uint32_t incl = wave_incl_scan(deg);
+    const uint32_t excl = incl - deg;
+    const uint32_t total = readlane(incl, 63);
+    for (uint32_t wb = 0; wb < total && !st.ovf; wb += kWin) {
+        const uint32_t lo = max(excl, wb), hi = min(excl + deg, wb + kWin);
+        for (uint32_t p = lo; p < hi; ++p) L.win[p - wb] = make_uint2(static_cast<uint32_t>(b) + (p - excl), d);
+        wave_sync();
+        const uint32_t cnt = min(kWin, total - wb);
+        switch ((cnt + 63u) / 64u) {
+            case 1: window_step<HB, 1>(L, st, c, a.arcs, cnt, bound); break;
+            case 2: window_step<HB, 2>(L, st, c, a.arcs, cnt, bound); break;
+            case 3: window_step<HB, 3>(L, st, c, a.arcs, cnt, bound); break;
+            default: window_step<HB, 4>(L, st, c, a.arcs, cnt, bound); break;
+        }
+        wave_sync();
+    }
+}
+
 // Bounded search from u.  Bucket b holds tentative distances in
 // [b*delta, (b+1)*delta); each phase expands every pending vertex of the
 // lowest non-empty bucket and relaxes its arcs.  With delta <= the smallest
 // arc weight each vertex is expanded once, at its final distance (Dijkstra
-// order by buckets); a larger delta trades re-expansions for fewer phases, and
-// delta = 0 expands the whole pending set every phase (the pending list simply
-// becomes the next frontier).  A vertex's distance is read when its frontier
-// chunk is expanded, so improvements made earlier in the same phase are used
-// at once.  The search ends when nothing is pending; every table entry then
-// holds its exact distance, and entries in S become pairs.
+// order by buckets); a larger delta trades re-expansions for fewer phases.
+// delta = 0 has no buckets at all: the pending list is a FIFO ring, each step
+// expands the 64 oldest pending vertices, and the vertices they improve queue
+// up behind the rest at once, so no window waits for a phase to end.  The
+// search ends when nothing is pending; every table entry then holds its exact
+// distance, and entries in S become pairs.
 template <int HB>
 __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u) {
     constexpr int H = Tier<HB>::H;
@@ -446,31 +484,45 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
     st.np = 1;
     st.nins = 1;
     st.pnew = 0;
+    st.imin = kInf;
     st.ovf = (ue - ub) > 0xFFFF;
     st.probing = false;
-    uint32_t P = 0;      // list receiving appends (the pending list)
-    uint32_t pmin = 0;
     uint32_t bound = c.theta;
     uint32_t seen = 0, phase = 0;
 
-    while (st.np > 0 && !st.ovf) {
-        // small searches (the first two phases) never count discoveries
-        if (c.hist != nullptr && phase >= 2) probe_phase(c, st.pnew, st.probing, seen);
-        ++phase;
-        bound = current_bound(c);
-        uint32_t F, nf;
-        uint32_t kmin = kInf;
-        if (c.delta == 0) {
-            F = P;
-            nf = st.np;
-            P ^= 1u;
-            st.np = 0;
-        } else {
+    if (c.delta == 0) {
+        // one bucket: a FIFO ring of pending vertices; each step expands up to
+        // 64 of them, and vertices they improve join the ring at once
+        constexpr uint32_t RC = 2u * PC;
+        uint2 *q = &L.lst[0][0];
+        st.tail = 1;
+        st.amask = RC - 1u;
+        st.cap = RC;
+        uint32_t head = 0;
+        while (st.np > 0 && !st.ovf) {
+            // small searches (the first two steps) never count discoveries
+            if (c.hist != nullptr && phase >= 2) probe_phase(c, st.pnew, st.probing, seen);
+            ++phase;
+            bound = current_bound(c);
+            const uint32_t m = min(64u, st.np);
+            const bool valid = lane < m;
+            const uint2 eb = q[(head + lane) & (RC - 1u)];
+            head += m;
+            st.np -= m;
+            wave_sync();  // the taken entries are read before appends reuse their slots
+            expand_chunk<HB>(L, st, c, a, eb, valid, bound);
+        }
+    } else {
+        uint32_t P = 0;      // list receiving appends (the pending list)
+        uint32_t pmin = 0;
+        while (st.np > 0 && !st.ovf) {
+            if (c.hist != nullptr && phase >= 2) probe_phase(c, st.pnew, st.probing, seen);
+            ++phase;
+            bound = current_bound(c);
             const uint64_t t64 = (static_cast<uint64_t>(pmin / c.delta) + 1ull) * c.delta;
             const uint32_t thr = t64 > kInf ? kInf : static_cast<uint32_t>(t64);
-            F = P ^ 1u;
-            nf = 0;
-            uint32_t nk = 0;
+            const uint32_t F = P ^ 1u;
+            uint32_t nf = 0, nk = 0, kmin = kInf;
             for (uint32_t base = 0; base < st.np; base += 64) {
                 const uint32_t i = base + lane;
                 const bool valid = i < st.np;
@@ -493,42 +545,20 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 nk += popc(mK);
             }
             st.np = nk;
-        }
-        st.imin = kInf;
-        wave_sync();
-        // ---- expand the frontier, kWin arcs at a time
-        for (uint32_t fb = 0; fb < nf && !st.ovf; fb += 64) {
-            const uint32_t f = fb + lane;
-            const bool valid = f < nf;
-            const uint32_t fc = valid ? f : 0u;
-            const uint2 eb = L.lst[F][fc];
-            const uint32_t e = eb.x;
-            const int32_t b = static_cast<int32_t>(eb.y);
-            const uint32_t s = e & 0xFFFFu;
-            const uint32_t d = L.dw[s] >> 1;
-            atomicAnd(&L.dw[valid ? s : lane], valid ? ~1u : 0xFFFFFFFFu);  // expanded now: not pending
-            const uint32_t deg = (valid && d <= bound) ? (e >> 16) : 0u;
-            const uint32_t incl = wave_incl_scan(deg);
-            const uint32_t excl = incl - deg;
-            const uint32_t total = readlane(incl, 63);
-            for (uint32_t wb = 0; wb < total && !st.ovf; wb += kWin) {
-                const uint32_t lo = max(excl, wb), hi = min(excl + deg, wb + kWin);
-                for (uint32_t p = lo; p < hi; ++p) {
-                    L.win[p - wb] = make_uint2(static_cast<uint32_t>(b) + (p - excl), d);
-                }
-                wave_sync();
-                const uint32_t cnt = min(kWin, total - wb);
-                switch ((cnt + 63u) / 64u) {
-                    case 1: window_step<HB, 1>(L, st, P, c, a.arcs, cnt, bound); break;
-                    case 2: window_step<HB, 2>(L, st, P, c, a.arcs, cnt, bound); break;
-                    case 3: window_step<HB, 3>(L, st, P, c, a.arcs, cnt, bound); break;
-                    default: window_step<HB, 4>(L, st, P, c, a.arcs, cnt, bound); break;
-                }
-                wave_sync();
+            st.tail = P * (PC + 1u) + nk;
+            st.amask = 0xFFFFFFFFu;
+            st.cap = PC;
+            st.imin = kInf;
+            wave_sync();
+            for (uint32_t fb = 0; fb < nf && !st.ovf; fb += 64) {
+                const uint32_t f = fb + lane;
+                const bool valid = f < nf;
+                const uint2 eb = L.lst[F][valid ? f : 0u];
+                expand_chunk<HB>(L, st, c, a, eb, valid, bound);
             }
+            if (st.ovf) break;
+            pmin = min(wave_min(kmin), wave_min(st.imin));
         }
-        if (st.ovf) break;
-        if (c.delta != 0) pmin = min(wave_min(kmin), wave_min(st.imin));
     }
 
     // ---- emit table entries in S, and clear the table for the next source
@@ -689,7 +719,7 @@ __device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t *ws, ui
     return off + incl - v;
 }
 
-__global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slots, size_t slot_words,
+__global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slots, uint32_t nslots,
                                                       int32_t Vmax) {
     __shared__ int32_t s_widx[kGWin];
     __shared__ uint32_t s_wd[kGWin];
@@ -698,14 +728,15 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     uint32_t sb, n;
     launch_range(a, sb, n);
-    const size_t V = static_cast<size_t>(Vmax);
-    uint32_t *dist = slots + blockIdx.x * slot_words;    // local ids
-    uint32_t *stamp = dist + V;                          // local ids: round a vertex is queued for
-    uint32_t *fa = stamp + V;                            // global ids
-    uint32_t *fb = fa + V;
-    uint32_t *touched = fb + V;                          // local ids
-    uint32_t *far = touched + V;                         // local ids
-    uint32_t *farbits = far + V;                         // local ids
+    const size_t V = static_cast<size_t>(Vmax), NV = nslots * V, W = global_bitmap_words(Vmax);
+    const size_t k = blockIdx.x;
+    uint32_t *dist = slots + k * V;                                 // local ids
+    uint32_t *stamp = slots + NV + k * V;                           // local ids: round a vertex is queued for
+    uint32_t *farbits = slots + 2 * NV + k * W;                     // local ids
+    uint32_t *fa = slots + 2 * NV + nslots * W + k * V;             // global ids
+    uint32_t *fb = fa + NV;
+    uint32_t *touched = fb + NV;                                    // local ids
+    uint32_t *far = touched + NV;                                   // local ids
     for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
         const int32_t u = a.src[sb + i];
         const SrcCtx c = load_ctx(a, a.srcq[sb + i]);
@@ -1319,7 +1350,7 @@ __global__ __launch_bounds__(256) void k_sort_pass(const Rec *in, Rec *out, Call
 }
 
 template <int HB, bool GEN>
-hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, hipStream_t s) {
+hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, bool persistent, hipStream_t s) {
     static int resident = 0;  // blocks per CU, per device this process uses first
     static int cus = 0;
     if (resident == 0) {
@@ -1335,10 +1366,13 @@ hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, hipStream_t
         cus = prop.multiProcessorCount;
         resident = occ > 0 ? occ : 1;
     }
+    // persistent: as many blocks as fit on the device at once, each looping
+    // over sources; otherwise one block per source, so that the kernel's
+    // blocks are short and launches from other streams interleave with them
     uint64_t grid = static_cast<uint64_t>(cus) * resident;
     grid = (grid + 7) / 8 * 8;
     const uint64_t want = (static_cast<uint64_t>(max_sources) + 7) / 8 * 8;
-    if (want < grid) grid = want;
+    if (want < grid || !persistent) grid = want;
     if (grid == 0) grid = 8;
     hipLaunchKernelGGL((k_join<HB, GEN>), dim3(static_cast<uint32_t>(grid)), dim3(64), 0, s, a);
     return hipGetLastError();
@@ -1370,10 +1404,12 @@ hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, cons
 
 int join_tier_supported(int hash_log2) { return hash_log2 >= kMinHB && hash_log2 <= kMaxHB; }
 
-hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, uint32_t max_sources, hipStream_t s) {
-#define RN_TIER(HB) \
-    case HB:        \
-        return generic ? launch_join_tier<HB, true>(a, max_sources, s) : launch_join_tier<HB, false>(a, max_sources, s);
+hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, uint32_t max_sources, bool persistent,
+                       hipStream_t s) {
+#define RN_TIER(HB)                                                                   \
+    case HB:                                                                          \
+        return generic ? launch_join_tier<HB, true>(a, max_sources, persistent, s)    \
+                       : launch_join_tier<HB, false>(a, max_sources, persistent, s);
     switch (hash_log2) {
         RN_TIER(8)
         RN_TIER(9)
@@ -1391,7 +1427,7 @@ hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslot
                               uint32_t max_sources, hipStream_t s) {
     uint32_t grid = nslots < max_sources ? nslots : max_sources;
     if (grid == 0) grid = 1;
-    hipLaunchKernelGGL(k_join_global, dim3(grid), dim3(kGT), 0, s, a, slots, global_slot_words(Vmax), Vmax);
+    hipLaunchKernelGGL(k_join_global, dim3(grid), dim3(kGT), 0, s, a, slots, nslots, Vmax);
     return hipGetLastError();
 }
 

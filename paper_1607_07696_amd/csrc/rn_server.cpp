@@ -142,7 +142,11 @@ void fail_batch(rn_server *s, Lane &L, rn_status st, const std::string &msg) {
 }
 
 rn_status enqueue_lane(rn_server *s, Lane &L) {
-    RN_TRY(enqueue_call(s->g, L.ws, L.prep, L.d_out, static_cast<int64_t>(L.out_cap), L.stream, false));
+    // the device is shared with the other lanes: one stream per lane (side
+    // streams would share the few hardware queues with other lanes and
+    // serialise their kernels) and one block per source, so that the blocks
+    // of a long batch do not hold every CU until it ends
+    RN_TRY(enqueue_call(s->g, L.ws, L.prep, L.d_out, static_cast<int64_t>(L.out_cap), L.stream, false, true));
     const size_t bytes = sizeof(CallCtl) + static_cast<size_t>(L.prep.nq) * sizeof(QueryState);
     RN_HIP(hipMemcpyAsync(L.ws.h_state, L.ws.d_block, bytes, hipMemcpyDeviceToHost, L.stream), "reading the status");
     RN_HIP(hipEventRecord(L.ev_state, L.stream), "recording an event");

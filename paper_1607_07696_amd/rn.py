@@ -409,8 +409,8 @@ class Server:
     """A request server on one graph of a handle (rn_server_*): submit host
     node sets, wait for host results; batching and overlap happen inside."""
 
-    def __init__(self, net: RoadNetwork, graph: int = 0, lanes: int = 3, max_batch: int = 64,
-                 global_slots: int = 16, hbm_budget: int = 8 << 30):
+    def __init__(self, net: RoadNetwork, graph: int = 0, lanes: int = 2, max_batch: int = 8,
+                 global_slots: int = 128, hbm_budget: int = 8 << 30):
         self.net = net
         cfg = ServerConfig(int(graph), int(lanes), int(max_batch), int(global_slots), int(hbm_budget))
         h = C.c_void_p()
