@@ -143,10 +143,11 @@ def batch_leg(torch, rn, steps):
     a = rn.pairs_to_numpy(out)
     total_pairs = int(off[-1])
     # work: arcs out of every vertex within theta (theta-joins) or within the
-    # k-th distance (k-closest pairs) of each source
+    # k-th distance (k-closest pairs) of each source in R (searches forced to
+    # run from R, whichever side the library would search from)
     wspecs = []
     for i, x in enumerate(inst):
-        sp = dict(specs[i])
+        sp = dict(specs[i], forward=True)
         if x.k:
             seg = a[off[i]:off[i + 1]]
             sp["k"], sp["theta"] = 0, int(seg["dist"][-1]) if len(seg) else 0
@@ -278,12 +279,12 @@ def serve_leg(torch, rn, rate_hz=1000.0, count=2000):
         done = max(done, r.arrival_s) + s_
         plat.append((done - r.arrival_s) * 1e3)
     # work: arcs out of every vertex within theta (theta-joins) or within the
-    # k-th distance (k-closest pairs) of each source
+    # k-th distance (k-closest pairs) of each source in R
     log("serve: counting work")
     net.set_profiling(times=False, work=True)
     arcs = 0
     for c0 in range(0, count, 64):
-        specs = [{"R": r.R, "S": r.S, "k": 0, "theta": (dk if r.k else r.theta)}
+        specs = [{"R": r.R, "S": r.S, "k": 0, "theta": (dk if r.k else r.theta), "forward": True}
                  for r, dk in zip(reqs[c0:c0 + 64], dks[c0:c0 + 64])]
         net.join_batch(specs)
         arcs += int(net.stats()["arcs"])

@@ -214,8 +214,14 @@ typedef struct rn_query {
     uint32_t theta;
     uint32_t delta;
     int32_t hash_log2;
-    int32_t reserved;   /* set to 0 */
+    int32_t flags;      /* 0, or RN_QUERY_FORWARD */
 } rn_query;
+
+/* rn_query.flags: run the searches from R even when S is smaller.  By default
+ * a query whose S holds fewer vertices than its R searches from S over the
+ * reversed arcs (dist(u, v) is the same path read backwards); the result is
+ * identical either way.  Work counts (RN_PROFILE_WORK) follow the side searched. */
+#define RN_QUERY_FORWARD 1
 
 /*
  * rn_join_batch -- run nq queries (1 <= nq <= 65536) as one call.

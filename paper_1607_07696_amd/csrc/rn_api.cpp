@@ -68,6 +68,7 @@ rn_status check_queries(const rn_graph *g, const rn_query *q, int32_t nq, int32_
         else if (x.k < 0 || x.k > (1 << 24)) m = "k must be 0 (theta-join) or in [1, 2^24]";
         else if (x.theta > kMaxDist) m = "theta must be <= 2^32 - 2";
         else if (x.hash_log2 != 0 && !join_tier_supported(x.hash_log2)) m = "hash_log2 must be 0 or in [8, 14]";
+        else if (x.flags & ~RN_QUERY_FORWARD) m = "unknown query flags";
         if (status) status[i] = m ? RN_ERR_ARG : RN_OK;
         if (m && bad < 0) {
             bad = i;
@@ -94,7 +95,7 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         hb[i] = x.hash_log2 ? x.hash_log2 : (x.k ? kMinHB : g->hash_log2);
         p.any_kcp |= x.k > 0;
         dmax = std::max(dmax, x.theta);
-        p.total_R += static_cast<uint64_t>(x.nR);
+        p.total_R += static_cast<uint64_t>(std::max(x.nR, 0));
     }
     // staging order: grouped by first table size and kind, query order within a group
     for (int32_t i = 0; i < nq; ++i) p.perm[i] = static_cast<uint32_t>(i);
@@ -109,10 +110,14 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         const uint32_t words = static_cast<uint32_t>((static_cast<int64_t>(V) + 31) / 32);
         QueryDesc &d = p.qd[i];
         std::memset(&d, 0, sizeof(d));
-        d.R = x.R;
-        d.S = x.S;
-        d.nR = x.nR;
-        d.nS = x.nS;
+        // search from the smaller side: with fewer vertices in S than in R the
+        // searches run from S over the reversed arcs (pairs are turned back on emission)
+        const bool swap = g->can_swap && !(x.flags & RN_QUERY_FORWARD) && x.nS < x.nR;
+        d.R = swap ? x.S : x.R;
+        d.S = swap ? x.R : x.S;
+        d.nR = swap ? x.nS : x.nR;
+        d.nS = swap ? x.nR : x.nS;
+        d.orient = swap ? (kOrientSwap | g->rev_rpo) : 0u;
         d.voff = g->voff[x.graph];
         d.V = V;
         d.theta = x.theta;
@@ -131,7 +136,7 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         if (p.groups.empty() || p.groups.back().hb != hb[i] || p.groups.back().kcp != (x.k > 0))
             p.groups.push_back(Group{hb[i], x.k > 0, s, s + 1, 0});
         p.groups.back().end = s + 1;
-        p.groups.back().sources += static_cast<uint64_t>(x.nR);
+        p.groups.back().sources += static_cast<uint64_t>(d.nR);
     }
     p.rbase[nq] = static_cast<uint32_t>(rw);
     p.total_elems = p.ebase[nq];
@@ -443,7 +448,14 @@ rn_status finish(rn_graph *g, Workspace &ws, const Prepared &p, int64_t cap, int
         st.relax_launches = static_cast<int32_t>(p.groups.size()) + (p.need_list0 ? 1 : 0) + (p.need_list1 ? 1 : 0) + 1;
     }
     int bad = -1;
+    uint32_t bad_err = 0;
     for (int32_t i = 0; i < p.nq; ++i) {
+        if (qs[i].err && bad < 0) {
+            bad_err = qs[i].err;
+            if (p.qd[i].orient & kOrientSwap)   // duplicates were found in the swapped sets
+                bad_err = (bad_err & ~(kErrDupR | kErrDupS)) | ((bad_err & kErrDupR) ? kErrDupS : 0u) |
+                          ((bad_err & kErrDupS) ? kErrDupR : 0u);
+        }
         if (offsets) offsets[i] = static_cast<int64_t>(qs[i].off);
         if (status) status[i] = qs[i].err ? RN_ERR_ARG : RN_OK;
         if (qs[i].err && bad < 0) bad = i;
@@ -452,7 +464,7 @@ rn_status finish(rn_graph *g, Workspace &ws, const Prepared &p, int64_t cap, int
     if (c.nout > static_cast<unsigned long long>(cap)) return fail(RN_ERR_CAPACITY, "output buffer too small");
     if (bad >= 0)
         return fail(RN_ERR_ARG, (p.nq > 1 ? "query " + std::to_string(bad) + ": " : std::string()) +
-                                    "invalid node sets:" + describe_err(qs[bad].err));
+                                    "invalid node sets:" + describe_err(bad_err));
     return RN_OK;
 }
 
@@ -590,17 +602,58 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
         g->gdelta[i] = static_cast<uint32_t>(std::min(std::max(gd, 1.0), 2147483648.0));
     }
     g->row_ptr[totV] = static_cast<int32_t>(totA);
+    // the reversed arcs (transpose), used when a query's S is smaller than its
+    // R: the searches then run from S.  Symmetric graphs are their own
+    // transpose and keep one copy.
+    std::vector<int32_t> rrow(static_cast<size_t>(totV) + 1, 0), rcol;
+    std::vector<uint32_t> rw;
+    bool symmetric = true;
+    try {
+        rcol.resize(static_cast<size_t>(totA));
+        rw.resize(static_cast<size_t>(totA));
+    } catch (...) {
+        delete g;
+        return fail(RN_ERR_NOMEM, "transposing the CSR");
+    }
+    for (int64_t a = 0; a < totA; ++a) rrow[g->col[a] + 1] += 1;
+    for (int32_t x = 0; x < totV; ++x) rrow[x + 1] += rrow[x];
+    {
+        std::vector<int32_t> fill(rrow.begin(), rrow.end() - 1);
+        for (int32_t x = 0; x < totV; ++x)
+            for (int32_t a = g->row_ptr[x]; a < g->row_ptr[x + 1]; ++a) {
+                const int32_t b = fill[g->col[a]]++;
+                rcol[b] = x;
+                rw[b] = g->w[a];
+            }
+    }
+    symmetric = rrow == g->row_ptr && rcol == g->col && rw == g->w;
+    const bool keep_rev = !symmetric && 2 * totA < 0x7FFFFFFFLL;
+    g->can_swap = symmetric || keep_rev;
+    g->rev_rpo = keep_rev ? static_cast<uint32_t>(totV + 1) : 0u;
+    const size_t nrow = (static_cast<size_t>(totV) + 1) * (keep_rev ? 2 : 1);
+    const size_t narc = static_cast<size_t>(totA) * (keep_rev ? 2 : 1);
+    std::vector<int32_t> rows(g->row_ptr);
+    try {
+        arcs.resize(narc);
+        if (keep_rev)
+            for (int32_t x = 0; x <= totV; ++x) rows.push_back(static_cast<int32_t>(totA) + rrow[x]);
+    } catch (...) {
+        delete g;
+        return fail(RN_ERR_NOMEM, "copying the CSR");
+    }
     for (int64_t a = 0; a < totA; ++a) {
         const int32_t y = g->col[a];
         arcs[a] = ArcRec{y, g->w[a], g->row_ptr[y], g->row_ptr[y + 1]};
     }
+    if (keep_rev)
+        for (int64_t b = 0; b < totA; ++b) {
+            const int32_t y = rcol[b];
+            arcs[totA + b] = ArcRec{y, rw[b], static_cast<int32_t>(totA) + rrow[y], static_cast<int32_t>(totA) + rrow[y + 1]};
+        }
     rn_status st = RN_OK;
-    if ((e = dev_alloc(&g->d_row_ptr, static_cast<size_t>(totV) + 1)) != hipSuccess ||
-        (e = dev_alloc(&g->d_arcs, static_cast<size_t>(totA))) != hipSuccess ||
-        (e = hipMemcpy(g->d_row_ptr, g->row_ptr.data(), (static_cast<size_t>(totV) + 1) * sizeof(int32_t),
-                       hipMemcpyHostToDevice)) != hipSuccess ||
-        (totA > 0 && (e = hipMemcpy(g->d_arcs, arcs.data(), static_cast<size_t>(totA) * sizeof(ArcRec),
-                                    hipMemcpyHostToDevice)) != hipSuccess)) {
+    if ((e = dev_alloc(&g->d_row_ptr, nrow)) != hipSuccess || (e = dev_alloc(&g->d_arcs, narc)) != hipSuccess ||
+        (e = hipMemcpy(g->d_row_ptr, rows.data(), nrow * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (narc > 0 && (e = hipMemcpy(g->d_arcs, arcs.data(), narc * sizeof(ArcRec), hipMemcpyHostToDevice)) != hipSuccess)) {
         st = hip_fail(e, "uploading the graph");
     }
     if (st != RN_OK) {

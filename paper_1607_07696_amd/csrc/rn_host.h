@@ -184,6 +184,8 @@ struct rn_graph {
     int32_t Vmax = 0;
     std::vector<int32_t> row_ptr, col;   // concatenated, global ids
     std::vector<uint32_t> w;
+    bool can_swap = false;          // searches may run from S (reversed arcs available)
+    uint32_t rev_rpo = 0;           // row pointer offset of the reversed arcs (0: the graphs are symmetric)
 
     int32_t *d_row_ptr = nullptr;
     rn::ArcRec *d_arcs = nullptr;

@@ -62,9 +62,12 @@ struct QueryDesc {
     uint32_t rbits;             // word offset of the query's rank bitmap in the rank-bitmap pool
     uint32_t hist;              // k > 0: word offset of its histogram region in the histogram pool
     uint32_t gdelta;            // bucket width of the global-memory tier (>= 1)
-    uint32_t pad;
+    uint32_t orient;            // bit 31: the caller's R and S are swapped here (the search runs
+                                // from S over the reversed arcs); bits 0-30: row pointer offset
+                                // of the arcs searched (0: the forward CSR)
 };
 static_assert(sizeof(QueryDesc) == 64, "QueryDesc is 64 bytes");
+constexpr uint32_t kOrientSwap = 1u << 31;
 
 // Per-query device state of one call.  Zeroed first.
 struct QueryState {
@@ -108,7 +111,9 @@ struct alignas(16) Rec {
 
 // One arc as the relaxation kernels read it: target, weight, and the target's
 // own arc range, so expanding a vertex needs no separate row_ptr lookup.
-// Vertex ids and arc indices are global across the resident graphs.
+// Vertex ids and arc indices are global across the resident graphs.  A handle
+// whose graphs are not symmetric also keeps the reversed arcs: row pointers
+// [V+1, 2V+2) and arcs [A, 2A) after the forward ones.
 struct alignas(16) ArcRec {
     int32_t y;
     uint32_t w;

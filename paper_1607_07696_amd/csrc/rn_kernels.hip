@@ -196,6 +196,8 @@ struct SrcCtx {
     int32_t voff;                   // first global id of the query's graph
     uint32_t q;
     uint32_t tier;
+    uint32_t rpo;                   // row pointer offset of the arcs searched
+    bool swapped;                   // the search runs from S: emitted pairs are reversed
     const uint32_t *sbits;          // the query's S bitmap (local ids)
     uint32_t *hist;                 // k > 0: the query's histogram region (else null)
     QueryState *qs;                 // the query's state
@@ -210,6 +212,8 @@ __device__ __forceinline__ SrcCtx load_ctx(const JoinArgs &a, uint32_t q) {
     c.voff = d.voff;
     c.q = q;
     c.tier = static_cast<uint32_t>(a.tier);
+    c.rpo = d.orient & ~kOrientSwap;
+    c.swapped = (d.orient & kOrientSwap) != 0;
     c.sbits = a.sbits + d.sbits;
     c.hist = d.k ? a.hists + d.hist : nullptr;
     c.qs = a.qs + q;
@@ -411,9 +415,10 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
         const unsigned long long idx = base + i;
         if (idx < a.rec_cap) {
             Rec r;
-            r.u = u - c.voff;
             const uint2 e = L.lst[0][i];
-            r.v = static_cast<int32_t>(e.y) - c.voff;
+            const int32_t from = u - c.voff, to = static_cast<int32_t>(e.y) - c.voff;
+            r.u = c.swapped ? to : from;
+            r.v = c.swapped ? from : to;
             r.d = e.x;
             r.q = c.q;
             a.recs[idx] = r;
@@ -471,8 +476,8 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
     constexpr int PC = Tier<HB>::PC;
     constexpr int U = Tier<HB>::U;
     const uint32_t lane = lane_id();
-    const int32_t ub = a.row_ptr[u];
-    const int32_t ue = a.row_ptr[u + 1];
+    const int32_t ub = a.row_ptr[c.rpo + u];
+    const int32_t ue = a.row_ptr[c.rpo + u + 1];
     if (lane == 0) {
         const uint32_t h0 = slot_hash<HB>(static_cast<uint32_t>(u));   // table is empty
         lds_store(&L.key[h0], static_cast<uint32_t>(u));
@@ -580,7 +585,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
 #pragma unroll
             for (int j = 0; j < U; ++j)
                 if (k[j] != kEmpty && d[j] <= bound) {
-                    warcs += static_cast<unsigned long long>(a.row_ptr[k[j] + 1] - a.row_ptr[k[j]]);
+                    warcs += static_cast<unsigned long long>(a.row_ptr[c.rpo + k[j] + 1] - a.row_ptr[c.rpo + k[j]]);
                     wsettled += 1;
                 }
         }
@@ -818,8 +823,9 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                 const bool valid = t < nf;
                 const uint32_t x = valid ? F[t] : 0u;
                 const uint32_t dx = valid ? gload(&dist[x - voff]) : kInf;
-                const int32_t beg = valid ? a.row_ptr[x] : 0;
-                const uint32_t deg = (valid && dx <= bound) ? static_cast<uint32_t>(a.row_ptr[x + 1] - beg) : 0u;
+                const int32_t beg = valid ? a.row_ptr[c.rpo + x] : 0;
+                const uint32_t deg =
+                    (valid && dx <= bound) ? static_cast<uint32_t>(a.row_ptr[c.rpo + x + 1] - beg) : 0u;
                 uint32_t total;
                 const uint32_t excl = block_scan_1024(deg, s_ws, &total);
                 for (uint32_t wb = 0; wb < total; wb += kGWin) {
@@ -899,7 +905,8 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                 gstore(&stamp[yl], 0u);
                 m = d <= bound && ((c.sbits[yl >> 5] >> (yl & 31u)) & 1u);
                 if (a.count_work && d <= bound) {
-                    warcs += static_cast<unsigned long long>(a.row_ptr[yl + voff + 1] - a.row_ptr[yl + voff]);
+                    warcs += static_cast<unsigned long long>(a.row_ptr[c.rpo + yl + voff + 1] -
+                                                             a.row_ptr[c.rpo + yl + voff]);
                     wsettled += 1;
                 }
             }
@@ -917,8 +924,8 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                 const unsigned long long idx = base + mbcnt(mm);
                 if (m && idx < a.rec_cap) {
                     Rec rr;
-                    rr.u = u - c.voff;
-                    rr.v = static_cast<int32_t>(yl);
+                    rr.u = c.swapped ? static_cast<int32_t>(yl) : u - c.voff;
+                    rr.v = c.swapped ? u - c.voff : static_cast<int32_t>(yl);
                     rr.d = d;
                     rr.q = c.q;
                     a.recs[idx] = rr;
@@ -1085,7 +1092,7 @@ __global__ void k_kcp_seed_hist(JoinArgs a) {
     if (c.k == 0) return;
     uint32_t *seed = c.hist + kHistSeed;
     const int32_t u = a.src[i];
-    const int32_t b = a.row_ptr[u], e = a.row_ptr[u + 1];
+    const int32_t b = a.row_ptr[c.rpo + u], e = a.row_ptr[c.rpo + u + 1];
     for (int32_t x = b; x < e; ++x) {
         const ArcRec r = a.arcs[x];
         if (!in_s(c, static_cast<uint32_t>(r.y))) continue;

@@ -29,6 +29,7 @@ EXPORTS = (
     "rn_server_create", "rn_server_submit", "rn_server_wait", "rn_server_get_stats", "rn_server_free",
 )
 RN_DELTA_DEFAULT = 0xFFFFFFFF
+RN_QUERY_FORWARD = 1
 MAX_DIST = 0xFFFFFFFE
 
 
@@ -42,7 +43,7 @@ class Query(C.Structure):
     """struct rn_query (include/rn.h)."""
     _fields_ = [("R", C.c_void_p), ("S", C.c_void_p), ("nR", C.c_int32), ("nS", C.c_int32),
                 ("graph", C.c_int32), ("k", C.c_int32), ("theta", C.c_uint32), ("delta", C.c_uint32),
-                ("hash_log2", C.c_int32), ("reserved", C.c_int32)]
+                ("hash_log2", C.c_int32), ("flags", C.c_int32)]
 
 
 class ServerConfig(C.Structure):
@@ -284,7 +285,8 @@ class RoadNetwork:
 
     # -------------------------------------------------------------- batches
     def make_queries(self, specs, keep: list | None = None):
-        """rn_query array from dicts {R, S, theta=MAX_DIST, k=0, graph=0, delta=None, hash_log2=0}.
+        """rn_query array from dicts {R, S, theta=MAX_DIST, k=0, graph=0, delta=None, hash_log2=0,
+        forward=False}.
 
         R and S become int32 device tensors, appended to ``keep`` (they must stay
         alive while the queries are used)."""
@@ -296,7 +298,8 @@ class RoadNetwork:
             d = sp.get("delta")
             arr[i] = Query(R.data_ptr(), S.data_ptr(), R.numel(), S.numel(), int(sp.get("graph", 0)),
                            int(sp.get("k", 0)), int(sp.get("theta", MAX_DIST)),
-                           RN_DELTA_DEFAULT if d is None else int(d), int(sp.get("hash_log2", 0)), 0)
+                           RN_DELTA_DEFAULT if d is None else int(d), int(sp.get("hash_log2", 0)),
+                           RN_QUERY_FORWARD if sp.get("forward") else 0)
         return arr, keep
 
     def _bout_buffer(self, n: int):

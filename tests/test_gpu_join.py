@@ -236,3 +236,31 @@ def test_profiling_stats(rnmod, rg, g64):
     st = net.stats()
     assert st["pairs"] == out.shape[0]
     assert st["relax_ms"] > 0 and st["total_ms"] >= st["relax_ms"]
+
+
+@pytest.mark.parametrize("graph", ["road", "directed"])
+def test_searches_from_the_smaller_side(rnmod, orc, rg, graph):
+    # |S| < |R|: the library searches from S over the reversed arcs; a directed
+    # graph with zero weights makes the reversal visible if it were wrong
+    if graph == "road":
+        g = rg.road_graph(96, 4)
+    else:
+        g = rg.random_digraph(3000, 12000, 31, wmin=1, wmax=60, zero_frac=0.2)
+    net = rnmod.RoadNetwork.from_graph(g)
+    R, S = rg.sample_disjoint(g.V, 900, 60, 32)
+    for theta in (0, 40, 1500, 0xFFFFFFFE):
+        want = orc.dist_join(g, R, S, theta).pairs
+        assert_same(gpu_join(rnmod, net, R, S, theta), want)
+        out, off, status = net.join_batch([{"R": R, "S": S, "theta": theta, "forward": True},
+                                           {"R": R, "S": S, "theta": theta}])
+        segs = rnmod.split_batch(out, off)
+        assert_same(segs[0], want)
+        assert_same(segs[1], want)
+    for k in (1, 77, 5000):
+        assert_same(rnmod.pairs_to_numpy(net.kcp_join(R, S, k)), orc.kcp_join(g, R, S, k))
+    # argument errors name the caller's sets
+    S2 = S.copy()
+    S2[1] = S2[0]
+    with pytest.raises(rnmod.RnError) as ei:
+        net.dist_join(R, S2, 100)
+    assert "duplicate in S" in str(ei.value)
