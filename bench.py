@@ -220,7 +220,7 @@ def batch_leg(torch, rn, steps):
     return res
 
 
-def serve_leg(torch, rn, rate_hz=1000.0, count=2000):
+def serve_leg(torch, rn, rate_hz=300.0, count=2000):
     """Poisson stream of joins on the resident 2048x2048 graph: the request
     server (continuous batching) against the same requests served one at a
     time, in arrival order, by the single-query calls."""

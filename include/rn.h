@@ -160,6 +160,8 @@ rn_status rn_kcp_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *
  *                (frontier-synchronous relaxation).  Default chosen at load.
  *   hash_log2    log2 of the per-source LDS table size tried first (8..14);
  *                sources whose search outgrows it are re-run with larger ones.
+ *                Until it is set, theta-joins start at 2^11 or at the size the
+ *                expected ball for their theta needs, whichever is larger.
  * Pass a negative value to keep a knob's current setting.
  */
 rn_status rn_set_tuning(rn_graph *g, int64_t delta, int32_t hash_log2);

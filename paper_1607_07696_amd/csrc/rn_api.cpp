@@ -81,6 +81,19 @@ rn_status check_queries(const rn_graph *g, const rn_query *q, int32_t nq, int32_
     return RN_OK;
 }
 
+// First on-chip table of a theta-join when the caller set none: the handle's
+// size, raised to hold 1.3x the expected ball (a planar road graph holds
+// about 2 (theta / mean arc weight)^2 vertices within theta; a table is
+// filled to 3/4).  Larger balls would overflow the small table and re-run.
+int first_table(const rn_graph *g, int32_t graph, uint32_t theta) {
+    if (!g->hash_auto) return g->hash_log2;
+    const double r = static_cast<double>(theta) / std::max(1.0, g->wmean[graph]);
+    const double need = 1.3 * 2.0 * r * r / 0.75;
+    int hb = g->hash_log2;
+    while (hb < kMaxHB && static_cast<double>(1u << hb) < need) ++hb;
+    return hb;
+}
+
 rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p) {
     p = Prepared{};
     p.nq = nq;
@@ -92,7 +105,7 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
     uint32_t dmax = 0;
     for (int32_t i = 0; i < nq; ++i) {
         const rn_query &x = q[i];
-        hb[i] = x.hash_log2 ? x.hash_log2 : (x.k ? kMinHB : g->hash_log2);
+        hb[i] = x.hash_log2 ? x.hash_log2 : (x.k ? kMinHB : first_table(g, x.graph, x.theta));
         p.any_kcp |= x.k > 0;
         dmax = std::max(dmax, x.theta);
         p.total_R += static_cast<uint64_t>(std::max(x.nR, 0));
@@ -572,6 +585,7 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
         g->aoff.assign(n + 1, 0);
         g->w_min.assign(n, 0);
         g->gdelta.assign(n, 1);
+        g->wmean.assign(n, 1.0);
         g->row_ptr.resize(static_cast<size_t>(totV) + 1);
         g->col.resize(static_cast<size_t>(totA));
         g->w.resize(static_cast<size_t>(totA));
@@ -598,7 +612,8 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
         // one per arc on road graphs at a few thousand rounds for a whole graph
         double wsum = 0;
         for (int64_t a = 0; a < A[i]; ++a) wsum += w[i][a];
-        const double gd = A[i] ? 8.0 * wsum / static_cast<double>(A[i]) : 1.0;
+        g->wmean[i] = A[i] ? std::max(1.0, wsum / static_cast<double>(A[i])) : 1.0;
+        const double gd = 8.0 * g->wmean[i];
         g->gdelta[i] = static_cast<uint32_t>(std::min(std::max(gd, 1.0), 2147483648.0));
     }
     g->row_ptr[totV] = static_cast<int32_t>(totA);
@@ -771,7 +786,10 @@ rn_status rn_set_tuning(rn_graph *g, int64_t delta, int32_t hash_log2) {
     if (delta > static_cast<int64_t>(kMaxDist)) return fail(RN_ERR_ARG, "delta out of range");
     if (hash_log2 >= 0 && !join_tier_supported(hash_log2)) return fail(RN_ERR_ARG, "hash_log2 must be in [8, 14]");
     if (delta >= 0) g->delta = static_cast<uint32_t>(delta);
-    if (hash_log2 >= 0) g->hash_log2 = hash_log2;
+    if (hash_log2 >= 0) {
+        g->hash_log2 = hash_log2;
+        g->hash_auto = false;
+    }
     return RN_OK;
 }
 

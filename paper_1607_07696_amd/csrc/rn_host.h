@@ -194,6 +194,8 @@ struct rn_graph {
 
     uint32_t delta = 0;
     int hash_log2 = 11;
+    bool hash_auto = true;          // no first table size set: theta-joins size it from theta
+    std::vector<double> wmean;      // per graph: mean arc weight
 
     rn::host::Workspace ws;
 
