@@ -148,7 +148,9 @@ __device__ __forceinline__ void lds_store(uint32_t *p, uint32_t v) {
 template <int HB>
 struct Tier {
     static constexpr int H = 1 << HB;
-    static constexpr int PC = HB <= 9 ? 128 : (HB <= 11 ? 256 : (HB == 12 ? 512 : 1024));
+    // list capacity: the ring (2 PC entries) holds a search's pending frontier; sized so that
+    // a 2^12 table fits 4 waves per CU and a 2^13 table 2
+    static constexpr int PC = HB <= 9 ? 128 : (HB <= 12 ? 256 : (HB == 13 ? 512 : 1024));
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
 };
 
