@@ -152,6 +152,11 @@ struct Tier {
     // a 2^12 table fits 4 waves per CU and a 2^13 table 2
     static constexpr int PC = HB <= 9 ? 128 : (HB <= 12 ? 256 : (HB == 13 ? 512 : 1024));
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
+    // vertices per ring step, in units of 64, and the window size: the large
+    // tables hold one or two waves per CU, so each of their steps keeps twice
+    // as many loads and atomics in flight
+    static constexpr int G = HB >= 13 ? 2 : 1;
+    static constexpr uint32_t W = kWin * G;
 };
 
 // Distance words: (distance << 1) | pending, the low bit set while the vertex
@@ -174,7 +179,7 @@ struct SearchLds {
     uint2 lst[2][PC + 1];       // two vertex lists of {slot | (arc count << 16), first arc} (with
                                 //   delta = 0, one ring of 2 PC entries over the same words);
                                 //   the last entry is a write sink for lanes with nothing to store
-    uint2 win[kWin];            // window arc -> {arc index, distance of the arc's tail}
+    uint2 win[Tier<HB>::W];     // window arc -> {arc index, distance of the arc's tail}
 };
 
 struct WaveState {
@@ -430,33 +435,56 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
     nst = 0;
 }
 
-// Expand up to 64 queued vertices (one per lane: its list entry eb, valid):
-// clear their pending flags, then relax their arcs kWin at a time.  A
-// vertex's distance is read here, so improvements made since it was queued
-// are used.  Whole wave.
-template <int HB>
+// Expand up to 64 G queued vertices (G per lane: list entries eb[g], valid[g]):
+// clear their pending flags, then relax their arcs, windows of 256 G at a
+// time.  A vertex's distance is read here, so improvements made since it was
+// queued are used.  Whole wave.
+template <int HB, int G>
 __device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, const SrcCtx &c, const JoinArgs &a,
-                                             uint2 eb, bool valid, uint32_t bound) {
+                                             const uint2 *eb, const bool *valid, uint32_t bound) {
+    constexpr uint32_t W = kWin * G;
     const uint32_t lane = lane_id();
-    const uint32_t e = eb.x;
-    const int32_t b = static_cast<int32_t>(eb.y);
-    const uint32_t sl = e & 0xFFFFu;
-    const uint32_t d = L.dw[valid ? sl : lane] >> 1;
-    atomicAnd(&L.dw[valid ? sl : lane], valid ? ~1u : 0xFFFFFFFFu);  // expanded now: not pending
-    const uint32_t deg = (valid && d <= bound) ? (e >> 16) : 0u;
-    const uint32_t incl = wave_incl_scan(deg);
-    const uint32_t excl = incl - deg;
+    uint32_t d[G], deg[G];
+    int32_t b[G];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int g = 0; g < G; ++g) {
+        const uint32_t e = eb[g].x;
+        const uint32_t sl = e & 0xFFFFu;
+        b[g] = static_cast<int32_t>(eb[g].y);
+        d[g] = L.dw[valid[g] ? sl : lane] >> 1;
+        atomicAnd(&L.dw[valid[g] ? sl : lane], valid[g] ? ~1u : 0xFFFFFFFFu);  // expanded now: not pending
+        deg[g] = (valid[g] && d[g] <= bound) ? (e >> 16) : 0u;
+        sum += deg[g];
+    }
+    const uint32_t incl = wave_incl_scan(sum);
     const uint32_t total = readlane(incl, 63);
-    for (uint32_t wb = 0; wb < total && !st.ovf; wb += kWin) {
-        const uint32_t lo = max(excl, wb), hi = min(excl + deg, wb + kWin);
-        for (uint32_t p = lo; p < hi; ++p) L.win[p - wb] = make_uint2(static_cast<uint32_t>(b) + (p - excl), d);
+    for (uint32_t wb = 0; wb < total && !st.ovf; wb += W) {
+        uint32_t first = incl - sum;   // this lane's entries occupy [first, incl) in order
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const uint32_t lo = max(first, wb), hi = min(first + deg[g], wb + W);
+            for (uint32_t p = lo; p < hi; ++p)
+                L.win[p - wb] = make_uint2(static_cast<uint32_t>(b[g]) + (p - first), d[g]);
+            first += deg[g];
+        }
         wave_sync();
-        const uint32_t cnt = min(kWin, total - wb);
+        const uint32_t cnt = min(W, total - wb);
         switch ((cnt + 63u) / 64u) {
             case 1: window_step<HB, 1>(L, st, c, a.arcs, cnt, bound); break;
             case 2: window_step<HB, 2>(L, st, c, a.arcs, cnt, bound); break;
             case 3: window_step<HB, 3>(L, st, c, a.arcs, cnt, bound); break;
-            default: window_step<HB, 4>(L, st, c, a.arcs, cnt, bound); break;
+            case 4: window_step<HB, 4>(L, st, c, a.arcs, cnt, bound); break;
+            default:
+                if constexpr (G > 1) {
+                    switch ((cnt + 63u) / 64u) {
+                        case 5: window_step<HB, 5>(L, st, c, a.arcs, cnt, bound); break;
+                        case 6: window_step<HB, 6>(L, st, c, a.arcs, cnt, bound); break;
+                        case 7: window_step<HB, 7>(L, st, c, a.arcs, cnt, bound); break;
+                        default: window_step<HB, 8>(L, st, c, a.arcs, cnt, bound); break;
+                    }
+                }
+                break;
         }
         wave_sync();
     }
@@ -511,13 +539,19 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
             if (c.hist != nullptr && phase >= 2) probe_phase(c, st.pnew, st.probing, seen);
             ++phase;
             bound = current_bound(c);
-            const uint32_t m = min(64u, st.np);
-            const bool valid = lane < m;
-            const uint2 eb = q[(head + lane) & (RC - 1u)];
+            constexpr int G = Tier<HB>::G;
+            const uint32_t m = min(64u * G, st.np);
+            uint2 eb[G];
+            bool valid[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) {
+                valid[g] = g * 64u + lane < m;
+                eb[g] = q[(head + g * 64u + lane) & (RC - 1u)];
+            }
             head += m;
             st.np -= m;
             wave_sync();  // the taken entries are read before appends reuse their slots
-            expand_chunk<HB>(L, st, c, a, eb, valid, bound);
+            expand_chunk<HB, G>(L, st, c, a, eb, valid, bound);
         }
     } else {
         uint32_t P = 0;      // list receiving appends (the pending list)
@@ -561,7 +595,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 const uint32_t f = fb + lane;
                 const bool valid = f < nf;
                 const uint2 eb = L.lst[F][valid ? f : 0u];
-                expand_chunk<HB>(L, st, c, a, eb, valid, bound);
+                expand_chunk<HB, 1>(L, st, c, a, &eb, &valid, bound);
             }
             if (st.ovf) break;
             pmin = min(wave_min(kmin), wave_min(st.imin));
