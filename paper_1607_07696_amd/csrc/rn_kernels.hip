@@ -392,9 +392,12 @@ __device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, con
 // k-closest pairs: once the query has emitted k records, bound its k-th
 // distance by its emitted-distance histogram and lower the shared bound.
 // Whole wave.
-__device__ __forceinline__ void tighten_bound(const SrcCtx &c) {
+// seen: the count at this wave's last recomputation for the query; the bound
+// is recomputed only once the count has grown by an eighth since then.
+__device__ __forceinline__ void tighten_bound(const SrcCtx &c, unsigned long long &seen) {
     const unsigned long long n = __hip_atomic_load(&c.qs->npairs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (n < c.k) return;
+    if (n < c.k || n < seen + (seen >> 3) + 1ull) return;
+    seen = n;
     const uint32_t b = wave_bound_from_hist(c.hist + kHistEmit, c.k);
     if ((threadIdx.x & 63u) == 0) atomicMin(&c.qs->bound, b);
 }
@@ -501,7 +504,8 @@ __device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, co
 // search ends when nothing is pending; every table entry then holds its exact
 // distance, and entries in S become pairs.
 template <int HB>
-__device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u) {
+__device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
+                              unsigned long long &tseen) {
     constexpr int H = Tier<HB>::H;
     constexpr int PC = Tier<HB>::PC;
     constexpr int U = Tier<HB>::U;
@@ -648,7 +652,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
     }
     wave_sync();
     flush_pairs<HB>(L, a, c, u, nst);
-    if (c.k && emitted != 0) tighten_bound(c);
+    if (c.k && emitted != 0) tighten_bound(c, tseen);
     if (a.count_work && !st.ovf) {
         for (int o = 32; o > 0; o >>= 1) {
             const uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(warcs & 0xFFFFFFFFull), o));
@@ -695,6 +699,8 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
         L.dw[i] = kWordNone;
     }
     wave_sync();
+    uint32_t tq = kInf;              // query of tseen
+    unsigned long long tseen = 0;    // its emitted count at this wave's last bound update
     for (uint32_t t = blockIdx.x; t < 8u * per; t += gridDim.x) {
         const uint32_t si = (t & 7u) * per + (t >> 3);
         if (si >= n) continue;
@@ -703,7 +709,11 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
             c.k = 0;
             c.hist = nullptr;
         }
-        search_source<HB>(L, a, c, a.src[b + si]);
+        if (c.q != tq) {
+            tq = c.q;
+            tseen = 0;
+        }
+        search_source<HB>(L, a, c, a.src[b + si], tseen);
     }
 }
 
@@ -981,7 +991,8 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
             }
         }
         __syncthreads();
-        if (c.k && tid < 64) tighten_bound(c);
+        unsigned long long tseen = 0;
+        if (c.k && tid < 64) tighten_bound(c, tseen);
         __syncthreads();   // the slot is clean before the next source starts
     }
 }
@@ -1121,23 +1132,44 @@ __global__ __launch_bounds__(1024) void k_rank_emit(CallBuffers b, const uint32_
 // dist(u, y) <= the lightest such arc's weight, so the bin edge where k of
 // these weights are reached bounds the k-th smallest distance.  A pair with
 // parallel arcs is counted once, at its first lightest arc.
-__global__ void k_kcp_seed_hist(JoinArgs a) {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= *a.send) return;
-    const SrcCtx c = load_ctx(a, a.srcq[i]);
-    if (c.k == 0) return;
-    uint32_t *seed = c.hist + kHistSeed;
-    const int32_t u = a.src[i];
-    const int32_t b = a.row_ptr[c.rpo + u], e = a.row_ptr[c.rpo + u + 1];
-    for (int32_t x = b; x < e; ++x) {
-        const ArcRec r = a.arcs[x];
-        if (!in_s(c, static_cast<uint32_t>(r.y))) continue;
-        bool first = true;
-        for (int32_t z = b; z < e && first; ++z) {
-            const ArcRec o = a.arcs[z];
-            if (o.y == r.y && (o.w < r.w || (o.w == r.w && z < x))) first = false;
+__global__ __launch_bounds__(256) void k_kcp_seed_hist(JoinArgs a) {
+    __shared__ uint32_t h[kDistBins];
+    const uint32_t n = *a.send;
+    const uint32_t first = blockIdx.x * blockDim.x;
+    if (first >= n) return;
+    const uint32_t i = first + threadIdx.x;
+    // sources are listed query by query, so the block's sources belong to one
+    // query when its first and last do: then count in LDS, one global atomic per bin
+    const uint32_t last = min(first + blockDim.x, n) - 1u;
+    const bool one = a.srcq[first] == a.srcq[last];
+    if (one) {
+        for (uint32_t j = threadIdx.x; j < kDistBins; j += blockDim.x) h[j] = 0;
+        __syncthreads();
+    }
+    if (i < n) {
+        const SrcCtx c = load_ctx(a, a.srcq[i]);
+        if (c.k != 0) {
+            uint32_t *seed = c.hist + kHistSeed;
+            const int32_t u = a.src[i];
+            const int32_t b = a.row_ptr[c.rpo + u], e = a.row_ptr[c.rpo + u + 1];
+            for (int32_t x = b; x < e; ++x) {
+                const ArcRec r = a.arcs[x];
+                if (!in_s(c, static_cast<uint32_t>(r.y))) continue;
+                bool lightest = true;
+                for (int32_t z = b; z < e && lightest; ++z) {
+                    const ArcRec o = a.arcs[z];
+                    if (o.y == r.y && (o.w < r.w || (o.w == r.w && z < x))) lightest = false;
+                }
+                if (lightest) atomicAdd(one ? &h[dist_bin(r.w)] : &seed[dist_bin(r.w)], 1u);
+            }
         }
-        if (first) atomicAdd(&seed[dist_bin(r.w)], 1u);
+    }
+    if (one) {
+        __syncthreads();
+        const SrcCtx c = load_ctx(a, a.srcq[first]);
+        if (c.k != 0)
+            for (uint32_t j = threadIdx.x; j < kDistBins; j += blockDim.x)
+                if (h[j]) atomicAdd(&c.hist[kHistSeed + j], h[j]);
     }
 }
 
