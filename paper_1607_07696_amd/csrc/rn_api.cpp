@@ -137,6 +137,7 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         d.k = static_cast<uint32_t>(x.k);
         d.delta = x.delta == RN_DELTA_DEFAULT ? g->delta : x.delta;
         d.gdelta = g->gdelta[x.graph];
+        d.wmin = g->w_min[x.graph];
         d.sbits = static_cast<uint32_t>(sw);
         d.rbits = static_cast<uint32_t>(rw);
         d.hist = x.k ? nkcp * kHistWords : 0;

@@ -65,8 +65,10 @@ struct QueryDesc {
     uint32_t orient;            // bit 31: the caller's R and S are swapped here (the search runs
                                 // from S over the reversed arcs); bits 0-30: row pointer offset
                                 // of the arcs searched (0: the forward CSR)
+    uint32_t wmin;              // lightest arc weight of the query's graph
+    uint32_t pad[3];
 };
-static_assert(sizeof(QueryDesc) == 64, "QueryDesc is 64 bytes");
+static_assert(sizeof(QueryDesc) == 80, "QueryDesc is 80 bytes");
 constexpr uint32_t kOrientSwap = 1u << 31;
 
 // Per-query device state of one call.  Zeroed first.

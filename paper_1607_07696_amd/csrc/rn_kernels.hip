@@ -204,6 +204,7 @@ struct SrcCtx {
     uint32_t q;
     uint32_t tier;
     uint32_t rpo;                   // row pointer offset of the arcs searched
+    uint32_t wmin;                  // lightest arc weight of the graph
     bool swapped;                   // the search runs from S: emitted pairs are reversed
     const uint32_t *sbits;          // the query's S bitmap (local ids)
     uint32_t *hist;                 // k > 0: the query's histogram region (else null)
@@ -220,6 +221,7 @@ __device__ __forceinline__ SrcCtx load_ctx(const JoinArgs &a, uint32_t q) {
     c.q = q;
     c.tier = static_cast<uint32_t>(a.tier);
     c.rpo = d.orient & ~kOrientSwap;
+    c.wmin = d.wmin;
     c.swapped = (d.orient & kOrientSwap) != 0;
     c.sbits = a.sbits + d.sbits;
     c.hist = d.k ? a.hists + d.hist : nullptr;
@@ -493,6 +495,48 @@ __device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, co
     }
 }
 
+// k-closest pairs with a bound below twice the lightest arc: every path of two
+// or more arcs is longer than the bound, so the pairs within it are exactly
+// the direct arcs from u into S no heavier than the bound, at the weight of
+// the lightest arc of each pair (parallel arcs: the first lightest).  The
+// source emits those without a search.  Whole wave.
+template <int HB>
+__device__ __forceinline__ void direct_pairs(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
+                                             unsigned long long &tseen) {
+    constexpr uint32_t PC = Tier<HB>::PC;
+    const uint32_t lane = lane_id();
+    const uint32_t bound = current_bound(c);
+    const int32_t ub = a.row_ptr[c.rpo + u], ue = a.row_ptr[c.rpo + u + 1];
+    uint32_t nst = 0, emitted = 0;
+    for (int32_t x0 = ub; x0 < ue; x0 += 64) {
+        const int32_t x = x0 + static_cast<int32_t>(lane);
+        bool m = false;
+        ArcRec r{0, 0, 0, 0};
+        if (x < ue) {
+            r = a.arcs[x];
+            m = r.w <= bound && in_s(c, static_cast<uint32_t>(r.y));
+            for (int32_t z = ub; z < ue && m; ++z) {
+                const ArcRec o = a.arcs[z];
+                if (o.y == r.y && (o.w < r.w || (o.w == r.w && z < x))) m = false;
+            }
+        }
+        const uint64_t mM = __ballot(m);
+        if (m) atomicAdd(&c.hist[kHistEmit + dist_bin(r.w)], 1u);
+        emitted += popc(mM);
+        const uint32_t idx = m ? nst + mbcnt(mM) : PC;
+        L.lst[0][idx] = make_uint2(r.w, static_cast<uint32_t>(r.y));
+        nst += popc(mM);
+        if (nst + 64 > PC) {
+            wave_sync();
+            flush_pairs<HB>(L, a, c, u, nst);
+        }
+    }
+    wave_sync();
+    flush_pairs<HB>(L, a, c, u, nst);
+    if (emitted != 0) tighten_bound(c, tseen);
+    wave_sync();
+}
+
 // Bounded search from u.  Bucket b holds tentative distances in
 // [b*delta, (b+1)*delta); each phase expands every pending vertex of the
 // lowest non-empty bucket and relaxes its arcs.  With delta <= the smallest
@@ -713,7 +757,11 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
             tq = c.q;
             tseen = 0;
         }
-        search_source<HB>(L, a, c, a.src[b + si], tseen);
+        if (GEN && c.k != 0 && !a.count_work &&
+            static_cast<uint64_t>(current_bound(c)) < 2ull * static_cast<uint64_t>(c.wmin))
+            direct_pairs<HB>(L, a, c, a.src[b + si], tseen);
+        else
+            search_source<HB>(L, a, c, a.src[b + si], tseen);
     }
 }
 

@@ -133,3 +133,22 @@ def test_invalid_request_fails_alone(rnmod, orc, graph, rg):
     assert ei.value.status == rnmod.RN_ERR_BUSY
     srv.close()
     assert_same(rnmod.pairs_to_numpy(net.dist_join(R, S, 1500)), orc.dist_join(graph, R, S, 1500).pairs)
+
+
+def test_config5_stream_sample_full_size(rnmod, orc, rg):
+    # the 2048x2048 serving workload, served as the benchmark serves it (2
+    # lanes, batches of up to 8): sampled requests the oracle answers in
+    # about a second (theta-joins and k closest pairs, either side smaller)
+    g = rg.road_graph(2048, 0)
+    reqs = rg.serving_stream(g, 2000, 300.0, 5)
+    sample = [1, 8, 9, 10, 11, 12, 14, 16, 18, 24, 26, 29, 35]
+    net = rnmod.RoadNetwork.from_graph(g)
+    srv = rnmod.Server(net, lanes=2, max_batch=8, global_slots=128)
+    ids = [srv.submit(reqs[i].R, reqs[i].S, reqs[i].theta if reqs[i].k == 0 else MAX_DIST, reqs[i].k)
+           for i in sample]
+    got = [srv.wait(x)[0] for x in ids]
+    srv.close()
+    for i, a in zip(sample, got):
+        r = reqs[i]
+        want = orc.kcp_join(g, r.R, r.S, r.k) if r.k else orc.dist_join(g, r.R, r.S, r.theta).pairs
+        assert_same(a, want, f"request {i}")
