@@ -160,6 +160,20 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         p.need_list0 |= gr.hb < kRetryHB1;
         p.need_list1 |= gr.hb < kMaxHB;
     }
+    // the bucket sort: theta-joins only, on graphs with varied weights, with
+    // at most kMaxBins (query, dist) bins in all
+    {
+        uint64_t nb = 0;
+        bool ok = !p.any_kcp;
+        p.binbase.assign(static_cast<size_t>(nq) + 1, 0);
+        for (int32_t i = 0; i < nq && ok; ++i) {
+            p.binbase[i] = static_cast<uint32_t>(nb);
+            nb += static_cast<uint64_t>(q[i].theta) + 1;
+            ok = nb <= kMaxBins && g->varied[q[i].graph];
+        }
+        p.nbins = ok ? static_cast<uint32_t>(nb) : 0u;
+        if (ok) p.binbase[nq] = p.nbins;
+    }
     p.qb = nq > 1 ? bitlen(static_cast<uint64_t>(nq - 1)) : 0u;
     p.vb = std::max<uint32_t>(1u, bitlen(static_cast<uint64_t>(std::max(g->Vmax - 1, 0))));
     p.max_passes = std::max<uint32_t>(1u, (p.qb + std::max<uint32_t>(bitlen(dmax), 1u) + 2u * p.vb + 7u) / 8u);
@@ -168,15 +182,19 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
     p.off_sbits = round_up(p.off_qs + static_cast<size_t>(nq) * (sizeof(QueryState) / 4), 64);
     p.off_rbits = round_up(p.off_sbits + sw, 64);
     p.off_hists = round_up(p.off_rbits + rw, 64);
-    p.off_sort = round_up(p.off_hists + static_cast<size_t>(nkcp) * kHistWords, 64);
+    p.off_bins = round_up(p.off_hists + static_cast<size_t>(nkcp) * kHistWords, 64);
+    p.off_sort = round_up(p.off_bins + (p.nbins ? bucket_words(p.nbins) : 0), 64);
     p.block_words = p.off_sort + sort_hist_words();
     // the pass-0 histogram is written whole and the digit totals before use;
-    // the histograms later passes accumulate start at zero
-    p.zero_words = p.off_sort + static_cast<size_t>(p.max_passes + 1) * 256u * 256u;
+    // the histograms later passes accumulate start at zero; the bucket sort
+    // needs only its bin counts cleared
+    p.zero_words = p.nbins ? p.off_bins + p.nbins
+                           : p.off_sort + static_cast<size_t>(p.max_passes + 1) * 256u * 256u;
     p.off_ebase = round_up(static_cast<size_t>(nq) * sizeof(QueryDesc), 16);
     p.off_rbase = round_up(p.off_ebase + static_cast<size_t>(nq + 1) * sizeof(unsigned long long), 16);
     p.off_perm = round_up(p.off_rbase + static_cast<size_t>(nq + 1) * sizeof(uint32_t), 16);
-    p.desc_bytes = p.off_perm + static_cast<size_t>(nq) * sizeof(uint32_t);
+    p.off_binbase = round_up(p.off_perm + static_cast<size_t>(nq) * sizeof(uint32_t), 16);
+    p.desc_bytes = p.off_binbase + (static_cast<size_t>(nq) + 1) * sizeof(uint32_t);
     return RN_OK;
 }
 
@@ -276,6 +294,7 @@ void fill_host_desc(const Prepared &p, uint8_t *h) {
     std::memcpy(h + p.off_ebase, p.ebase.data(), p.ebase.size() * sizeof(unsigned long long));
     std::memcpy(h + p.off_rbase, p.rbase.data(), p.rbase.size() * sizeof(uint32_t));
     std::memcpy(h + p.off_perm, p.perm.data(), p.perm.size() * sizeof(uint32_t));
+    std::memcpy(h + p.off_binbase, p.binbase.data(), p.binbase.size() * sizeof(uint32_t));
 }
 
 CallBuffers call_buffers(const Workspace &ws, const Prepared &p) {
@@ -285,6 +304,9 @@ CallBuffers call_buffers(const Workspace &ws, const Prepared &p) {
     b.ebase = reinterpret_cast<const unsigned long long *>(ws.d_desc + p.off_ebase);
     b.rbase = reinterpret_cast<const uint32_t *>(ws.d_desc + p.off_rbase);
     b.perm = reinterpret_cast<const uint32_t *>(ws.d_desc + p.off_perm);
+    b.binbase = reinterpret_cast<const uint32_t *>(ws.d_desc + p.off_binbase);
+    b.nbins = p.nbins;
+    b.bins = ws.d_block + p.off_bins;
     b.ctl = reinterpret_cast<CallCtl *>(ws.d_block);
     b.qs = reinterpret_cast<QueryState *>(ws.d_block + p.off_qs);
     b.sbits = ws.d_block + p.off_sbits;
@@ -406,8 +428,11 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     if (p.any_kcp) RN_HIP(launch_select(b, s), "selecting candidates");
     RN_HIP(launch_layout(b, p.any_kcp ? 1 : 0, p.qb, p.vb, s), "laying out the output");
     record(g, ws, timed, EV_SELECTED, s);
-    RN_HIP(launch_sort_out(b, p.any_kcp ? 1 : 0, p.max_passes, p.vb, out, static_cast<unsigned long long>(cap), s),
-           "sorting pairs");
+    if (p.nbins)
+        RN_HIP(launch_bucket_sort(b, out, static_cast<unsigned long long>(cap), s), "sorting pairs");
+    else
+        RN_HIP(launch_sort_out(b, p.any_kcp ? 1 : 0, p.max_passes, p.vb, out, static_cast<unsigned long long>(cap), s),
+               "sorting pairs");
     record(g, ws, timed, EV_DONE, s);
     return RN_OK;
 }
@@ -587,6 +612,7 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
         g->w_min.assign(n, 0);
         g->gdelta.assign(n, 1);
         g->wmean.assign(n, 1.0);
+        g->varied.assign(n, 0);
         g->row_ptr.resize(static_cast<size_t>(totV) + 1);
         g->col.resize(static_cast<size_t>(totA));
         g->w.resize(static_cast<size_t>(totA));
@@ -614,6 +640,12 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
         double wsum = 0;
         for (int64_t a = 0; a < A[i]; ++a) wsum += w[i][a];
         g->wmean[i] = A[i] ? std::max(1.0, wsum / static_cast<double>(A[i])) : 1.0;
+        {
+            std::vector<uint32_t> seen;
+            for (int64_t a = 0; a < A[i] && seen.size() < 16; ++a)
+                if (std::find(seen.begin(), seen.end(), w[i][a]) == seen.end()) seen.push_back(w[i][a]);
+            g->varied[i] = seen.size() >= 16 ? 1 : 0;
+        }
         const double gd = 8.0 * g->wmean[i];
         g->gdelta[i] = static_cast<uint32_t>(std::min(std::max(gd, 1.0), 2147483648.0));
     }

@@ -150,6 +150,10 @@ struct Prepared {
     size_t zero_words = 0;
     uint32_t sbits_words = 0, rbits_words = 0;
     size_t desc_bytes = 0, off_ebase = 0, off_rbase = 0, off_perm = 0;
+    // bucket sort (theta-join calls with few bins); nbins = 0: radix sort
+    uint32_t nbins = 0;
+    std::vector<uint32_t> binbase;
+    size_t off_bins = 0, off_binbase = 0;
 };
 
 std::string describe_err(uint32_t err);
@@ -196,6 +200,7 @@ struct rn_graph {
     int hash_log2 = 11;
     bool hash_auto = true;          // no first table size set: theta-joins size it from theta
     std::vector<double> wmean;      // per graph: mean arc weight
+    std::vector<char> varied;       // per graph: at least 16 distinct arc weights
 
     rn::host::Workspace ws;
 

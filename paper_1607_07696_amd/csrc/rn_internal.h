@@ -99,7 +99,8 @@ struct CallCtl {
     unsigned long long nout;    // pairs owed to the caller
     uint32_t sort_db;           // distance bits of the sort key
     uint32_t sort_passes;       // 8-bit digit passes the sort needs
-    uint32_t pad[2];
+    uint32_t nchunks;           // bucket sort: 64-record chunks over all bins
+    uint32_t pad;
 };
 static_assert(sizeof(CallCtl) == 80, "CallCtl is 80 bytes");
 
@@ -170,6 +171,9 @@ struct CallBuffers {
     uint32_t rwords;            // its words
     uint32_t *hists;            // histogram pool
     uint32_t *sort_hist;        // sort_hist_words() words
+    const uint32_t *binbase;    // bucket sort: [nq+1] first bin of each query (query order)
+    uint32_t nbins;             //   bins (query, dist); 0 when the call uses the radix sort
+    uint32_t *bins;             //   count[nbins] (zeroed) | start[nbins] | cursor[nbins] | chunk start[nbins+1]
     uint32_t *stage_scratch;    // stage_scratch_words(rwords) words
     int32_t *src;               // source list and its queries
     uint32_t *srcq;
@@ -222,5 +226,15 @@ hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_pass
                            rn_pair *out, unsigned long long user_cap, hipStream_t s);
 size_t sort_hist_words();
 constexpr uint32_t kSortPassesMax = 16;
+
+// Bucket sort, for calls of theta-joins only whose bins (query, dist), theta+1
+// per query, number at most kMaxBins: count records per bin, scan, scatter
+// them into their bins, then order each bin by (u, v) by counting the smaller
+// keys of its records, one wave per 64 of them, writing each query's output
+// segment as the radix sort's last pass does.  Work per bin grows with the
+// square of its size, so it is chosen only for graphs with varied weights.
+constexpr uint32_t kMaxBins = 65536;
+inline size_t bucket_words(uint32_t nbins) { return 4 * static_cast<size_t>(nbins) + 1; }
+hipError_t launch_bucket_sort(const CallBuffers &b, rn_pair *out, unsigned long long user_cap, hipStream_t s);
 
 }  // namespace rn

@@ -1472,6 +1472,96 @@ __global__ __launch_bounds__(256) void k_sort_pass(const Rec *in, Rec *out, Call
     }
 }
 
+// ---- bucket sort (theta-join calls with few distinct distances per query)
+__device__ __forceinline__ uint32_t rec_bin(const CallBuffers &b, const Rec &r) { return b.binbase[r.q] + r.d; }
+
+__global__ __launch_bounds__(256) void k_bucket_count(CallBuffers b) {
+    const unsigned long long n = b.ctl->nsel;
+    uint32_t *cnt = b.bins;
+    for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull)
+        atomicAdd(&cnt[rec_bin(b, b.recs[0][i])], 1u);
+}
+
+// One block: bin starts (exclusive prefix of the counts), scatter cursors and
+// the first 64-record chunk of each bin.
+__global__ __launch_bounds__(1024) void k_bucket_scan(CallBuffers b) {
+    __shared__ uint32_t wsum[16];
+    const uint32_t nb = b.nbins, tid = threadIdx.x;
+    const uint32_t *cnt = b.bins;
+    uint32_t *start = b.bins + nb, *cursor = b.bins + 2 * nb, *cstart = b.bins + 3 * nb;
+    const uint32_t per = (nb + 1023u) / 1024u, lo = min(nb, tid * per), hi = min(nb, lo + per);
+    uint32_t sr = 0, sc = 0;
+    for (uint32_t i = lo; i < hi; ++i) {
+        sr += cnt[i];
+        sc += (cnt[i] + 63u) / 64u;
+    }
+    uint32_t tr, tc;
+    uint32_t er = block_excl_scan_1024(sr, wsum, &tr);
+    uint32_t ec = block_excl_scan_1024(sc, wsum, &tc);
+    for (uint32_t i = lo; i < hi; ++i) {
+        start[i] = er;
+        cursor[i] = er;
+        cstart[i] = ec;
+        er += cnt[i];
+        ec += (cnt[i] + 63u) / 64u;
+    }
+    if (tid == 0) {
+        cstart[nb] = tc;
+        b.ctl->nchunks = tc;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bucket_scatter(CallBuffers b) {
+    const unsigned long long n = b.ctl->nsel;
+    uint32_t *cursor = b.bins + 2 * b.nbins;
+    for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) {
+        const Rec r = b.recs[0][i];
+        b.recs[1][atomicAdd(&cursor[rec_bin(b, r)], 1u)] = r;
+    }
+}
+
+// One wave per 64-record chunk of a bin: each record's place in the bin is the
+// number of the bin's records with a smaller (u, v) (keys are unique within a
+// query); the record goes to the caller's output at its query's offset.
+__global__ __launch_bounds__(256) void k_bucket_rank(CallBuffers b, rn_pair *out, unsigned long long user_cap) {
+    const CallCtl *ctl = b.ctl;
+    if (ctl->npairs > b.rec_cap || ctl->nout > user_cap) return;
+    const uint32_t nb = b.nbins, lane = lane_id();
+    const uint32_t *cnt = b.bins, *start = b.bins + nb, *cstart = b.bins + 3 * nb;
+    const uint32_t total = ctl->nchunks;
+    const uint32_t waves = gridDim.x * 4u;
+    for (uint32_t c = blockIdx.x * 4u + (threadIdx.x >> 6); c < total; c += waves) {
+        const uint32_t bin = seg_of(cstart, nb, c);
+        const uint32_t m = cnt[bin], s0 = start[bin];
+        const uint32_t j = (c - cstart[bin]) * 64u + lane;
+        const bool valid = j < m;
+        const Rec r = b.recs[1][s0 + (valid ? j : 0u)];
+        const uint32_t mu = static_cast<uint32_t>(r.u), mv = static_cast<uint32_t>(r.v);
+        uint32_t rank = 0;
+        for (uint32_t j0 = 0; j0 < m; j0 += 64u) {
+            const uint32_t jj = j0 + lane < m ? j0 + lane : j0;
+            const Rec o = b.recs[1][s0 + jj];
+            const uint32_t ou = static_cast<uint32_t>(o.u), ov = static_cast<uint32_t>(o.v);
+            const uint32_t lim = min(64u, m - j0);
+            for (uint32_t t = 0; t < lim; ++t) {
+                const uint32_t xu = readlane(ou, static_cast<int>(t)), xv = readlane(ov, static_cast<int>(t));
+                rank += (xu < mu || (xu == mu && xv < mv)) ? 1u : 0u;
+            }
+        }
+        if (valid) {
+            const QueryState &st = b.qs[r.q];
+            const unsigned long long rel = static_cast<unsigned long long>(s0 + rank) - st.start;
+            if (rel < st.nout) {
+                rn_pair pr;
+                pr.u = r.u;
+                pr.v = r.v;
+                pr.dist = r.d;
+                out[st.off + rel] = pr;
+            }
+        }
+    }
+}
+
 template <int HB, bool GEN>
 hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, bool persistent, hipStream_t s) {
     static int resident = 0;  // blocks per CU, per device this process uses first
@@ -1590,6 +1680,14 @@ hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_pass
         in = o;
         o = t;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_bucket_sort(const CallBuffers &b, rn_pair *out, unsigned long long user_cap, hipStream_t s) {
+    hipLaunchKernelGGL(k_bucket_count, dim3(1024), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, b);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(1024), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bucket_rank, dim3(1024), dim3(256), 0, s, b, out, user_cap);
     return hipGetLastError();
 }
 
