@@ -359,6 +359,8 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     a.ctl = b.ctl;
     a.recs = b.recs[0];
     a.rec_cap = b.rec_cap;
+    a.bins = p.nbins ? b.bins : nullptr;
+    a.binbase = b.binbase;
     a.count_work = g->count_work ? 1 : 0;
     if (p.any_kcp) {
         JoinArgs k = a;

@@ -143,6 +143,8 @@ struct JoinArgs {
     int32_t *ovf;               // where searches that outgrow this tier are queued
     uint32_t *ovfq;
     uint32_t *novf;
+    uint32_t *bins;             // bucket sort: per-bin record counts, kept as records are stored (else null)
+    const uint32_t *binbase;    //   first bin of each query
     int32_t first_tier;         // 1: count re-queued searches in ctl->nretry
     int32_t tier;               // 0 first table, 1 and 2 the re-run tables, 3 the global tier
     int32_t count_work;         // 1: accumulate ctl->arcs / ctl->settled
@@ -228,8 +230,9 @@ size_t sort_hist_words();
 constexpr uint32_t kSortPassesMax = 16;
 
 // Bucket sort, for calls of theta-joins only whose bins (query, dist), theta+1
-// per query, number at most kMaxBins: count records per bin, scan, scatter
-// them into their bins, then order each bin by (u, v) by counting the smaller
+// per query, number at most kMaxBins: the relaxation kernels count the records
+// per bin as they store them; scan, scatter the records into their bins, then
+// order each bin by (u, v) by counting the smaller
 // keys of its records, one wave per 64 of them, writing each query's output
 // segment as the radix sort's last pass does.  Work per bin grows with the
 // square of its size, so it is chosen only for graphs with varied weights.

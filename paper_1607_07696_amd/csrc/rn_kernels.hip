@@ -422,6 +422,7 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
                                             uint32_t &nst) {
     if (nst == 0) return;
     const unsigned long long base = reserve_recs(a, c, nst);
+    const uint32_t bin0 = a.bins ? a.binbase[c.q] : 0u;
     wave_sync();
     for (uint32_t i = lane_id(); i < nst; i += 64) {
         const unsigned long long idx = base + i;
@@ -434,6 +435,7 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
             r.d = e.x;
             r.q = c.q;
             a.recs[idx] = r;
+            if (a.bins) atomicAdd(&a.bins[bin0 + r.d], 1u);
         }
     }
     wave_sync();
@@ -1023,6 +1025,7 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                     rr.d = d;
                     rr.q = c.q;
                     a.recs[idx] = rr;
+                    if (a.bins) atomicAdd(&a.bins[a.binbase[c.q] + d], 1u);
                 }
             }
         }
@@ -1475,13 +1478,6 @@ __global__ __launch_bounds__(256) void k_sort_pass(const Rec *in, Rec *out, Call
 // ---- bucket sort (theta-join calls with few distinct distances per query)
 __device__ __forceinline__ uint32_t rec_bin(const CallBuffers &b, const Rec &r) { return b.binbase[r.q] + r.d; }
 
-__global__ __launch_bounds__(256) void k_bucket_count(CallBuffers b) {
-    const unsigned long long n = b.ctl->nsel;
-    uint32_t *cnt = b.bins;
-    for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull)
-        atomicAdd(&cnt[rec_bin(b, b.recs[0][i])], 1u);
-}
-
 // One block: bin starts (exclusive prefix of the counts), scatter cursors and
 // the first 64-record chunk of each bin.
 __global__ __launch_bounds__(1024) void k_bucket_scan(CallBuffers b) {
@@ -1684,7 +1680,6 @@ hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_pass
 }
 
 hipError_t launch_bucket_sort(const CallBuffers &b, rn_pair *out, unsigned long long user_cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_bucket_count, dim3(1024), dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, b);
     hipLaunchKernelGGL(k_bucket_scatter, dim3(1024), dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_bucket_rank, dim3(1024), dim3(256), 0, s, b, out, user_cap);
