@@ -362,6 +362,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     a.bins = p.nbins ? b.bins : nullptr;
     a.binbase = b.binbase;
     a.count_work = g->count_work ? 1 : 0;
+    a.big_deg = g->big_deg ? 1 : 0;
     if (p.any_kcp) {
         JoinArgs k = a;
         k.src = b.src;
@@ -677,6 +678,8 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
             }
     }
     symmetric = rrow == g->row_ptr && rcol == g->col && rw == g->w;
+    for (int32_t x = 0; x < totV && !g->big_deg; ++x)
+        g->big_deg = g->row_ptr[x + 1] - g->row_ptr[x] > 0xFFFF || rrow[x + 1] - rrow[x] > 0xFFFF;
     const bool keep_rev = !symmetric && 2 * totA < 0x7FFFFFFFLL;
     g->can_swap = symmetric || keep_rev;
     g->rev_rpo = keep_rev ? static_cast<uint32_t>(totV + 1) : 0u;

@@ -190,6 +190,7 @@ struct rn_graph {
     std::vector<uint32_t> w;
     bool can_swap = false;          // searches may run from S (reversed arcs available)
     uint32_t rev_rpo = 0;           // row pointer offset of the reversed arcs (0: the graphs are symmetric)
+    bool big_deg = false;           // some vertex has 2^16 or more arcs (forward or reversed)
 
     int32_t *d_row_ptr = nullptr;
     rn::ArcRec *d_arcs = nullptr;

@@ -148,6 +148,7 @@ struct JoinArgs {
     int32_t first_tier;         // 1: count re-queued searches in ctl->nretry
     int32_t tier;               // 0 first table, 1 and 2 the re-run tables, 3 the global tier
     int32_t count_work;         // 1: accumulate ctl->arcs / ctl->settled
+    int32_t big_deg;            // 1: some vertex has 2^16 or more arcs (searches reaching one move on)
 };
 
 // State of the global-memory tier: n slots (one per concurrent block), V the

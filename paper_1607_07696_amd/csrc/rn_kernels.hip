@@ -206,6 +206,7 @@ struct SrcCtx {
     uint32_t rpo;                   // row pointer offset of the arcs searched
     uint32_t wmin;                  // lightest arc weight of the graph
     bool swapped;                   // the search runs from S: emitted pairs are reversed
+    bool big_deg;                   // some vertex of the graph has 2^16 or more arcs
     const uint32_t *sbits;          // the query's S bitmap (local ids)
     uint32_t *hist;                 // k > 0: the query's histogram region (else null)
     QueryState *qs;                 // the query's state
@@ -223,6 +224,7 @@ __device__ __forceinline__ SrcCtx load_ctx(const JoinArgs &a, uint32_t q) {
     c.rpo = d.orient & ~kOrientSwap;
     c.wmin = d.wmin;
     c.swapped = (d.orient & kOrientSwap) != 0;
+    c.big_deg = a.big_deg != 0;
     c.sbits = a.sbits + d.sbits;
     c.hist = d.k ? a.hists + d.hist : nullptr;
     c.qs = a.qs + q;
@@ -278,48 +280,69 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, co
     constexpr uint32_t PC = Tier<HB>::PC;
     // slot states: 0 idle, 1 slot holds y, 2 slot claimed for y, 3 keep probing
     uint32_t h[NJ], stt[NJ], old[NJ];
-    bool big = false;
+    // a distance the packed word cannot hold (possible only when the bound
+    // itself is that large) sends the search on to the next tier
+    const uint32_t lim = min(bound, kPackMax);
+    bool lost = false;
+    if (bound > kPackMax) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) lost |= nd[j] <= bound && nd[j] > kPackMax;
+    }
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         // idle lanes aim their no-op atomics at distinct slots: a shared address would serialise
-        h[j] = nd[j] <= bound ? slot_hash<HB>(static_cast<uint32_t>(r[j].y)) : lane_id();
-        big |= nd[j] <= bound && nd[j] > kPackMax;
+        h[j] = nd[j] <= lim ? slot_hash<HB>(static_cast<uint32_t>(r[j].y)) : lane_id();
     }
 #pragma unroll
     for (int j = 0; j < NJ; ++j)
-        old[j] = atomicCAS(&L.key[h[j]], nd[j] <= bound ? kEmpty : kNoKey, static_cast<uint32_t>(r[j].y));
+        old[j] = atomicCAS(&L.key[h[j]], nd[j] <= lim ? kEmpty : kNoKey, static_cast<uint32_t>(r[j].y));
+    __builtin_amdgcn_sched_barrier(0);   // every claim is issued before the first result is used
     bool probe = false;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const uint32_t y = static_cast<uint32_t>(r[j].y);
-        stt[j] = nd[j] > bound ? 0u : (old[j] == kEmpty ? 2u : (old[j] == y ? 1u : 3u));
+        stt[j] = nd[j] > lim ? 0u : (old[j] == kEmpty ? 2u : (old[j] == y ? 1u : 3u));
         probe |= stt[j] == 3u;
     }
-    bool lost = big;
     if (__ballot(probe) != 0) {
+        // linear probing past an occupied home slot, in rounds: each round
+        // moves every slot still searching one place on and issues all their
+        // compare-and-swaps (no-ops for the rest) before any result is used.
+        // (Linear probing beats double hashing here: the ids of a ball are
+        // clustered, and multiplicative hashing spreads runs of them evenly.)
+        for (uint32_t round = 1;; ++round) {
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-            if (stt[j] == 3u) {  // linear probing past an occupied home slot
+            for (int j = 0; j < NJ; ++j) {
+                const bool act = stt[j] == 3u;
+                h[j] = act ? ((h[j] + 1u) & (H - 1)) : h[j];
+                old[j] = atomicCAS(&L.key[act ? h[j] : lane_id()], act ? kEmpty : kNoKey,
+                                   static_cast<uint32_t>(r[j].y));
+            }
+            bool more = false;
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
                 const uint32_t y = static_cast<uint32_t>(r[j].y);
-                uint32_t hh = h[j];
-                for (uint32_t q = 1; q < H; ++q) {
-                    hh = (hh + 1) & (H - 1);
-                    const uint32_t o = atomicCAS(&L.key[hh], kEmpty, y);
-                    if (o == kEmpty) { stt[j] = 2u; break; }
-                    if (o == y) { stt[j] = 1u; break; }
-                }
-                if (stt[j] == 3u) lost = true;
-                h[j] = hh;
+                if (stt[j] == 3u) stt[j] = old[j] == kEmpty ? 2u : (old[j] == y ? 1u : 3u);
+                more |= stt[j] == 3u;
+            }
+            if (__ballot(more) == 0) break;
+            if (round >= H) {   // every slot visited: the table is full
+                lost = lost || more;
+                break;
             }
         }
     }
+    uint32_t v[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const uint32_t v =
-            (stt[j] == 1u || stt[j] == 2u) && nd[j] <= kPackMax ? (nd[j] << 1) | 1u : kWordNone;
-        old[j] = atomicMin(&L.dw[h[j]], v);
+        v[j] = (stt[j] == 1u || stt[j] == 2u) ? (nd[j] << 1) | 1u : kWordNone;   // nd <= lim here
+        old[j] = atomicMin(&L.dw[h[j]], v[j]);
+    }
+    __builtin_amdgcn_sched_barrier(0);   // every min is issued before the first result is used
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
         // 4: improved a pending vertex; 5: improved an idle or new one, which this lane appends
-        stt[j] = (v < old[j]) ? ((old[j] == kWordNone || (old[j] & 1u) == 0u) ? 5u : 4u) : stt[j];
+        stt[j] = (v[j] < old[j]) ? ((old[j] == kWordNone || (old[j] & 1u) == 0u) ? 5u : 4u) : stt[j];
     }
     uint64_t mA[NJ];
     uint32_t nadd = 0;
@@ -329,7 +352,10 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, co
         st.imin = min(st.imin, imp ? nd[j] : kInf);
         mA[j] = __ballot(stt[j] == 5u);
         nadd += popc(mA[j]);
-        lost |= stt[j] == 5u && (r[j].yend - r[j].ybeg) > 0xFFFF;
+    }
+    if (c.big_deg) {   // list entries hold arc counts below 2^16
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) lost |= stt[j] == 5u && (r[j].yend - r[j].ybeg) > 0xFFFF;
     }
     uint32_t ins = 0;
 #pragma unroll
@@ -385,8 +411,9 @@ __device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, con
     uint32_t nd[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) r[j] = arcs[idx[j]];
+    // (idle lanes: all ones, by a mask rather than a branch, so that no load is deferred)
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) nd[j] = (j * 64 + lane < cnt) ? sat_add(od[j], r[j].w) : kInf;
+    for (int j = 0; j < NJ; ++j) nd[j] = sat_add(od[j], r[j].w) | (j * 64 + lane < cnt ? 0u : kInf);
     wave_sync();  // window map fully read before the next window rewrites it
     relax_window<HB, NJ>(L, st, c, r, nd, bound);
 }
