@@ -66,7 +66,9 @@ struct QueryDesc {
                                 // from S over the reversed arcs); bits 0-30: row pointer offset
                                 // of the arcs searched (0: the forward CSR)
     uint32_t wmin;              // lightest arc weight of the query's graph
-    uint32_t pad[3];
+    uint32_t slack;             // delta = 0: a step of the on-chip search puts back the vertices
+                                // more than this above its least distance (kInf: none)
+    uint32_t pad[2];
 };
 static_assert(sizeof(QueryDesc) == 80, "QueryDesc is 80 bytes");
 constexpr uint32_t kOrientSwap = 1u << 31;

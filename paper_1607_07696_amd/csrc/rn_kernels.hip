@@ -205,6 +205,7 @@ struct SrcCtx {
     uint32_t tier;
     uint32_t rpo;                   // row pointer offset of the arcs searched
     uint32_t wmin;                  // lightest arc weight of the graph
+    uint32_t slack;                 // delta = 0: how far above a step's least distance a vertex waits
     bool swapped;                   // the search runs from S: emitted pairs are reversed
     bool big_deg;                   // some vertex of the graph has 2^16 or more arcs
     const uint32_t *sbits;          // the query's S bitmap (local ids)
@@ -223,6 +224,7 @@ __device__ __forceinline__ SrcCtx load_ctx(const JoinArgs &a, uint32_t q) {
     c.tier = static_cast<uint32_t>(a.tier);
     c.rpo = d.orient & ~kOrientSwap;
     c.wmin = d.wmin;
+    c.slack = d.slack;
     c.swapped = (d.orient & kOrientSwap) != 0;
     c.big_deg = a.big_deg != 0;
     c.sbits = a.sbits + d.sbits;
@@ -469,16 +471,17 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
     nst = 0;
 }
 
-// Expand up to 64 G queued vertices (G per lane: list entries eb[g], valid[g]):
-// clear their pending flags, then relax their arcs, windows of 256 G at a
-// time.  A vertex's distance is read here, so improvements made since it was
-// queued are used.  Whole wave.
+// Expand up to 64 G queued vertices (G per lane: list entries eb[g], valid[g],
+// distances d[g] read from the table just before, so that improvements made
+// since a vertex was queued are used): clear their pending flags, then relax
+// their arcs, windows of 256 G at a time.  Whole wave.
 template <int HB, int G>
 __device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, const SrcCtx &c, const JoinArgs &a,
-                                             const uint2 *eb, const bool *valid, uint32_t bound) {
+                                             const uint2 *eb, const bool *valid, const uint32_t *d,
+                                             uint32_t bound) {
     constexpr uint32_t W = kWin * G;
     const uint32_t lane = lane_id();
-    uint32_t d[G], deg[G];
+    uint32_t deg[G];
     int32_t b[G];
     uint32_t sum = 0;
 #pragma unroll
@@ -486,7 +489,6 @@ __device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, co
         const uint32_t e = eb[g].x;
         const uint32_t sl = e & 0xFFFFu;
         b[g] = static_cast<int32_t>(eb[g].y);
-        d[g] = L.dw[valid[g] ? sl : lane] >> 1;
         atomicAnd(&L.dw[valid[g] ? sl : lane], valid[g] ? ~1u : 0xFFFFFFFFu);  // expanded now: not pending
         deg[g] = (valid[g] && d[g] <= bound) ? (e >> 16) : 0u;
         sum += deg[g];
@@ -628,7 +630,30 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
             head += m;
             st.np -= m;
             wave_sync();  // the taken entries are read before appends reuse their slots
-            expand_chunk<HB, G>(L, st, c, a, eb, valid, bound);
+            uint32_t dd[G];
+#pragma unroll
+            for (int g = 0; g < G; ++g) dd[g] = L.dw[valid[g] ? (eb[g].x & 0xFFFFu) : lane] >> 1;
+            if (c.slack != kInf) {
+                // a vertex far above the step's least distance goes back to
+                // the tail, still pending: its distance is likely to improve
+                // before it comes round again, which saves expanding it twice
+                uint32_t mn = kInf;
+#pragma unroll
+                for (int g = 0; g < G; ++g) mn = min(mn, valid[g] ? dd[g] : kInf);
+                const uint32_t lim = sat_add(wave_min(mn), c.slack);
+                uint32_t base = st.tail;
+#pragma unroll
+                for (int g = 0; g < G; ++g) {
+                    const bool later = valid[g] && dd[g] > lim && dd[g] <= bound;
+                    const uint64_t mL = __ballot(later);
+                    q[later ? ((base + mbcnt(mL)) & (RC - 1u)) : RC + 1u] = eb[g];
+                    base += popc(mL);
+                    valid[g] = valid[g] && !later;
+                }
+                st.np += base - st.tail;
+                st.tail = base;
+            }
+            expand_chunk<HB, G>(L, st, c, a, eb, valid, dd, bound);
         }
     } else {
         uint32_t P = 0;      // list receiving appends (the pending list)
@@ -672,7 +697,8 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 const uint32_t f = fb + lane;
                 const bool valid = f < nf;
                 const uint2 eb = L.lst[F][valid ? f : 0u];
-                expand_chunk<HB, 1>(L, st, c, a, &eb, &valid, bound);
+                const uint32_t dd = L.dw[valid ? (eb.x & 0xFFFFu) : lane] >> 1;
+                expand_chunk<HB, 1>(L, st, c, a, &eb, &valid, &dd, bound);
             }
             if (st.ovf) break;
             pmin = min(wave_min(kmin), wave_min(st.imin));
