@@ -148,9 +148,11 @@ __device__ __forceinline__ void lds_store(uint32_t *p, uint32_t v) {
 template <int HB>
 struct Tier {
     static constexpr int H = 1 << HB;
-    // list capacity: the ring (2 PC entries) holds a search's pending frontier; sized so that
-    // a 2^12 table fits 4 waves per CU and a 2^13 table 2
-    static constexpr int PC = HB <= 9 ? 128 : (HB <= 12 ? 256 : (HB == 13 ? 512 : 1024));
+    // list capacity: the ring (2 PC entries) holds a search's pending set (at
+    // most about 120 vertices for searches that fit 2^11 entries on road
+    // graphs); sized so that a 2^11 table fits 8 waves per CU, a 2^12 table 4
+    // and a 2^13 table 2
+    static constexpr int PC = HB <= 11 ? 128 : (HB == 12 ? 256 : (HB == 13 ? 512 : 1024));
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
     // vertices per ring step, in units of 64, and the window size: the large
     // tables hold one or two waves per CU, so each of their steps keeps twice
@@ -176,10 +178,12 @@ struct SearchLds {
     static constexpr int PC = Tier<HB>::PC;
     uint32_t key[H];            // vertex id, or kEmpty
     uint32_t dw[H];             // distance word, kWordNone when empty
-    uint2 lst[2][PC + 1];       // two vertex lists of {slot | (arc count << 16), first arc} (with
-                                //   delta = 0, one ring of 2 PC entries over the same words);
-                                //   the last entry is a write sink for lanes with nothing to store
-    uint2 win[Tier<HB>::W];     // window arc -> {arc index, distance of the arc's tail}
+    uint2 lst[2][PC];           // two vertex lists of {slot | (arc count << 16), first arc} (with
+                                //   delta = 0, one ring of 2 PC entries over the same words)
+    uint2 win[Tier<HB>::W];     // window arc -> {arc index, distance of the arc's tail}; outside
+                                //   a window step, entry lane is the write sink of lanes with
+                                //   nothing to store (distinct addresses, no serialised writes)
+    __device__ uint2 *sink() { return &win[lane_id()]; }
 };
 
 struct WaveState {
@@ -279,7 +283,6 @@ template <int HB, int NJ>
 __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, const SrcCtx &c,
                                              const ArcRec *r, const uint32_t *nd, uint32_t bound) {
     constexpr uint32_t H = Tier<HB>::H;
-    constexpr uint32_t PC = Tier<HB>::PC;
     // slot states: 0 idle, 1 slot holds y, 2 slot claimed for y, 3 keep probing
     uint32_t h[NJ], stt[NJ], old[NJ];
     // a distance the packed word cannot hold (possible only when the bound
@@ -383,9 +386,9 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, co
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const bool app = stt[j] == 5u;
-        const uint32_t idx = app ? ((base + mbcnt(mA[j])) & st.amask) : 2u * PC + 1u;
-        q[idx] = make_uint2(h[j] | (static_cast<uint32_t>(r[j].yend - r[j].ybeg) << 16),
-                            static_cast<uint32_t>(r[j].ybeg));
+        uint2 *dst = app ? q + ((base + mbcnt(mA[j])) & st.amask) : L.sink();
+        *dst = make_uint2(h[j] | (static_cast<uint32_t>(r[j].yend - r[j].ybeg) << 16),
+                          static_cast<uint32_t>(r[j].ybeg));
         base += popc(mA[j]);
     }
     st.np += base - st.tail;
@@ -554,8 +557,7 @@ __device__ __forceinline__ void direct_pairs(SearchLds<HB> &L, const JoinArgs &a
         const uint64_t mM = __ballot(m);
         if (m) atomicAdd(&c.hist[kHistEmit + dist_bin(r.w)], 1u);
         emitted += popc(mM);
-        const uint32_t idx = m ? nst + mbcnt(mM) : PC;
-        L.lst[0][idx] = make_uint2(r.w, static_cast<uint32_t>(r.y));
+        *(m ? &L.lst[0][nst + mbcnt(mM)] : L.sink()) = make_uint2(r.w, static_cast<uint32_t>(r.y));
         nst += popc(mM);
         if (nst + 64 > PC) {
             wave_sync();
@@ -646,7 +648,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 for (int g = 0; g < G; ++g) {
                     const bool later = valid[g] && dd[g] > lim && dd[g] <= bound;
                     const uint64_t mL = __ballot(later);
-                    q[later ? ((base + mbcnt(mL)) & (RC - 1u)) : RC + 1u] = eb[g];
+                    *(later ? q + ((base + mbcnt(mL)) & (RC - 1u)) : L.sink()) = eb[g];
                     base += popc(mL);
                     valid[g] = valid[g] && !later;
                 }
@@ -679,16 +681,14 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 const uint64_t mF = __ballot(isF), mK = __ballot(isK);
                 wave_sync();  // every lane has read its entry before the in-place compaction
                 atomicAnd(&L.dw[valid ? (e & 0xFFFFu) : lane], drop ? ~1u : 0xFFFFFFFFu);  // dropped: not pending
-                const uint32_t fi = isF ? nf + mbcnt(mF) : static_cast<uint32_t>(PC);
-                L.lst[F][fi] = eb;
-                const uint32_t ki = isK ? nk + mbcnt(mK) : static_cast<uint32_t>(PC);
-                L.lst[P][ki] = eb;
+                *(isF ? &L.lst[F][nf + mbcnt(mF)] : L.sink()) = eb;
+                *(isK ? &L.lst[P][nk + mbcnt(mK)] : L.sink()) = eb;
                 kmin = min(kmin, isK ? d : kInf);
                 nf += popc(mF);
                 nk += popc(mK);
             }
             st.np = nk;
-            st.tail = P * (PC + 1u) + nk;
+            st.tail = P * PC + nk;
             st.amask = 0xFFFFFFFFu;
             st.cap = PC;
             st.imin = kInf;
@@ -740,8 +740,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
             const uint64_t mM = __ballot(m);
             if (c.k && m) atomicAdd(&c.hist[kHistEmit + dist_bin(d[j])], 1u);
             emitted += popc(mM);
-            const uint32_t idx = m ? nst + mbcnt(mM) : static_cast<uint32_t>(PC);
-            L.lst[0][idx] = make_uint2(d[j], k[j]);
+            *(m ? &L.lst[0][nst + mbcnt(mM)] : L.sink()) = make_uint2(d[j], k[j]);
             nst += popc(mM);
             if (nst + 64 > static_cast<uint32_t>(PC)) {
                 wave_sync();
