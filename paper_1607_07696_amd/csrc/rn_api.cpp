@@ -246,10 +246,15 @@ rn_status ensure_buffers(Workspace &ws, const Prepared &p) {
     const size_t state_bytes = sizeof(CallCtl) + static_cast<size_t>(p.nq) * sizeof(QueryState);
     if (ws.h_state_bytes < state_bytes) {
         host_free(ws.h_state);
+        ws.d_state_map = nullptr;
         ws.h_state_bytes = 0;
         const size_t bytes = std::max<size_t>(state_bytes + state_bytes / 4, 4096);
-        RN_HIP(hipHostMalloc(reinterpret_cast<void **>(&ws.h_state), bytes, 0), "allocating the read-back buffer");
+        RN_HIP(hipHostMalloc(reinterpret_cast<void **>(&ws.h_state), bytes, hipHostMallocMapped),
+               "allocating the read-back buffer");
         ws.h_state_bytes = bytes;
+        void *dp = nullptr;
+        RN_HIP(hipHostGetDevicePointer(&dp, ws.h_state, 0), "mapping the read-back buffer");
+        ws.d_state_map = static_cast<uint32_t *>(dp);
     }
     const size_t sw = stage_scratch_words(p.rbits_words);
     if (ws.stage_words < sw) {
@@ -441,7 +446,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     }
     record(g, ws, timed, EV_RELAXED, s);
     if (p.any_kcp) RN_HIP(launch_select(b, s), "selecting candidates");
-    RN_HIP(launch_layout(b, p.any_kcp ? 1 : 0, p.qb, p.vb, s), "laying out the output");
+    RN_HIP(launch_layout(b, p.any_kcp ? 1 : 0, p.qb, p.vb, p.nbins != 0, s), "laying out the output");
     record(g, ws, timed, EV_SELECTED, s);
     if (p.nbins)
         RN_HIP(launch_bucket_sort(b, out, static_cast<unsigned long long>(cap), s), "sorting pairs");
@@ -449,6 +454,10 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         RN_HIP(launch_sort_out(b, p.any_kcp ? 1 : 0, p.max_passes, p.vb, out, static_cast<unsigned long long>(cap), s),
                "sorting pairs");
     record(g, ws, timed, EV_DONE, s);
+    const size_t state_bytes = sizeof(CallCtl) + static_cast<size_t>(p.nq) * sizeof(QueryState);
+    RN_HIP(launch_publish(reinterpret_cast<const uint32_t *>(ws.d_block), ws.d_state_map,
+                          static_cast<uint32_t>(state_bytes / 4), s),
+           "publishing the call state");
     return RN_OK;
 }
 
@@ -459,9 +468,10 @@ namespace {
 
 constexpr uint32_t kDefaultSlots = 256;  // global-tier slots of a handle's calls and of a plan (one per CU)
 
+// The call's last kernel wrote its state into the mapped read-back buffer.
 rn_status read_back(Workspace &ws, const Prepared &p, hipStream_t s) {
-    const size_t bytes = sizeof(CallCtl) + static_cast<size_t>(p.nq) * sizeof(QueryState);
-    RN_HIP(hipMemcpyAsync(ws.h_state, ws.d_block, bytes, hipMemcpyDeviceToHost, s), "reading the call status");
+    (void)ws;
+    (void)p;
     RN_HIP(hipStreamSynchronize(s), "waiting for the call");
     return RN_OK;
 }

@@ -76,7 +76,8 @@ struct Workspace {
     size_t desc_bytes = 0;
     uint8_t *h_desc = nullptr;      // pinned staging of the same
     size_t h_desc_bytes = 0;
-    uint8_t *h_state = nullptr;     // pinned read-back of CallCtl | QueryState[nq]
+    uint8_t *h_state = nullptr;     // pinned read-back of CallCtl | QueryState[nq], mapped:
+    uint32_t *d_state_map = nullptr;  //   its device address, written by the call's last kernel
     size_t h_state_bytes = 0;
     uint32_t *d_stage = nullptr;
     size_t stage_words = 0;
@@ -101,6 +102,7 @@ struct Workspace {
         dev_free(d_desc);
         host_free(h_desc);
         host_free(h_state);
+        d_state_map = nullptr;
         dev_free(d_stage);
         dev_free(d_src);
         dev_free(d_srcq);

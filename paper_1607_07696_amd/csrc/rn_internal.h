@@ -190,6 +190,10 @@ struct CallBuffers {
 
 // ---- launchers (rn_kernels.hip); all enqueue on stream s
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+// Copy a call's state (words 32-bit words from device memory) into mapped
+// pinned host memory (dst: its device address), as the call's last kernel:
+// the host then only waits for the stream, with no copy queued after the call.
+hipError_t launch_publish(const uint32_t *src, uint32_t *dst, uint32_t words, hipStream_t s);
 
 // Validate every query's R and S, set the S bitmaps and rank bitmaps, and list
 // the sources query by query (staging order) in rank order.
@@ -221,7 +225,8 @@ hipError_t launch_select(const CallBuffers &b, hipStream_t s);
 // Per-query segments of the sorted records and of the output, the key layout
 // of the sort (ctl->sort_db, ctl->sort_passes); selected: records were
 // filtered by launch_select (else every emitted record is kept in place).
-hipError_t launch_layout(const CallBuffers &b, int selected, uint32_t qb, uint32_t vb, hipStream_t s);
+// bins: the call takes the bucket sort, whose bin scan runs in the same block.
+hipError_t launch_layout(const CallBuffers &b, int selected, uint32_t qb, uint32_t vb, bool bins, hipStream_t s);
 
 // Sort the kept records by (query, dist, u, v) and write each query's first
 // nout pairs to out at its offset, unless the records outgrew the buffer or
@@ -234,7 +239,7 @@ constexpr uint32_t kSortPassesMax = 16;
 
 // Bucket sort, for calls of theta-joins only whose bins (query, dist), theta+1
 // per query, number at most kMaxBins: the relaxation kernels count the records
-// per bin as they store them; scan, scatter the records into their bins, then
+// per bin as they store them; the layout launch scans them; scatter the records into their bins, then
 // order each bin by (u, v) by counting the smaller
 // keys of its records, one wave per 64 of them, writing each query's output
 // segment as the radix sort's last pass does.  Work per bin grows with the

@@ -3,7 +3,7 @@
 // A call runs any mix of theta-joins and k-closest-pairs queries, each on one
 // of the resident graphs, as one launch sequence on one HIP stream:
 //   stage     validate every query's R and S, set its S-membership bitmap and
-//             list all sources query by query (k_mark, k_overlap, k_rank_*)
+//             list all sources query by query (k_mark, k_overlap_count, k_rank_emit)
 //   seed      k-closest pairs: a first distance bound per query from the
 //             direct R-S arcs (k_kcp_seed_*)
 //   relax     one wavefront per source: a bounded, bucketed label-correcting
@@ -1101,6 +1101,11 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
 }
 
 // ------------------------------------------------------------------ staging
+__global__ __launch_bounds__(256) void k_publish(const uint32_t *src, uint32_t *dst, uint32_t words) {
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i < words) dst[i] = src[i];
+}
+
 __global__ void k_fill_u32(uint32_t *p, uint64_t n, uint32_t v) {
     for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
@@ -1153,8 +1158,9 @@ __global__ void k_mark(CallBuffers b, const int32_t *rank) {
     }
 }
 
-__global__ void k_overlap(CallBuffers b) {
-    const unsigned long long i = blockIdx.x * static_cast<unsigned long long>(blockDim.x) + threadIdx.x;
+// R and S must be disjoint: element i of the flattened lists, if it is in
+// some R, must not be in that query's S.
+__device__ __forceinline__ void check_overlap(const CallBuffers &b, unsigned long long i) {
     const uint32_t nq = static_cast<uint32_t>(b.nq);
     if (i >= b.ebase[nq]) return;
     const uint32_t p = seg_of(b.ebase, nq, i);
@@ -1187,14 +1193,17 @@ __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t *w
     return off + incl - v;
 }
 
-// Source listing, pass 1: marked ranks per 1024-word block of the rank pool.
-__global__ __launch_bounds__(1024) void k_rank_count(const uint32_t *rbits, uint32_t nwords,
-                                                     uint32_t *bsum) {
+// After the marks, in one launch: the disjointness check (thread i takes
+// element i of the flattened lists) and source listing pass 1, the marked
+// ranks per 1024-word block of the rank pool (the first nblk blocks).
+__global__ __launch_bounds__(1024) void k_overlap_count(CallBuffers b, uint32_t nblk) {
     __shared__ uint32_t wsum[16];
+    check_overlap(b, blockIdx.x * 1024ull + threadIdx.x);
+    if (blockIdx.x >= nblk) return;
     const uint32_t i = blockIdx.x * 1024u + threadIdx.x;
     uint32_t total;
-    block_excl_scan_1024(i < nwords ? __popc(rbits[i]) : 0u, wsum, &total);
-    if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+    block_excl_scan_1024(i < b.rwords ? __popc(b.rbits[i]) : 0u, wsum, &total);
+    if (threadIdx.x == 0) b.stage_scratch[blockIdx.x] = total;
 }
 
 // Source listing, pass 2: list the marked ranks in increasing pool order as
@@ -1343,9 +1352,8 @@ __device__ __forceinline__ uint32_t bitlen32(uint32_t x) { return x ? 32u - stat
 // One block: per query the kept count, its first position in the sorted
 // order, its output count (0 for a query with an argument error) and output
 // offset; then the sort key layout from the largest kept distance bound.
-__global__ __launch_bounds__(1024) void k_layout(CallBuffers b, int selected, uint32_t qb, uint32_t vb) {
-    __shared__ unsigned long long s[1024];
-    __shared__ uint32_t s_dmax;
+__device__ __forceinline__ void layout_block(const CallBuffers &b, int selected, uint32_t qb, uint32_t vb,
+                                             unsigned long long *s, uint32_t &s_dmax) {
     const uint32_t tid = threadIdx.x;
     if (tid == 0) s_dmax = 0;
     unsigned long long cs = 0, co = 0;
@@ -1381,6 +1389,12 @@ __global__ __launch_bounds__(1024) void k_layout(CallBuffers b, int selected, ui
         b.ctl->sort_db = db;
         b.ctl->sort_passes = max((qb + db + 2u * vb + 7u) / 8u, 1u);
     }
+}
+
+__global__ __launch_bounds__(1024) void k_layout(CallBuffers b, int selected, uint32_t qb, uint32_t vb) {
+    __shared__ unsigned long long s[1024];
+    __shared__ uint32_t s_dmax;
+    layout_block(b, selected, qb, vb, s, s_dmax);
 }
 
 // ------------------------------------------------------------------ radix sort
@@ -1532,8 +1546,7 @@ __device__ __forceinline__ uint32_t rec_bin(const CallBuffers &b, const Rec &r) 
 
 // One block: bin starts (exclusive prefix of the counts), scatter cursors and
 // the first 64-record chunk of each bin.
-__global__ __launch_bounds__(1024) void k_bucket_scan(CallBuffers b) {
-    __shared__ uint32_t wsum[16];
+__device__ __forceinline__ void bucket_scan_block(const CallBuffers &b, uint32_t *wsum) {
     const uint32_t nb = b.nbins, tid = threadIdx.x;
     const uint32_t *cnt = b.bins;
     uint32_t *start = b.bins + nb, *cursor = b.bins + 2 * nb, *cstart = b.bins + 3 * nb;
@@ -1557,6 +1570,15 @@ __global__ __launch_bounds__(1024) void k_bucket_scan(CallBuffers b) {
         cstart[nb] = tc;
         b.ctl->nchunks = tc;
     }
+}
+
+// theta-join calls: the output layout and the bin scan, in one block
+__global__ __launch_bounds__(1024) void k_layout_bins(CallBuffers b, uint32_t qb, uint32_t vb) {
+    __shared__ unsigned long long s[1024];
+    __shared__ uint32_t s_dmax;
+    layout_block(b, 0, qb, vb, s, s_dmax);
+    __syncthreads();
+    bucket_scan_block(b, reinterpret_cast<uint32_t *>(s));
 }
 
 __global__ __launch_bounds__(256) void k_bucket_scatter(CallBuffers b) {
@@ -1642,6 +1664,13 @@ hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, bool persis
 }  // namespace
 
 // ------------------------------------------------------------------ launchers
+hipError_t launch_publish(const uint32_t *src, uint32_t *dst, uint32_t words, hipStream_t s) {
+    if (words == 0) return hipSuccess;
+    const uint32_t blocks = (words + 255u) / 256u;
+    hipLaunchKernelGGL(k_publish, dim3(blocks), dim3(256), 0, s, src, dst, words);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
     if (n == 0) return hipSuccess;
     uint64_t blocks = (n + 255) / 256;
@@ -1656,9 +1685,9 @@ hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, cons
                         const int32_t *order, hipStream_t s) {
     const uint32_t eblk = static_cast<uint32_t>((max_elems + 255) / 256);
     hipLaunchKernelGGL(k_mark, dim3(eblk), dim3(256), 0, s, b, rank);
-    hipLaunchKernelGGL(k_overlap, dim3(eblk), dim3(256), 0, s, b);
     const uint32_t nblk = (b.rwords + 1023u) / 1024u;
-    hipLaunchKernelGGL(k_rank_count, dim3(nblk), dim3(1024), 0, s, b.rbits, b.rwords, b.stage_scratch);
+    const uint32_t oblk = static_cast<uint32_t>((max_elems + 1023) / 1024);
+    hipLaunchKernelGGL(k_overlap_count, dim3(max(nblk, oblk)), dim3(1024), 0, s, b, nblk);
     hipLaunchKernelGGL(k_rank_emit, dim3(nblk), dim3(1024), 0, s, b, b.stage_scratch, order);
     return hipGetLastError();
 }
@@ -1703,8 +1732,11 @@ hipError_t launch_select(const CallBuffers &b, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_layout(const CallBuffers &b, int selected, uint32_t qb, uint32_t vb, hipStream_t s) {
-    hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, b, selected, qb, vb);
+hipError_t launch_layout(const CallBuffers &b, int selected, uint32_t qb, uint32_t vb, bool bins, hipStream_t s) {
+    if (bins)
+        hipLaunchKernelGGL(k_layout_bins, dim3(1), dim3(1024), 0, s, b, qb, vb);
+    else
+        hipLaunchKernelGGL(k_layout, dim3(1), dim3(1024), 0, s, b, selected, qb, vb);
     return hipGetLastError();
 }
 
@@ -1732,7 +1764,6 @@ hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_pass
 }
 
 hipError_t launch_bucket_sort(const CallBuffers &b, rn_pair *out, unsigned long long user_cap, hipStream_t s) {
-    hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, b);
     hipLaunchKernelGGL(k_bucket_scatter, dim3(1024), dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_bucket_rank, dim3(1024), dim3(256), 0, s, b, out, user_cap);
     return hipGetLastError();

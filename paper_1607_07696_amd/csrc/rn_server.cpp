@@ -146,9 +146,8 @@ rn_status enqueue_lane(rn_server *s, Lane &L) {
     // streams would share the few hardware queues with other lanes and
     // serialise their kernels) and one block per source, so that the blocks
     // of a long batch do not hold every CU until it ends
+    // (the call's last kernel writes its state into the lane's mapped read-back buffer)
     RN_TRY(enqueue_call(s->g, L.ws, L.prep, L.d_out, static_cast<int64_t>(L.out_cap), L.stream, false, true));
-    const size_t bytes = sizeof(CallCtl) + static_cast<size_t>(L.prep.nq) * sizeof(QueryState);
-    RN_HIP(hipMemcpyAsync(L.ws.h_state, L.ws.d_block, bytes, hipMemcpyDeviceToHost, L.stream), "reading the status");
     RN_HIP(hipEventRecord(L.ev_state, L.stream), "recording an event");
     L.state = Lane::RUNNING;
     return RN_OK;
