@@ -1405,6 +1405,9 @@ __global__ __launch_bounds__(1024) void k_layout(CallBuffers b, int selected, ui
 // landed in) and the stable scatter.  db and the number of digits come from
 // the device (k_layout); launches for digits beyond it return at once.
 constexpr uint32_t kSortBlocks = 256;
+// words of the radix sort's scratch region (per pass a [256 digits][kSortBlocks
+// tiles] histogram, then 256 digit totals per pass)
+constexpr uint32_t kSortHistWords = (kSortPassesMax + 1) * 256u * (kSortBlocks + 1);
 
 __device__ __forceinline__ void sort_tile(const unsigned long long *nptr, unsigned long long cap,
                                           uint64_t &beg, uint64_t &end, uint64_t &tile) {
@@ -1545,7 +1548,9 @@ __global__ __launch_bounds__(256) void k_sort_pass(const Rec *in, Rec *out, Call
 __device__ __forceinline__ uint32_t rec_bin(const CallBuffers &b, const Rec &r) { return b.binbase[r.q] + r.d; }
 
 // One block: bin starts (exclusive prefix of the counts), scatter cursors and
-// the first 64-record chunk of each bin.
+// the first 64-record chunk of each bin; when the chunks fit the radix sort's
+// scratch region (unused by this sort), also the bin of every chunk, which
+// spares each ranking wave a search over the chunk starts.
 __device__ __forceinline__ void bucket_scan_block(const CallBuffers &b, uint32_t *wsum) {
     const uint32_t nb = b.nbins, tid = threadIdx.x;
     const uint32_t *cnt = b.bins;
@@ -1559,12 +1564,16 @@ __device__ __forceinline__ void bucket_scan_block(const CallBuffers &b, uint32_t
     uint32_t tr, tc;
     uint32_t er = block_excl_scan_1024(sr, wsum, &tr);
     uint32_t ec = block_excl_scan_1024(sc, wsum, &tc);
+    const bool map = tc <= kSortHistWords;
     for (uint32_t i = lo; i < hi; ++i) {
         start[i] = er;
         cursor[i] = er;
         cstart[i] = ec;
         er += cnt[i];
-        ec += (cnt[i] + 63u) / 64u;
+        const uint32_t nch = (cnt[i] + 63u) / 64u;
+        if (map)
+            for (uint32_t t = 0; t < nch; ++t) b.sort_hist[ec + t] = i;
+        ec += nch;
     }
     if (tid == 0) {
         cstart[nb] = tc;
@@ -1601,7 +1610,7 @@ __global__ __launch_bounds__(256) void k_bucket_rank(CallBuffers b, rn_pair *out
     const uint32_t total = ctl->nchunks;
     const uint32_t waves = gridDim.x * 4u;
     for (uint32_t c = blockIdx.x * 4u + (threadIdx.x >> 6); c < total; c += waves) {
-        const uint32_t bin = seg_of(cstart, nb, c);
+        const uint32_t bin = total <= kSortHistWords ? b.sort_hist[c] : seg_of(cstart, nb, c);
         const uint32_t m = cnt[bin], s0 = start[bin];
         const uint32_t j = (c - cstart[bin]) * 64u + lane;
         const bool valid = j < m;
@@ -1741,7 +1750,7 @@ hipError_t launch_layout(const CallBuffers &b, int selected, uint32_t qb, uint32
 }
 
 // per pass: a [256 digits][kSortBlocks tiles] histogram, then 256 digit totals per pass
-size_t sort_hist_words() { return static_cast<size_t>(kSortPassesMax + 1) * 256u * (kSortBlocks + 1); }
+size_t sort_hist_words() { return kSortHistWords; }
 
 hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_passes, uint32_t vb,
                            rn_pair *out, unsigned long long user_cap, hipStream_t s) {
