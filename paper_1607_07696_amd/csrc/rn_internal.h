@@ -78,7 +78,9 @@ struct QueryState {
     uint32_t err;               // kErr* bits
     uint32_t bound;             // k > 0: current distance bound (seeded, then lowered)
     uint32_t src_start;         // first entry of the query's sources in the source list
-    uint32_t pad;
+    uint32_t direct;            // k > 0: 1 when every pair within the seeded bound is a direct arc
+                                // (the bound is below twice the lightest arc): one thread per
+                                // source answers the query, and its searches are skipped
     unsigned long long npairs;  // records the query emitted
     unsigned long long nsel;    // records kept by the final bound
     unsigned long long start;   // first kept record of the query in the sorted order
@@ -216,7 +218,8 @@ hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslot
                               uint32_t max_sources, hipStream_t s);
 
 // k closest pairs: seed every k-query's bound from the direct arcs between its
-// R and S, capped by its theta.
+// R and S, capped by its theta; answer the queries whose seeded bound is below
+// twice their lightest arc from the direct arcs alone (QueryState::direct).
 hipError_t launch_kcp_seed(const JoinArgs &a, const CallBuffers &b, uint32_t max_sources, hipStream_t s);
 
 // Keep the records within their query's final bound (into recs[1]).

@@ -5,7 +5,8 @@
 //   stage     validate every query's R and S, set its S-membership bitmap and
 //             list all sources query by query (k_mark, k_overlap_count, k_rank_emit)
 //   seed      k-closest pairs: a first distance bound per query from the
-//             direct R-S arcs (k_kcp_seed_*)
+//             direct R-S arcs (k_kcp_seed_*); a query whose bound is below twice
+//             the lightest arc is answered here, one thread per source (k_kcp_direct)
 //   relax     one wavefront per source: a bounded, bucketed label-correcting
 //             search whose whole state (distance table, pending set, frontier)
 //             lives in LDS; emits (u, v, dist, query) for v in S (k_join), with
@@ -792,6 +793,8 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
     launch_range(a, b, n);
     const uint32_t per = (n + 7u) / 8u;
     if (blockIdx.x >= 8u * per) return;
+    // one k-query answered by k_kcp_direct: nothing to search
+    if (GEN && a.srcq[b] == a.srcq[b + n - 1] && a.qs[a.srcq[b]].direct) return;
     for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(H); i += 64) {
         lds_store(&L.key[i], kEmpty);
         L.dw[i] = kWordNone;
@@ -802,6 +805,7 @@ __global__ __launch_bounds__(64) void k_join(JoinArgs a) {
     for (uint32_t t = blockIdx.x; t < 8u * per; t += gridDim.x) {
         const uint32_t si = (t & 7u) * per + (t >> 3);
         if (si >= n) continue;
+        if (GEN && a.qs[a.srcq[b + si]].direct) continue;   // answered by k_kcp_direct
         SrcCtx c = load_ctx(a, a.srcq[b + si]);
         if (!GEN) {
             c.k = 0;
@@ -1285,12 +1289,69 @@ __global__ __launch_bounds__(256) void k_kcp_seed_hist(JoinArgs a) {
     }
 }
 
-// One wave per query: the seeded bound of each k-query, capped by its theta.
-__global__ __launch_bounds__(64) void k_kcp_seed_bound(const QueryDesc *qd, QueryState *qs, const uint32_t *hists) {
+// One wave per query: the seeded bound of each k-query, capped by its theta,
+// and whether every pair within it is a direct arc (allow_direct: not when
+// the searches count their work).
+__global__ __launch_bounds__(64) void k_kcp_seed_bound(const QueryDesc *qd, QueryState *qs, const uint32_t *hists,
+                                                       int allow_direct) {
     const QueryDesc &d = qd[blockIdx.x];
     if (d.k == 0) return;
-    const uint32_t b = wave_bound_from_hist(hists + d.hist + kHistSeed, d.k);
-    if (threadIdx.x == 0) qs[blockIdx.x].bound = min(b, d.theta);
+    const uint32_t b = min(wave_bound_from_hist(hists + d.hist + kHistSeed, d.k), d.theta);
+    if (threadIdx.x == 0) {
+        qs[blockIdx.x].bound = b;
+        qs[blockIdx.x].direct =
+            allow_direct && static_cast<uint64_t>(b) < 2ull * static_cast<uint64_t>(d.wmin) ? 1u : 0u;
+    }
+}
+
+// k-closest pairs whose seeded bound is below twice the lightest arc: every
+// path of two or more arcs is longer, so the pairs within the bound are the
+// direct arcs from a source into S no heavier than it, each at the weight of
+// the pair's lightest arc (parallel arcs: the first lightest).  One thread
+// per source (a source has a few arcs, so a wave per source would idle):
+// count, reserve, then write.  The query's searches are skipped.
+__device__ __forceinline__ bool direct_pair(const JoinArgs &a, const SrcCtx &c, int32_t b, int32_t e, int32_t x,
+                                            uint32_t bound, ArcRec &r) {
+    r = a.arcs[x];
+    if (r.w > bound || !in_s(c, static_cast<uint32_t>(r.y))) return false;
+    for (int32_t z = b; z < e; ++z) {
+        const ArcRec o = a.arcs[z];
+        if (o.y == r.y && (o.w < r.w || (o.w == r.w && z < x))) return false;
+    }
+    return true;
+}
+
+__global__ __launch_bounds__(256) void k_kcp_direct(JoinArgs a) {
+    const uint32_t n = *a.send;
+    const uint32_t i = blockIdx.x * 256u + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t q = a.srcq[i];
+    if (!a.qs[q].direct) return;
+    const SrcCtx c = load_ctx(a, q);
+    const uint32_t bound = c.qs->bound;
+    const int32_t u = a.src[i];
+    const int32_t b = a.row_ptr[c.rpo + u], e = a.row_ptr[c.rpo + u + 1];
+    ArcRec r;
+    uint32_t cnt = 0;
+    for (int32_t x = b; x < e; ++x) cnt += direct_pair(a, c, b, e, x, bound, r) ? 1u : 0u;
+    if (cnt == 0) return;
+    const unsigned long long base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(cnt));
+    atomicAdd(&c.qs->npairs, static_cast<unsigned long long>(cnt));
+    unsigned long long idx = base;
+    for (int32_t x = b; x < e; ++x) {
+        if (!direct_pair(a, c, b, e, x, bound, r)) continue;
+        atomicAdd(&c.hist[kHistEmit + dist_bin(r.w)], 1u);
+        if (idx < a.rec_cap) {
+            const int32_t from = u - c.voff, to = r.y - c.voff;
+            Rec o;
+            o.u = c.swapped ? to : from;
+            o.v = c.swapped ? from : to;
+            o.d = r.w;
+            o.q = q;
+            a.recs[idx] = o;
+        }
+        ++idx;
+    }
 }
 
 // Keep the records within their query's final bound (order is restored by the
@@ -1732,7 +1793,9 @@ hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslot
 
 hipError_t launch_kcp_seed(const JoinArgs &a, const CallBuffers &b, uint32_t max_sources, hipStream_t s) {
     hipLaunchKernelGGL(k_kcp_seed_hist, dim3((max_sources + 255) / 256), dim3(256), 0, s, a);
-    hipLaunchKernelGGL(k_kcp_seed_bound, dim3(static_cast<uint32_t>(b.nq)), dim3(64), 0, s, b.qd, b.qs, b.hists);
+    hipLaunchKernelGGL(k_kcp_seed_bound, dim3(static_cast<uint32_t>(b.nq)), dim3(64), 0, s, b.qd, b.qs, b.hists,
+                       a.count_work ? 0 : 1);
+    hipLaunchKernelGGL(k_kcp_direct, dim3((max_sources + 255) / 256), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

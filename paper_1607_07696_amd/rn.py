@@ -374,21 +374,24 @@ class Plan:
         _check(load_library().rn_plan_create(net._h, queries, len(queries), C.c_void_p(self.out.data_ptr()),
                                              int(cap), C.c_void_p(stream.cuda_stream), C.byref(h)))
         self._h = h
+        # what every run passes, built once (a replay is a few hundred microseconds)
+        self._stream = C.c_void_p(stream.cuda_stream)
+        self._off = np.zeros(len(queries) + 1, dtype=np.int64)
+        self._status = np.zeros(len(queries), dtype=np.int32)
+        self._offp = self._off.ctypes.data_as(C.POINTER(C.c_int64))
+        self._statusp = self._status.ctypes.data_as(C.POINTER(C.c_int32))
+        self._run = load_library().rn_plan_run
 
     def run(self, stream=None, check: bool = True):
-        """Replay: returns (pairs tensor view, offsets, status) as join_batch."""
-        import torch
-        if stream is None:
-            stream = torch.cuda.current_stream()
-        nq = len(self.queries)
-        off = np.zeros(nq + 1, dtype=np.int64)
-        status = np.zeros(nq, dtype=np.int32)
-        st = load_library().rn_plan_run(self._h, off.ctypes.data_as(C.POINTER(C.c_int64)),
-                                        status.ctypes.data_as(C.POINTER(C.c_int32)),
-                                        C.c_void_p(stream.cuda_stream))
+        """Replay on ``stream`` (default: the stream the plan was created on):
+        returns (pairs tensor view, offsets, status) as join_batch."""
+        sp = self._stream if stream is None else C.c_void_p(stream.cuda_stream)
+        st = self._run(self._h, self._offp, self._statusp, sp)
+        off, status = self._off.copy(), self._status.copy()
+        n = int(off[-1])
         if st != RN_OK and not (st == RN_ERR_ARG and not check and status.any()):
-            _check(st, int(off[nq]))
-        return self.out[: int(off[nq])], off, status
+            _check(st, n)
+        return self.out[:n], off, status
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
