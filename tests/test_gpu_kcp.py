@@ -136,3 +136,41 @@ def test_bound_tightens_while_searches_run(rnmod, orc, rg):
     net = rnmod.RoadNetwork.from_graph(g)
     assert_same(gpu_kcp(rnmod, net, R, S, 100), orc.kcp_join(g, R, S, 100))
     assert net.stats()["global_searches"] == 0
+
+
+def _one_hop(want, g):
+    # every answer is a direct arc when d_k < 2 * (lightest arc): the queries below
+    # are built to take the one-thread-per-source path
+    return len(want) > 0 and int(want["dist"][-1]) < 2 * int(np.min(g.w))
+
+
+@pytest.mark.parametrize("nR,nS", [(2000, 600), (600, 2000)])   # the second searches from S
+def test_one_hop_answers_both_orientations(rnmod, orc, rg, nR, nS):
+    g = rg.road_graph(96, 5)
+    R, S = rg.sample_disjoint(g.V, nR, nS, 31)
+    net = rnmod.RoadNetwork.from_graph(g)
+    for k in (1, 20, 200):                        # 200: beyond one hop, the searches answer
+        want = orc.kcp_join(g, R, S, k)
+        assert _one_hop(want, g) == (k < 200), k
+        assert_same(gpu_kcp(rnmod, net, R, S, k), want)
+
+
+def test_one_hop_answers_with_parallel_arcs(rnmod, orc, rg):
+    # every arc gets a parallel copy 0, 1 or 2 heavier (0: an exact duplicate);
+    # the reversed arcs then differ from the forward ones, so searches from S
+    # read the transposed arcs
+    a = rg.road_graph(48, 6)
+    rows, cols, ws = [0], [], []
+    for x in range(a.V):
+        for e in range(a.row_ptr[x], a.row_ptr[x + 1]):
+            cols += [a.col[e], a.col[e]]
+            ws += [a.w[e], a.w[e] + e % 3]
+        rows.append(len(cols))
+    g = rg.Graph(np.array(rows, np.int32), np.array(cols, np.int32), np.array(ws, np.uint32))
+    net = rnmod.RoadNetwork.from_graph(g)
+    for nR, nS in ((700, 300), (300, 700)):
+        R, S = rg.sample_disjoint(g.V, nR, nS, 32)
+        for k in (2, 5, 60):                      # 60: beyond one hop
+            want = orc.kcp_join(g, R, S, k)
+            assert _one_hop(want, g) == (k < 60), (nR, nS, k)
+            assert_same(gpu_kcp(rnmod, net, R, S, k), want)
