@@ -151,16 +151,29 @@ struct Tier {
     static constexpr int H = 1 << HB;
     // list capacity: the ring (2 PC entries) holds a search's pending set (at
     // most about 120 vertices for searches that fit 2^11 entries on road
-    // graphs); sized so that a 2^11 table fits 8 waves per CU, a 2^12 table 4
-    // and a 2^13 table 2
-    static constexpr int PC = HB <= 11 ? 128 : (HB == 12 ? 256 : (HB == 13 ? 512 : 1024));
+    // graphs, 250 for 2^13 and 370 for 2^14); sized so that a 2^11 table
+    // fits 8 waves per CU, a 2^12 table 4, a 2^13 table (a block of four
+    // waves) 8 and a 2^14 table 4
+    static constexpr int PC = HB <= 11 ? 128 : (HB == 12 ? 256 : (HB == 13 ? 256 : 512));
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
-    // vertices per ring step, in units of 64, and the window size: the large
-    // tables hold one or two waves per CU, so each of their steps keeps twice
-    // as many loads and atomics in flight
-    static constexpr int G = HB >= 13 ? 2 : 1;
+    // waves per search: a large table leaves room for one or two searches
+    // per CU, so four waves share each one (a block); every wave takes 64
+    // vertices per step and has its own window of W arcs
+    static constexpr int NW = HB >= 13 ? 4 : 1;
+    static constexpr int G = 1;
     static constexpr uint32_t W = kWin * G;
 };
+
+// Ring bookkeeping shared by the waves of a block that runs one search
+// (tables of 2^13 and 2^14 entries).
+struct BlockRing {
+    uint32_t tail;      // unwrapped ring index of the next append (atomic)
+    uint32_t nins;      // table entries in use (atomic)
+    uint32_t ovf;       // the search outgrew this tier
+    uint32_t dmin[2];   // least distance taken by the step, by step parity (atomic)
+};
+
+__device__ __forceinline__ uint32_t wave_in_block() { return threadIdx.x >> 6; }
 
 // Distance words: (distance << 1) | pending, the low bit set while the vertex
 // is in the pending list.  One atomicMin with (nd << 1) | 1 lowers the distance
@@ -181,10 +194,15 @@ struct SearchLds {
     uint32_t dw[H];             // distance word, kWordNone when empty
     uint2 lst[2][PC];           // two vertex lists of {slot | (arc count << 16), first arc} (with
                                 //   delta = 0, one ring of 2 PC entries over the same words)
-    uint2 win[Tier<HB>::W];     // window arc -> {arc index, distance of the arc's tail}; outside
-                                //   a window step, entry lane is the write sink of lanes with
-                                //   nothing to store (distinct addresses, no serialised writes)
-    __device__ uint2 *sink() { return &win[lane_id()]; }
+    uint2 win[Tier<HB>::W * Tier<HB>::NW];   // per wave: window arc -> {arc index, distance of the
+                                //   arc's tail}; outside a window step, entry lane is the write
+                                //   sink of lanes with nothing to store (distinct addresses, no
+                                //   serialised writes) and the staging area of emitted pairs
+    __device__ uint2 *wwin() {
+        if constexpr (Tier<HB>::NW == 1) return win;
+        else return win + wave_in_block() * Tier<HB>::W;
+    }
+    __device__ uint2 *sink() { return wwin() + lane_id(); }
 };
 
 struct WaveState {
@@ -197,6 +215,8 @@ struct WaveState {
     uint32_t pnew;  // k-closest pairs: discoveries counted this phase, not yet published
     bool ovf;       // the search outgrew this tier
     bool probing;   // k-closest pairs: count discoveries of S members
+    uint32_t head;  // block search: the ring's head once this step's entries are taken
+    BlockRing *blk; // block search: the shared ring state (else null)
 };
 
 // What a search needs to know about its query (read once per source; uniform
@@ -366,7 +386,7 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, co
     uint32_t ins = 0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) ins += popc(__ballot(old[j] == kWordNone && stt[j] >= 4u));
-    st.nins += ins;
+    if constexpr (Tier<HB>::NW == 1) st.nins += ins;
     if (st.probing && ins != 0) {
         // k-closest pairs: a first discovery of an S member is a pair with a
         // path of length nd
@@ -378,11 +398,36 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, co
             st.pnew += popc(__ballot(fresh));
         }
     }
+    uint2 *q = &L.lst[0][0];
+    if constexpr (Tier<HB>::NW > 1) {
+        // a block search: reserve ring entries and count table entries in
+        // the block's shared state (one atomic each per wave)
+        uint32_t base = 0, fill = 0;
+        if (lane_id() == 0) {
+            base = atomicAdd(&st.blk->tail, nadd);
+            fill = atomicAdd(&st.blk->nins, ins) + ins;
+        }
+        base = readlane(base, 0);
+        fill = readlane(fill, 0);
+        if (__ballot(lost) != 0 || fill > (3u * H) / 4u || base + nadd - st.head > st.cap) {
+            st.ovf = true;
+            if (lane_id() == 0) st.blk->ovf = 1u;
+            return;
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const bool app = stt[j] == 5u;
+            uint2 *dst = app ? q + ((base + mbcnt(mA[j])) & st.amask) : L.sink();
+            *dst = make_uint2(h[j] | (static_cast<uint32_t>(r[j].yend - r[j].ybeg) << 16),
+                              static_cast<uint32_t>(r[j].ybeg));
+            base += popc(mA[j]);
+        }
+        return;
+    }
     if (__ballot(lost) != 0 || st.nins > (3u * H) / 4u || st.np + nadd > st.cap) {
         st.ovf = true;
         return;
     }
-    uint2 *q = &L.lst[0][0];
     uint32_t base = st.tail;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -409,7 +454,7 @@ __device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, con
     for (int j = 0; j < NJ; ++j) {
         const uint32_t t = j * 64 + lane;
         const uint32_t tc = t < cnt ? t : 0u;
-        const uint2 w = L.win[tc];
+        const uint2 w = L.wwin()[tc];
         idx[j] = t < cnt ? static_cast<int32_t>(w.x) : 0;
         od[j] = w.y;
     }
@@ -449,10 +494,10 @@ __device__ __forceinline__ unsigned long long reserve_recs(const JoinArgs &a, co
            readlane(static_cast<uint32_t>(base), 0);
 }
 
-// Write this wave's staged pairs ({dist, v} in list 0) for source u.
+// Write this wave's staged pairs ({dist, v} in stg) for source u.
 template <int HB>
 __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
-                                            uint32_t &nst) {
+                                            uint32_t &nst, const uint2 *stg) {
     if (nst == 0) return;
     const unsigned long long base = reserve_recs(a, c, nst);
     const uint32_t bin0 = a.bins ? a.binbase[c.q] : 0u;
@@ -461,7 +506,7 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
         const unsigned long long idx = base + i;
         if (idx < a.rec_cap) {
             Rec r;
-            const uint2 e = L.lst[0][i];
+            const uint2 e = stg[i];
             const int32_t from = u - c.voff, to = static_cast<int32_t>(e.y) - c.voff;
             r.u = c.swapped ? to : from;
             r.v = c.swapped ? from : to;
@@ -505,7 +550,7 @@ __device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, co
         for (int g = 0; g < G; ++g) {
             const uint32_t lo = max(first, wb), hi = min(first + deg[g], wb + W);
             for (uint32_t p = lo; p < hi; ++p)
-                L.win[p - wb] = make_uint2(static_cast<uint32_t>(b[g]) + (p - first), d[g]);
+                L.wwin()[p - wb] = make_uint2(static_cast<uint32_t>(b[g]) + (p - first), d[g]);
             first += deg[g];
         }
         wave_sync();
@@ -562,11 +607,11 @@ __device__ __forceinline__ void direct_pairs(SearchLds<HB> &L, const JoinArgs &a
         nst += popc(mM);
         if (nst + 64 > PC) {
             wave_sync();
-            flush_pairs<HB>(L, a, c, u, nst);
+            flush_pairs<HB>(L, a, c, u, nst, &L.lst[0][0]);
         }
     }
     wave_sync();
-    flush_pairs<HB>(L, a, c, u, nst);
+    flush_pairs<HB>(L, a, c, u, nst, &L.lst[0][0]);
     if (emitted != 0) tighten_bound(c, tseen);
     wave_sync();
 }
@@ -604,6 +649,8 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
     st.imin = kInf;
     st.ovf = (ue - ub) > 0xFFFF;
     st.probing = false;
+    st.head = 0;
+    st.blk = nullptr;
     uint32_t bound = c.theta;
     uint32_t seen = 0, phase = 0;
 
@@ -745,12 +792,12 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
             nst += popc(mM);
             if (nst + 64 > static_cast<uint32_t>(PC)) {
                 wave_sync();
-                flush_pairs<HB>(L, a, c, u, nst);
+                flush_pairs<HB>(L, a, c, u, nst, &L.lst[0][0]);
             }
         }
     }
     wave_sync();
-    flush_pairs<HB>(L, a, c, u, nst);
+    flush_pairs<HB>(L, a, c, u, nst, &L.lst[0][0]);
     if (c.k && emitted != 0) tighten_bound(c, tseen);
     if (a.count_work && !st.ovf) {
         for (int o = 32; o > 0; o >>= 1) {
@@ -773,6 +820,160 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
     wave_sync();
 }
 
+// The same search by a block of Tier<HB>::NW waves sharing one table (tables
+// of 2^13 and 2^14 entries, which leave room for one or two searches per CU):
+// the ring of pending vertices is shared, each step the waves take 64
+// vertices each, put back the ones far above the step's least distance (the
+// deferral of the one-wave search) and expand the rest in windows of their
+// own; appends reserve ring entries with LDS atomics.  Two block barriers
+// per step; every loop that crosses a barrier decides on values read from
+// LDS after a barrier, so the waves always agree.  The delta of the query
+// is not used (one bucket, as with delta = 0: the distances are the same).
+template <int HB>
+__device__ void search_source_block(SearchLds<HB> &L, BlockRing &B, const JoinArgs &a, const SrcCtx &c,
+                                    int32_t u, unsigned long long &tseen) {
+    constexpr int H = Tier<HB>::H;
+    constexpr int NW = Tier<HB>::NW;
+    constexpr int U = Tier<HB>::U;
+    constexpr uint32_t RC = 2u * Tier<HB>::PC;
+    const uint32_t lane = lane_id(), wv = wave_in_block();
+    const int32_t ub = a.row_ptr[c.rpo + u];
+    const int32_t ue = a.row_ptr[c.rpo + u + 1];
+    uint2 *q = &L.lst[0][0];
+    if (threadIdx.x == 0) {
+        const uint32_t h0 = slot_hash<HB>(static_cast<uint32_t>(u));   // table is empty
+        lds_store(&L.key[h0], static_cast<uint32_t>(u));
+        L.dw[h0] = 1u;                                                // distance 0, pending
+        q[0] = make_uint2(h0 | (static_cast<uint32_t>(min(ue - ub, 0xFFFF)) << 16), static_cast<uint32_t>(ub));
+        B.tail = 1;
+        B.nins = 1;
+        B.ovf = (ue - ub) > 0xFFFF ? 1u : 0u;
+        B.dmin[0] = kInf;
+        B.dmin[1] = kInf;
+    }
+    __syncthreads();
+    WaveState st;
+    st.np = 0;
+    st.tail = 0;
+    st.nins = 0;
+    st.pnew = 0;
+    st.imin = kInf;
+    st.ovf = false;
+    st.probing = false;
+    st.amask = RC - 1u;
+    st.cap = RC;
+    st.blk = &B;
+    uint32_t seen = 0, phase = 0, head = 0;
+    while (true) {
+        // after a barrier: every wave reads the same tail and overflow flag
+        const uint32_t tail = B.tail;
+        if (B.ovf != 0 || tail == head) break;
+        if (c.hist != nullptr && phase >= 2) probe_phase(c, st.pnew, st.probing, seen);
+        const uint32_t par = phase & 1u;
+        ++phase;
+        const uint32_t bound = current_bound(c);
+        const uint32_t m = min(64u * NW, tail - head);
+        const uint32_t mine = wv * 64u + lane;
+        bool valid = mine < m;
+        const uint2 eb = q[(head + mine) & (RC - 1u)];
+        uint32_t dd = L.dw[valid ? (eb.x & 0xFFFFu) : lane] >> 1;
+        head += m;
+        st.head = head;
+        if (c.slack != kInf) {
+            const uint32_t mn = wave_min(valid ? dd : kInf);
+            if (lane == 0 && mn != kInf) atomicMin(&B.dmin[par], mn);
+        }
+        __syncthreads();   // every taken entry is read, the step's least distance complete
+        if (threadIdx.x == 0) B.dmin[par ^ 1u] = kInf;   // for the next step (read after the next barrier)
+        if (c.slack != kInf) {
+            const uint32_t lim = sat_add(B.dmin[par], c.slack);
+            const bool later = valid && dd > lim && dd <= bound;
+            const uint64_t mL = __ballot(later);
+            if (mL != 0) {
+                uint32_t base = 0;
+                if (lane == 0) base = atomicAdd(&B.tail, popc(mL));
+                base = readlane(base, 0);
+                *(later ? q + ((base + mbcnt(mL)) & (RC - 1u)) : L.sink()) = eb;
+            }
+            valid = valid && !later;
+        }
+        expand_chunk<HB, 1>(L, st, c, a, &eb, &valid, &dd, bound);
+        __syncthreads();   // every append of the step is done
+    }
+    const bool ovf = B.ovf != 0;
+
+    // ---- emit table entries in S (each wave a slice of the table, staged in
+    // its slice of the ring, free once the search has ended; the window areas
+    // take the sink writes), and clear the table for the next source
+    const uint32_t bound = current_bound(c);
+    constexpr uint32_t SC = RC / NW;   // staging entries per wave
+    uint2 *stg = q + wv * SC;
+    uint32_t nst = 0, emitted = 0;
+    unsigned long long warcs = 0;
+    uint32_t wsettled = 0;
+    constexpr uint32_t SL = static_cast<uint32_t>(H / NW);
+    for (uint32_t g0 = wv * SL; g0 < (wv + 1) * SL; g0 += 64 * U) {
+        uint32_t k[U], d[U];
+        bool sb[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint32_t slot = g0 + j * 64 + lane;
+            k[j] = lds_load(&L.key[slot]);
+            d[j] = L.dw[slot] >> 1;
+            sb[j] = !ovf && k[j] != kEmpty && in_s(c, k[j]);
+        }
+        if (a.count_work && !ovf) {
+#pragma unroll
+            for (int j = 0; j < U; ++j)
+                if (k[j] != kEmpty && d[j] <= bound) {
+                    warcs += static_cast<unsigned long long>(a.row_ptr[c.rpo + k[j] + 1] - a.row_ptr[c.rpo + k[j]]);
+                    wsettled += 1;
+                }
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const uint32_t slot = g0 + j * 64 + lane;
+            lds_store(&L.key[slot], kEmpty);
+            L.dw[slot] = kWordNone;
+        }
+#pragma unroll
+        for (int j = 0; j < U; ++j) {
+            const bool mm = sb[j] && d[j] <= bound;
+            const uint64_t mM = __ballot(mm);
+            if (c.k && mm) atomicAdd(&c.hist[kHistEmit + dist_bin(d[j])], 1u);
+            emitted += popc(mM);
+            *(mm ? stg + nst + mbcnt(mM) : L.sink()) = make_uint2(d[j], k[j]);
+            nst += popc(mM);
+            if (nst + 64 > SC) {
+                wave_sync();
+                flush_pairs<HB>(L, a, c, u, nst, stg);
+            }
+        }
+    }
+    wave_sync();
+    flush_pairs<HB>(L, a, c, u, nst, stg);
+    if (c.k && emitted != 0) tighten_bound(c, tseen);
+    if (a.count_work && !ovf) {
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint32_t lo = static_cast<uint32_t>(__shfl_xor(static_cast<int>(warcs & 0xFFFFFFFFull), o));
+            const uint32_t hi = static_cast<uint32_t>(__shfl_xor(static_cast<int>(warcs >> 32), o));
+            warcs += (static_cast<unsigned long long>(hi) << 32) | lo;
+            wsettled += static_cast<uint32_t>(__shfl_xor(static_cast<int>(wsettled), o));
+        }
+        if (lane == 0) {
+            atomicAdd(&a.ctl->arcs, warcs);
+            atomicAdd(&a.ctl->settled, static_cast<unsigned long long>(wsettled));
+        }
+    }
+    if (ovf && threadIdx.x == 0) {
+        const uint32_t idx = atomicAdd(a.novf, 1u);
+        a.ovf[idx] = u;
+        a.ovfq[idx] = c.q;
+        if (a.first_tier) atomicAdd(&a.ctl->nretry, 1u);
+    }
+    __syncthreads();   // the table is clear and B is free before the next source
+}
+
 __device__ __forceinline__ void launch_range(const JoinArgs &a, uint32_t &b, uint32_t &n) {
     b = a.sbeg ? *a.sbeg : 0u;
     const uint32_t e = *a.send;
@@ -786,40 +987,63 @@ __device__ __forceinline__ void launch_range(const JoinArgs &a, uint32_t &b, uin
 // every source belongs to a theta-join, and the k-closest-pairs code is
 // compiled out.
 template <int HB, bool GEN>
-__global__ __launch_bounds__(64) void k_join(JoinArgs a) {
+__global__ __launch_bounds__(64 * Tier<HB>::NW) void k_join(JoinArgs a) {
     __shared__ SearchLds<HB> L;
     constexpr int H = Tier<HB>::H;
+    constexpr int NW = Tier<HB>::NW;
     uint32_t b, n;
     launch_range(a, b, n);
     const uint32_t per = (n + 7u) / 8u;
     if (blockIdx.x >= 8u * per) return;
     // one k-query answered by k_kcp_direct: nothing to search
     if (GEN && a.srcq[b] == a.srcq[b + n - 1] && a.qs[a.srcq[b]].direct) return;
-    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(H); i += 64) {
+    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(H); i += 64 * NW) {
         lds_store(&L.key[i], kEmpty);
         L.dw[i] = kWordNone;
     }
-    wave_sync();
-    uint32_t tq = kInf;              // query of tseen
-    unsigned long long tseen = 0;    // its emitted count at this wave's last bound update
-    for (uint32_t t = blockIdx.x; t < 8u * per; t += gridDim.x) {
-        const uint32_t si = (t & 7u) * per + (t >> 3);
-        if (si >= n) continue;
-        if (GEN && a.qs[a.srcq[b + si]].direct) continue;   // answered by k_kcp_direct
-        SrcCtx c = load_ctx(a, a.srcq[b + si]);
-        if (!GEN) {
-            c.k = 0;
-            c.hist = nullptr;
+    if constexpr (NW > 1) {
+        __shared__ BlockRing B;
+        __syncthreads();
+        unsigned long long tseen = 0;
+        uint32_t tq = kInf;
+        for (uint32_t t = blockIdx.x; t < 8u * per; t += gridDim.x) {
+            const uint32_t si = (t & 7u) * per + (t >> 3);
+            if (si >= n) continue;
+            if (GEN && a.qs[a.srcq[b + si]].direct) continue;   // answered by k_kcp_direct
+            SrcCtx c = load_ctx(a, a.srcq[b + si]);
+            if (!GEN) {
+                c.k = 0;
+                c.hist = nullptr;
+            }
+            if (c.q != tq) {
+                tq = c.q;
+                tseen = 0;
+            }
+            search_source_block<HB>(L, B, a, c, a.src[b + si], tseen);
         }
-        if (c.q != tq) {
-            tq = c.q;
-            tseen = 0;
+    } else {
+        wave_sync();
+        uint32_t tq = kInf;              // query of tseen
+        unsigned long long tseen = 0;    // its emitted count at this wave's last bound update
+        for (uint32_t t = blockIdx.x; t < 8u * per; t += gridDim.x) {
+            const uint32_t si = (t & 7u) * per + (t >> 3);
+            if (si >= n) continue;
+            if (GEN && a.qs[a.srcq[b + si]].direct) continue;   // answered by k_kcp_direct
+            SrcCtx c = load_ctx(a, a.srcq[b + si]);
+            if (!GEN) {
+                c.k = 0;
+                c.hist = nullptr;
+            }
+            if (c.q != tq) {
+                tq = c.q;
+                tseen = 0;
+            }
+            if (GEN && c.k != 0 && !a.count_work &&
+                static_cast<uint64_t>(current_bound(c)) < 2ull * static_cast<uint64_t>(c.wmin))
+                direct_pairs<HB>(L, a, c, a.src[b + si], tseen);
+            else
+                search_source<HB>(L, a, c, a.src[b + si], tseen);
         }
-        if (GEN && c.k != 0 && !a.count_work &&
-            static_cast<uint64_t>(current_bound(c)) < 2ull * static_cast<uint64_t>(c.wmin))
-            direct_pairs<HB>(L, a, c, a.src[b + si], tseen);
-        else
-            search_source<HB>(L, a, c, a.src[b + si], tseen);
     }
 }
 
@@ -1714,7 +1938,7 @@ hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, bool persis
         e = hipGetDeviceProperties(&prop, dev);
         if (e != hipSuccess) return e;
         int occ = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_join<HB, GEN>, 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_join<HB, GEN>, 64 * Tier<HB>::NW, 0);
         if (e != hipSuccess) return e;
         cus = prop.multiProcessorCount;
         resident = occ > 0 ? occ : 1;
@@ -1727,7 +1951,7 @@ hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, bool persis
     const uint64_t want = (static_cast<uint64_t>(max_sources) + 7) / 8 * 8;
     if (want < grid || !persistent) grid = want;
     if (grid == 0) grid = 8;
-    hipLaunchKernelGGL((k_join<HB, GEN>), dim3(static_cast<uint32_t>(grid)), dim3(64), 0, s, a);
+    hipLaunchKernelGGL((k_join<HB, GEN>), dim3(static_cast<uint32_t>(grid)), dim3(64 * Tier<HB>::NW), 0, s, a);
     return hipGetLastError();
 }
 
