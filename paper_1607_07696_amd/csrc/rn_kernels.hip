@@ -152,14 +152,16 @@ struct Tier {
     // list capacity: the ring (2 PC entries) holds a search's pending set (at
     // most about 120 vertices for searches that fit 2^11 entries on road
     // graphs, 250 for 2^13 and 370 for 2^14); sized so that a 2^11 table
-    // fits 8 waves per CU, a 2^12 table 4, a 2^13 table (a block of four
-    // waves) 8 and a 2^14 table 4
+    // fits 8 waves per CU, a 2^12 table 4, and the 2^13 and 2^14 tables
+    // (blocks of several waves) 8
     static constexpr int PC = HB <= 11 ? 128 : (HB == 12 ? 256 : (HB == 13 ? 256 : 512));
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
     // waves per search: a large table leaves room for one or two searches
-    // per CU, so four waves share each one (a block); every wave takes 64
-    // vertices per step and has its own window of W arcs
-    static constexpr int NW = HB >= 13 ? 4 : 1;
+    // per CU, so several waves share each one (a block): four for 2^13 (two
+    // searches per CU), eight for 2^14 (one); every wave takes 64 vertices per
+    // step and has its own window of W arcs.  (Eight waves on a 2^13 search
+    // are slower: its pending set is smaller than a step of 512 vertices.)
+    static constexpr int NW = HB >= 14 ? 8 : (HB == 13 ? 4 : 1);
     static constexpr int G = 1;
     static constexpr uint32_t W = kWin * G;
 };
