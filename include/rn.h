@@ -157,7 +157,9 @@ rn_status rn_kcp_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *
 /*
  * Tuning knobs of a handle (they never change results).
  *   delta        bucket width of the bucketed relaxation; 0 = one bucket
- *                (frontier-synchronous relaxation).  Default chosen at load.
+ *                (a FIFO of pending vertices).  Default chosen at load.  Used by
+ *                tables up to 2^11 entries; larger tables, searched by several
+ *                waves together, always use one bucket.
  *   hash_log2    log2 of the per-source LDS table size tried first (8..14);
  *                sources whose search outgrows it are re-run with larger ones.
  *                Until it is set, theta-joins start at 2^11 or at the size the

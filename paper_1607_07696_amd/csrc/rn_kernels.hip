@@ -151,23 +151,23 @@ struct Tier {
     static constexpr int H = 1 << HB;
     // list capacity: the ring (2 PC entries) holds a search's pending set (at
     // most about 120 vertices for searches that fit 2^11 entries on road
-    // graphs, 250 for 2^13 and 370 for 2^14); sized so that a 2^11 table
-    // fits 8 waves per CU, a 2^12 table 4, and the 2^13 and 2^14 tables
-    // (blocks of several waves) 8
-    static constexpr int PC = HB <= 11 ? 128 : (HB == 12 ? 256 : (HB == 13 ? 256 : 512));
+    // graphs, 250 for 2^13 and 370 for 2^14); sized so that every table from
+    // 2^11 on fits 8 waves per CU
+    static constexpr int PC = HB <= 12 ? 128 : (HB == 13 ? 256 : 512);
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
-    // waves per search: a large table leaves room for one or two searches
-    // per CU, so several waves share each one (a block): four for 2^13 (two
-    // searches per CU), eight for 2^14 (one); every wave takes 64 vertices per
-    // step and has its own window of W arcs.  (Eight waves on a 2^13 search
-    // are slower: its pending set is smaller than a step of 512 vertices.)
-    static constexpr int NW = HB >= 14 ? 8 : (HB == 13 ? 4 : 1);
+    // waves per search: a large table leaves room for few searches per CU, so
+    // several waves share each one (a block): two for 2^12 (four searches per
+    // CU), four for 2^13 (two), eight for 2^14 (one); every wave takes 64
+    // vertices per step and has its own window of W arcs.  (More waves per
+    // search are slower where the pending set is smaller than a step: eight
+    // on 2^13, two on 2^11.)
+    static constexpr int NW = HB >= 14 ? 8 : (HB == 13 ? 4 : (HB == 12 ? 2 : 1));
     static constexpr int G = 1;
     static constexpr uint32_t W = kWin * G;
 };
 
 // Ring bookkeeping shared by the waves of a block that runs one search
-// (tables of 2^13 and 2^14 entries).
+// (tables of 2^12 entries and more).
 struct BlockRing {
     uint32_t tail;      // unwrapped ring index of the next append (atomic)
     uint32_t nins;      // table entries in use (atomic)
@@ -823,14 +823,15 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
 }
 
 // The same search by a block of Tier<HB>::NW waves sharing one table (tables
-// of 2^13 and 2^14 entries, which leave room for one or two searches per CU):
+// of 2^12 entries and more, which leave room for few searches per CU):
 // the ring of pending vertices is shared, each step the waves take 64
 // vertices each, put back the ones far above the step's least distance (the
 // deferral of the one-wave search) and expand the rest in windows of their
 // own; appends reserve ring entries with LDS atomics.  Two block barriers
 // per step; every loop that crosses a barrier decides on values read from
 // LDS after a barrier, so the waves always agree.  The delta of the query
-// is not used (one bucket, as with delta = 0: the distances are the same).
+// is not used (one bucket, as with delta = 0: the distances are the same),
+// nor the one-hop shortcut of k-closest pairs (the search finds those pairs).
 template <int HB>
 __device__ void search_source_block(SearchLds<HB> &L, BlockRing &B, const JoinArgs &a, const SrcCtx &c,
                                     int32_t u, unsigned long long &tseen) {
