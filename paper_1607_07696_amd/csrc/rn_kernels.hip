@@ -825,9 +825,9 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
 // The same search by a block of Tier<HB>::NW waves sharing one table (tables
 // of 2^12 entries and more, which leave room for few searches per CU):
 // the ring of pending vertices is shared, each step the waves take 64
-// vertices each, put back the ones far above the step's least distance (the
-// deferral of the one-wave search) and expand the rest in windows of their
-// own; appends reserve ring entries with LDS atomics.  Two block barriers
+// vertices at most each (dealt round-robin), put back the ones far above the
+// step's least distance (the deferral of the one-wave search) and expand the
+// rest in windows of their own; appends reserve ring entries with LDS atomics.  Two block barriers
 // per step; every loop that crosses a barrier decides on values read from
 // LDS after a barrier, so the waves always agree.  The delta of the query
 // is not used (one bucket, as with delta = 0: the distances are the same),
@@ -876,7 +876,10 @@ __device__ void search_source_block(SearchLds<HB> &L, BlockRing &B, const JoinAr
         ++phase;
         const uint32_t bound = current_bound(c);
         const uint32_t m = min(64u * NW, tail - head);
-        const uint32_t mine = wv * 64u + lane;
+        // the step's entries dealt round-robin over the waves: with fewer
+        // than 64 NW pending, every wave gets a share and no window is longer
+        // than it needs to be
+        const uint32_t mine = lane * NW + wv;
         bool valid = mine < m;
         const uint2 eb = q[(head + mine) & (RC - 1u)];
         uint32_t dd = L.dw[valid ? (eb.x & 0xFFFFu) : lane] >> 1;
