@@ -222,53 +222,64 @@ def batch_leg(torch, rn, steps):
     return res
 
 
-def serve_leg(torch, rn, rate_hz=300.0, count=2000):
-    """Poisson stream of joins on the resident 2048x2048 graph: the request
-    server (continuous batching) against the same requests served one at a
-    time, in arrival order, by the single-query calls."""
+def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8):
+    """Poisson streams of joins on the resident 2048x2048 graph through the
+    request server (continuous batching), against the same requests served
+    one at a time, in arrival order, by the single-query calls.  The server's
+    capacity C is measured first (every request submitted at once); the same
+    requests then arrive as Poisson streams at the given fractions of C (the
+    stream's inter-arrival draws only scale with the rate)."""
     import threading
     from paper_1607_07696_amd import roadgen
     MAX = rn.MAX_DIST
     g = roadgen.road_graph(2048, 0)
-    reqs = roadgen.serving_stream(g, count, rate_hz, 5)
-    log(f"serve: graph V={g.V} A={g.A}, {count} requests over {reqs[-1].arrival_s:.2f} s")
+    reqs = roadgen.serving_stream(g, count, 1.0, 5)          # arrival times for 1 request/s
+    log(f"serve: graph V={g.V} A={g.A}, {count} requests")
     net = rn.RoadNetwork.from_graph(g)
     theta_of = [r.theta if r.k == 0 else MAX for r in reqs]
-    # warm-up outside the timed stream
-    srv = rn.Server(net, lanes=2, max_batch=8, global_slots=128, hbm_budget=16 << 30)
-    for r, t in zip(reqs[:8], theta_of[:8]):
-        srv.wait(srv.submit(r.R, r.S, t, r.k))
-    ids = [None] * count
-    t0 = time.perf_counter()
+    srv_cfg = dict(lanes=2, max_batch=8, global_slots=128, hbm_budget=16 << 30)
+    pct = lambda a, q: round(float(np.percentile(a, q)), 3)
 
-    def producer():
-        for i, (r, t) in enumerate(zip(reqs, theta_of)):
-            delay = r.arrival_s - (time.perf_counter() - t0)
-            if delay > 0:
-                time.sleep(delay)
-            ids[i] = srv.submit(r.R, r.S, t, r.k)
-    th = threading.Thread(target=producer)
-    th.start()
-    lat, dks, npairs = [], [], 0
-    for i in range(count):
-        while ids[i] is None:
-            time.sleep(0.0001)
-        out, ms = srv.wait(ids[i])
-        lat.append(ms)
-        if (i + 1) % 250 == 0:
-            log(f"serve: {i + 1} answered, {time.perf_counter() - t0:.2f} s")
-        npairs += out.shape[0]
-        dks.append(int(out["dist"][-1]) if (reqs[i].k and out.shape[0]) else 0)
-    makespan = time.perf_counter() - t0
-    th.join()
-    st = srv.stats()
-    srv.close()
-    log(f"serve: server done in {makespan:.2f} s; the same requests one at a time")
-    # the plain path: each request alone (upload, call, result to the host),
-    # queued first come first served
+    def run_server(scale):
+        """scale: seconds per unit of the 1/s arrival times (0: all at once)."""
+        srv = rn.Server(net, **srv_cfg)
+        for r, t in zip(reqs[:8], theta_of[:8]):                # warm-up outside the timed stream
+            srv.wait(srv.submit(r.R, r.S, t, r.k))
+        ids = [None] * count
+        t0 = time.perf_counter()
+
+        def producer():
+            for i, (r, t) in enumerate(zip(reqs, theta_of)):
+                delay = r.arrival_s * scale - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+                ids[i] = srv.submit(r.R, r.S, t, r.k)
+        th = threading.Thread(target=producer)
+        th.start()
+        lat, dks, npairs = [], [], 0
+        for i in range(count):
+            while ids[i] is None:
+                time.sleep(0.0001)
+            out, ms = srv.wait(ids[i])
+            lat.append(ms)
+            if (i + 1) % 500 == 0:
+                log(f"serve: {i + 1} answered, {time.perf_counter() - t0:.2f} s")
+            npairs += out.shape[0]
+            dks.append(int(out["dist"][-1]) if (reqs[i].k and out.shape[0]) else 0)
+        makespan = time.perf_counter() - t0
+        th.join()
+        st = srv.stats()
+        srv.close()
+        return lat, makespan, st, dks, npairs
+
+    log("serve: capacity (every request submitted at once)")
+    _, cap_span, _, dks, npairs = run_server(0.0)
+    capacity = count / cap_span
+    log(f"serve: capacity {capacity:.0f} requests/s; the same requests one at a time")
+    # the plain path: each request alone (upload, call, result to the host)
     service = []
     for i, (r, t) in enumerate(zip(reqs, theta_of)):
-        if (i + 1) % 250 == 0:
+        if (i + 1) % 500 == 0:
             log(f"serve: plain {i + 1} done, {sum(service):.2f} s")
         a = time.perf_counter()
         Rd = torch.as_tensor(r.R, device="cuda")
@@ -276,10 +287,6 @@ def serve_leg(torch, rn, rate_hz=300.0, count=2000):
         out = net.kcp_join(Rd, Sd, r.k) if r.k else net.dist_join(Rd, Sd, t)
         rn.pairs_to_numpy(out)
         service.append(time.perf_counter() - a)
-    done, plat = 0.0, []
-    for r, s_ in zip(reqs, service):
-        done = max(done, r.arrival_s) + s_
-        plat.append((done - r.arrival_s) * 1e3)
     # work: arcs out of every vertex within theta (theta-joins) or within the
     # k-th distance (k-closest pairs) of each source in R
     log("serve: counting work")
@@ -291,21 +298,117 @@ def serve_leg(torch, rn, rate_hz=300.0, count=2000):
         net.join_batch(specs)
         arcs += int(net.stats()["arcs"])
     net.set_profiling(times=False, work=False)
-    net.close()
-    pct = lambda a, q: round(float(np.percentile(a, q)), 3)
-    return {"workload": (f"{count} requests, Poisson arrivals at {rate_hz:g}/s (seed 5), on the 2048x2048 road "
-                         "graph (seed 0): 60% theta-joins with theta uniform in [500, 8000], 40% k closest "
-                         "pairs with k log-uniform in [1, 4096]; |R|, |S| log-uniform in [64, 32768]"),
-            "V": g.V, "A": g.A, "pairs": int(npairs), "work_arcs": arcs,
-            "server": {"lanes": 2, "max_batch": 8, "global_slots": 128, "hbm_budget_gib": 16,
-                       "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": pct(lat, 100)},
+    streams = {}
+    for f in loads:
+        rate = f * capacity
+        log(f"serve: Poisson stream at {f:g} C = {rate:.0f}/s")
+        lat, makespan, st, _, _ = run_server(1.0 / rate)
+        done, plat = 0.0, []
+        for r, s_ in zip(reqs, service):                       # first come, first served
+            arr = r.arrival_s / rate
+            done = max(done, arr) + s_
+            plat.append((done - arr) * 1e3)
+        streams[f"{f:g}C"] = {
+            "rate_rps": round(rate, 1),
+            "server": {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": pct(lat, 100)},
                        "throughput_rps": round(count / makespan, 1), "makespan_s": round(makespan, 3),
                        "gteps": round(arcs / makespan / 1e9, 3), "stats": st},
             "plain_fifo": {"latency_ms": {"p50": pct(plat, 50), "p99": pct(plat, 99), "max": pct(plat, 100)},
-                           "service_ms": {"p50": pct(np.array(service) * 1e3, 50),
-                                          "p99": pct(np.array(service) * 1e3, 99)},
                            "throughput_rps": round(count / done, 1), "makespan_s": round(done, 3),
                            "gteps": round(arcs / done / 1e9, 3)}}
+    net.close()
+    head = streams[f"{headline:g}C"]
+    return {"workload": (f"{count} requests on the 2048x2048 road graph (seed 0): 60% theta-joins with theta "
+                         "uniform in [500, 8000], 40% k closest pairs with k log-uniform in [1, 4096]; |R|, |S| "
+                         "log-uniform in [64, 32768]; Poisson arrivals (seed 5) at fractions of the server's "
+                         f"measured capacity, headline {headline:g} C"),
+            "V": g.V, "A": g.A, "pairs": int(npairs), "work_arcs": arcs,
+            "config": {"lanes": 2, "max_batch": 8, "global_slots": 128, "hbm_budget_gib": 16},
+            "capacity_rps": round(capacity, 1), "capacity_gteps": round(arcs / cap_span / 1e9, 3),
+            "plain_service_ms": {"p50": pct(np.array(service) * 1e3, 50), "p99": pct(np.array(service) * 1e3, 99),
+                                 "total_s": round(float(np.sum(service)), 3)},
+            "headline": f"{headline:g}C", "server": head["server"], "plain_fifo": head["plain_fifo"],
+            "streams": streams}
+
+
+def partition_study(torch, rn, g, R, S, theta, arcs, steps):
+    """Partition quality against speed: the same theta-join with the sources in
+    the order of Algorithm 1's leaves for several alpha and leaf sizes, and in
+    id order (no partition).  Results never depend on it (tested)."""
+    Rd = torch.as_tensor(R, device="cuda")
+    Sd = torch.as_tensor(S, device="cuda")
+    # (alpha = 0 leaves the two clusters of a bisection unbalanced, so the
+    # recursion runs deep: about 100 s on this graph against 5 s for alpha > 0)
+    alphas = tuple(float(x) for x in os.environ.get("RN_STUDY_ALPHAS", "0.25,0.5,0.75,1").split(","))
+    settings = [("none", None, None)] + [(f"{a:g},{leaf}", a, leaf) for leaf in (64, 256, 1024)
+                                         for a in alphas]
+    rows = []
+    for name, a, leaf in settings:
+        net = rn.RoadNetwork.from_graph(g)
+        part_s = None
+        if a is not None:
+            t0 = time.perf_counter()
+            net.partition(a, leaf)
+            part_s = round(time.perf_counter() - t0, 2)
+        net.set_profiling(times=True)
+        for _ in range(2):
+            net.dist_join(Rd, Sd, theta)
+        torch.cuda.synchronize()
+        rel, wall = [], []
+        for _ in range(steps):
+            t = time.perf_counter()
+            net.dist_join(Rd, Sd, theta)
+            wall.append(time.perf_counter() - t)
+            rel.append(net.stats()["relax_ms"])
+        net.close()
+        ms = float(np.median(wall)) * 1e3
+        rows.append({"partition": name, "partition_s": part_s, "relax_ms": round(float(np.median(rel)), 4),
+                     "ms_per_query": round(ms, 4), "gteps": round(arcs / (ms / 1e3) / 1e9, 3)})
+        log(f"partition {name}: {rows[-1]}")
+    # the generator numbers vertices row by row, so id order is already local;
+    # the same graph and query with the ids shuffled shows what the partition
+    # order restores
+    from paper_1607_07696_amd import roadgen
+    rng = np.random.default_rng(7)
+    perm = rng.permutation(g.V).astype(np.int32)          # old id -> new id
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(g.V, dtype=np.int32)             # new id -> old id
+    deg = np.diff(g.row_ptr)[inv]
+    row = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    col = np.empty(g.A, np.int32)
+    w = np.empty(g.A, np.uint32)
+    for x_new in range(g.V):
+        x = inv[x_new]
+        b, e = g.row_ptr[x], g.row_ptr[x + 1]
+        col[row[x_new]:row[x_new + 1]] = perm[g.col[b:e]]
+        w[row[x_new]:row[x_new + 1]] = g.w[b:e]
+    gs = roadgen.Graph(row, col, w)
+    Rs = torch.as_tensor(perm[R], device="cuda")
+    Ss = torch.as_tensor(perm[S], device="cuda")
+    for name, a, leaf in (("shuffled ids, none", None, None), ("shuffled ids, 1,256", 1.0, 256),
+                          ("shuffled ids, 0.5,256", 0.5, 256)):
+        net = rn.RoadNetwork.from_graph(gs)
+        part_s = None
+        if a is not None:
+            t0 = time.perf_counter()
+            net.partition(a, leaf)
+            part_s = round(time.perf_counter() - t0, 2)
+        net.set_profiling(times=True)
+        for _ in range(2):
+            net.dist_join(Rs, Ss, theta)
+        torch.cuda.synchronize()
+        rel, wall = [], []
+        for _ in range(steps):
+            t = time.perf_counter()
+            net.dist_join(Rs, Ss, theta)
+            wall.append(time.perf_counter() - t)
+            rel.append(net.stats()["relax_ms"])
+        net.close()
+        ms = float(np.median(wall)) * 1e3
+        rows.append({"partition": name, "partition_s": part_s, "relax_ms": round(float(np.median(rel)), 4),
+                     "ms_per_query": round(ms, 4), "gteps": round(arcs / (ms / 1e3) / 1e9, 3)})
+        log(f"partition {name}: {rows[-1]}")
+    return rows
 
 
 def cpu_baseline(g, R, S, theta, arcs_total, budget_s):
@@ -342,6 +445,8 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving leg")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run one 256 MiB device copy (counter calibration)")
+    ap.add_argument("--partition-study", action="store_true",
+                    help="only time the workload under several partitions (alpha x leaf size, and none)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -378,6 +483,11 @@ def main():
     arcs, settled, npairs = st["arcs"], st["settled"], st["pairs"]
     log(f"work: arcs={arcs} settled={settled} pairs={npairs}")
     net.set_profiling(times=True, work=False)
+    if args.partition_study:
+        rows = partition_study(torch, rn, g, R, S, theta, arcs, args.steps)
+        print(json.dumps({"study": "source order by partition (Algorithm 1): eager theta-join, median of "
+                          f"{args.steps} calls each", "workload": desc, "arcs": arcs, "rows": rows}))
+        return
 
     # eager single-query calls (rn_dist_join), with per-stage HIP-event times
     for _ in range(args.warmup):
