@@ -369,20 +369,7 @@ def partition_study(torch, rn, g, R, S, theta, arcs, steps):
     # the same graph and query with the ids shuffled shows what the partition
     # order restores
     from paper_1607_07696_amd import roadgen
-    rng = np.random.default_rng(7)
-    perm = rng.permutation(g.V).astype(np.int32)          # old id -> new id
-    inv = np.empty_like(perm)
-    inv[perm] = np.arange(g.V, dtype=np.int32)             # new id -> old id
-    deg = np.diff(g.row_ptr)[inv]
-    row = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
-    col = np.empty(g.A, np.int32)
-    w = np.empty(g.A, np.uint32)
-    for x_new in range(g.V):
-        x = inv[x_new]
-        b, e = g.row_ptr[x], g.row_ptr[x + 1]
-        col[row[x_new]:row[x_new + 1]] = perm[g.col[b:e]]
-        w[row[x_new]:row[x_new + 1]] = g.w[b:e]
-    gs = roadgen.Graph(row, col, w)
+    gs, perm = roadgen.shuffle_ids(g, 7)
     Rs = torch.as_tensor(perm[R], device="cuda")
     Ss = torch.as_tensor(perm[S], device="cuda")
     for name, a, leaf in (("shuffled ids, none", None, None), ("shuffled ids, 1,256", 1.0, 256),

@@ -116,13 +116,24 @@ rn_status rn_partition_host(int32_t V, int64_t A, const int32_t *row_ptr, const 
 
 /*
  * rn_partition -- partition each graph of a handle (as rn_partition_host) and
- * keep the leaf-by-leaf vertex order in the handle.  Later joins visit their
- * sources in that order, so sources of one leaf run next to each other on the
- * device (well-separated regions, Section 3).  Join results never depend on it.
+ * renumber the handle's device copy of a graph in the leaf-by-leaf vertex
+ * order where that keeps the two ends of its arcs closer together (mean id
+ * distance over the arcs) than the numbering it was loaded with: the arcs of
+ * the vertices of one leaf then sit next to each other in memory, and joins
+ * visit their sources leaf by leaf (well-separated regions, Section 3).  A
+ * graph loaded with a numbering that is already local keeps it.  Ids at the
+ * boundary stay the caller's: R, S and the pairs of every call use the
+ * numbering the graph was loaded with.  Join results never depend on it.
+ * Waits for the device; do not call it while work of the handle (a plan
+ * replay) is running (a server holds the handle: RN_ERR_BUSY).
  *   part_out  host int32[total V] or NULL: the leaf id of each vertex, graph
  *             after graph; leaf ids are numbered on across the graphs
  */
 rn_status rn_partition(rn_graph *g, float alpha, int32_t max_leaf, int32_t *part_out);
+
+/* 1 if rn_partition renumbered the device copy of graph `graph` of the handle
+ * in leaf order, else 0 (also for a bad handle or index). */
+int32_t rn_graph_renumbered(const rn_graph *g, int32_t graph);
 
 /*
  * rn_dist_join -- the theta-join (on graph 0 of the handle).

@@ -362,7 +362,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     const CallBuffers b = call_buffers(ws, p);
     record(g, ws, timed, EV_START, s);
     RN_HIP(launch_fill_u32(ws.d_block, p.zero_words, 0u, s), "clearing call state");
-    RN_HIP(launch_stage(b, p.total_elems, g->d_rank, g->d_order, s), "staging the queries");
+    RN_HIP(launch_stage(b, p.total_elems, g->d_rank, s), "staging the queries");
     record(g, ws, timed, EV_STAGED, s);
 
     JoinArgs a;
@@ -380,6 +380,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     a.binbase = b.binbase;
     a.count_work = g->count_work ? 1 : 0;
     a.big_deg = g->big_deg ? 1 : 0;
+    a.order = g->d_order;
     if (p.any_kcp) {
         JoinArgs k = a;
         k.src = b.src;
@@ -605,6 +606,86 @@ const char *rn_last_error(void) { return last_error().c_str(); }
 
 const char *rn_version(void) { return "rn 0.2 (gfx950)"; }
 
+}  // extern "C"
+
+namespace {
+
+// Graph index of global vertex x.
+int32_t graph_of(const rn_graph *g, int32_t x) {
+    return static_cast<int32_t>(std::upper_bound(g->voff.begin(), g->voff.end(), x) - g->voff.begin()) - 1;
+}
+
+// Build the device copy of the resident graphs from the host CSR (caller
+// numbering), with global vertex x renumbered perm[x] (perm null: as is), and
+// copy it into g->d_row_ptr / g->d_arcs (allocated on the first call; the
+// size never changes, so plans captured earlier keep valid pointers).  Arc
+// records carry their target's arc range; with g->rev_rpo the reversed arcs
+// follow the forward ones.
+rn_status upload_csr(rn_graph *g, const int32_t *perm) {
+    const int32_t V = g->V;
+    const int64_t A = g->A;
+    const bool rev = g->rev_rpo != 0;
+    std::vector<int32_t> rp, cl, rrp, rcl;
+    std::vector<uint32_t> ww, rww;
+    std::vector<ArcRec> arcs;
+    try {
+        rp.assign(static_cast<size_t>(V) + 1, 0);
+        cl.resize(static_cast<size_t>(A));
+        ww.resize(static_cast<size_t>(A));
+        std::vector<int32_t> inv(static_cast<size_t>(V));
+        for (int32_t x = 0; x < V; ++x) inv[perm ? perm[x] : x] = x;
+        for (int32_t i = 0; i < V; ++i) rp[i + 1] = rp[i] + (g->row_ptr[inv[i] + 1] - g->row_ptr[inv[i]]);
+        for (int32_t i = 0; i < V; ++i) {
+            int32_t o = rp[i];
+            for (int32_t a = g->row_ptr[inv[i]]; a < g->row_ptr[inv[i] + 1]; ++a, ++o) {
+                cl[o] = perm ? perm[g->col[a]] : g->col[a];
+                ww[o] = g->w[a];
+            }
+        }
+        if (rev) {
+            rrp.assign(static_cast<size_t>(V) + 1, 0);
+            rcl.resize(static_cast<size_t>(A));
+            rww.resize(static_cast<size_t>(A));
+            for (int64_t a = 0; a < A; ++a) rrp[cl[a] + 1] += 1;
+            for (int32_t x = 0; x < V; ++x) rrp[x + 1] += rrp[x];
+            std::vector<int32_t> fill(rrp.begin(), rrp.end() - 1);
+            for (int32_t x = 0; x < V; ++x)
+                for (int32_t a = rp[x]; a < rp[x + 1]; ++a) {
+                    const int32_t b = fill[cl[a]]++;
+                    rcl[b] = x;
+                    rww[b] = ww[a];
+                }
+        }
+        arcs.resize(static_cast<size_t>(A) * (rev ? 2 : 1));
+        for (int64_t a = 0; a < A; ++a) {
+            const int32_t y = cl[a];
+            arcs[a] = ArcRec{y, ww[a], rp[y], rp[y + 1]};
+        }
+        if (rev) {
+            for (int64_t b = 0; b < A; ++b) {
+                const int32_t y = rcl[b];
+                arcs[A + b] = ArcRec{y, rww[b], static_cast<int32_t>(A) + rrp[y], static_cast<int32_t>(A) + rrp[y + 1]};
+            }
+            for (int32_t x = 0; x <= V; ++x) rp.push_back(static_cast<int32_t>(A) + rrp[x]);
+        }
+    } catch (...) {
+        return fail(RN_ERR_NOMEM, "building the device graph");
+    }
+    hipError_t e = hipSuccess;
+    if (!g->d_row_ptr && (e = dev_alloc(&g->d_row_ptr, rp.size())) != hipSuccess)
+        return hip_fail(e, "uploading the graph");
+    if (!g->d_arcs && (e = dev_alloc(&g->d_arcs, arcs.size())) != hipSuccess) return hip_fail(e, "uploading the graph");
+    if ((e = hipMemcpy(g->d_row_ptr, rp.data(), rp.size() * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (!arcs.empty() &&
+         (e = hipMemcpy(g->d_arcs, arcs.data(), arcs.size() * sizeof(ArcRec), hipMemcpyHostToDevice)) != hipSuccess))
+        return hip_fail(e, "uploading the graph");
+    return RN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, const int32_t *const *row_ptr,
                              const int32_t *const *col, const uint32_t *const *w, rn_graph **out) {
     if (!out) return fail(RN_ERR_ARG, "out is NULL");
@@ -630,7 +711,6 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
     g->ngraphs = n;
     g->V = static_cast<int32_t>(totV);
     g->A = totA;
-    std::vector<ArcRec> arcs;
     try {
         g->voff.assign(n + 1, 0);
         g->aoff.assign(n + 1, 0);
@@ -641,7 +721,6 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
         g->row_ptr.resize(static_cast<size_t>(totV) + 1);
         g->col.resize(static_cast<size_t>(totA));
         g->w.resize(static_cast<size_t>(totA));
-        arcs.resize(static_cast<size_t>(totA));
     } catch (...) {
         delete g;
         return fail(RN_ERR_NOMEM, "copying the CSR");
@@ -705,31 +784,22 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
     const bool keep_rev = !symmetric && 2 * totA < 0x7FFFFFFFLL;
     g->can_swap = symmetric || keep_rev;
     g->rev_rpo = keep_rev ? static_cast<uint32_t>(totV + 1) : 0u;
-    const size_t nrow = (static_cast<size_t>(totV) + 1) * (keep_rev ? 2 : 1);
-    const size_t narc = static_cast<size_t>(totA) * (keep_rev ? 2 : 1);
-    std::vector<int32_t> rows(g->row_ptr);
-    try {
-        arcs.resize(narc);
-        if (keep_rev)
-            for (int32_t x = 0; x <= totV; ++x) rows.push_back(static_cast<int32_t>(totA) + rrow[x]);
-    } catch (...) {
-        delete g;
-        return fail(RN_ERR_NOMEM, "copying the CSR");
-    }
-    for (int64_t a = 0; a < totA; ++a) {
-        const int32_t y = g->col[a];
-        arcs[a] = ArcRec{y, g->w[a], g->row_ptr[y], g->row_ptr[y + 1]};
-    }
-    if (keep_rev)
-        for (int64_t b = 0; b < totA; ++b) {
-            const int32_t y = rcol[b];
-            arcs[totA + b] = ArcRec{y, rw[b], static_cast<int32_t>(totA) + rrow[y], static_cast<int32_t>(totA) + rrow[y + 1]};
-        }
-    rn_status st = RN_OK;
-    if ((e = dev_alloc(&g->d_row_ptr, nrow)) != hipSuccess || (e = dev_alloc(&g->d_arcs, narc)) != hipSuccess ||
-        (e = hipMemcpy(g->d_row_ptr, rows.data(), nrow * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
-        (narc > 0 && (e = hipMemcpy(g->d_arcs, arcs.data(), narc * sizeof(ArcRec), hipMemcpyHostToDevice)) != hipSuccess)) {
-        st = hip_fail(e, "uploading the graph");
+    rcol.clear();
+    rw.clear();
+    // the resident copy, in the caller's numbering until rn_partition, and the
+    // identity maps between the two numberings
+    rn_status st = upload_csr(g, nullptr);
+    if (st == RN_OK) {
+        std::vector<int32_t> ident(static_cast<size_t>(totV));
+        for (int32_t i = 0; i < totV; ++i) ident[i] = i - g->voff[graph_of(g, i)];
+        std::vector<int32_t> rank_ident(ident);
+        if ((e = dev_alloc(&g->d_rank, static_cast<size_t>(totV))) != hipSuccess ||
+            (e = dev_alloc(&g->d_order, static_cast<size_t>(totV))) != hipSuccess ||
+            (totV > 0 && ((e = hipMemcpy(g->d_rank, rank_ident.data(), ident.size() * sizeof(int32_t),
+                                         hipMemcpyHostToDevice)) != hipSuccess ||
+                          (e = hipMemcpy(g->d_order, ident.data(), ident.size() * sizeof(int32_t),
+                                         hipMemcpyHostToDevice)) != hipSuccess)))
+            st = hip_fail(e, "uploading the vertex maps");
     }
     if (st != RN_OK) {
         rn_graph_free(g);
@@ -817,6 +887,18 @@ rn_status rn_partition(rn_graph *g, float alpha, int32_t max_leaf, int32_t *part
     for (auto &t : pool) t.join();
     for (int32_t i = 0; i < n; ++i)
         if (!ok[i]) return fail(RN_ERR_NOMEM, msgs[i]);
+    // within a leaf, keep the caller's order (the leaves are what the
+    // partition contributes; a graph numbered with locality keeps it inside them)
+    for (int32_t i = 0; i < n; ++i) {
+        std::vector<int32_t> &o = orders[i];
+        const std::vector<int32_t> &pt = parts[i];
+        for (size_t b = 0; b < o.size();) {
+            size_t e = b + 1;
+            while (e < o.size() && pt[o[e]] == pt[o[b]]) ++e;
+            std::sort(o.begin() + static_cast<std::ptrdiff_t>(b), o.begin() + static_cast<std::ptrdiff_t>(e));
+            b = e;
+        }
+    }
     std::vector<int32_t> rank(static_cast<size_t>(g->V)), order(static_cast<size_t>(g->V));
     int32_t leaf0 = 0;
     for (int32_t i = 0; i < n; ++i) {
@@ -832,13 +914,44 @@ rn_status rn_partition(rn_graph *g, float alpha, int32_t max_leaf, int32_t *part
         }
         leaf0 += nleaf;
     }
+    // the resident copy of a graph is renumbered in leaf order (in place: plans
+    // captured earlier stay valid) where that keeps the two ends of its arcs
+    // closer together than the loaded numbering does: mean |id(x) - id(y)|
+    // over the arcs, which ranks the numberings of the synthetic road graphs
+    // as their search times do (row by row 542, leaf order 1 499, shuffled
+    // 349 000 on the 1024^2 graph); otherwise it stays as loaded
+    std::vector<int32_t> perm(static_cast<size_t>(g->V));
+    g->renumbered.assign(static_cast<size_t>(n), 0);
+    for (int32_t i = 0; i < n; ++i) {
+        const int32_t vo = g->voff[i], V = g->voff[i + 1] - vo;
+        double as_loaded = 0, leaf = 0;
+        for (int32_t x = 0; x < V; ++x)
+            for (int32_t a = g->row_ptr[vo + x]; a < g->row_ptr[vo + x + 1]; ++a) {
+                const int32_t y = g->col[a] - vo;
+                as_loaded += std::abs(static_cast<double>(x) - y);
+                leaf += std::abs(static_cast<double>(rank[vo + x]) - rank[vo + y]);
+            }
+        g->renumbered[i] = leaf < as_loaded ? 1 : 0;
+        for (int32_t x = 0; x < V; ++x) {
+            if (!g->renumbered[i]) {
+                rank[vo + x] = x;
+                order[vo + x] = x;
+            }
+            perm[vo + x] = vo + rank[vo + x];
+        }
+    }
     RN_HIP(hipSetDevice(g->device), "selecting the device");
-    if (!g->d_rank) RN_HIP(dev_alloc(&g->d_rank, static_cast<size_t>(g->V)), "allocating ranks");
-    if (!g->d_order) RN_HIP(dev_alloc(&g->d_order, static_cast<size_t>(g->V)), "allocating ranks");
+    RN_HIP(hipDeviceSynchronize(), "waiting for the device");
+    RN_TRY(upload_csr(g, perm.data()));
     RN_HIP(hipMemcpy(g->d_rank, rank.data(), rank.size() * sizeof(int32_t), hipMemcpyHostToDevice), "uploading ranks");
     RN_HIP(hipMemcpy(g->d_order, order.data(), order.size() * sizeof(int32_t), hipMemcpyHostToDevice),
            "uploading ranks");
     return RN_OK;
+}
+
+int32_t rn_graph_renumbered(const rn_graph *g, int32_t graph) {
+    if (!g || graph < 0 || graph >= g->ngraphs || g->renumbered.empty()) return 0;
+    return g->renumbered[static_cast<size_t>(graph)];
 }
 
 rn_status rn_set_tuning(rn_graph *g, int64_t delta, int32_t hash_log2) {

@@ -196,8 +196,12 @@ struct rn_graph {
 
     int32_t *d_row_ptr = nullptr;
     rn::ArcRec *d_arcs = nullptr;
-    int32_t *d_rank = nullptr;      // global vertex -> rank within its graph (nullptr = identity)
-    int32_t *d_order = nullptr;     // voff + rank -> local vertex
+    // The device copy of the graphs is numbered in partition-leaf order once
+    // rn_partition has run (identity until then); the two maps, both
+    // allocated at load:
+    int32_t *d_rank = nullptr;      // global vertex (caller numbering) -> local id in the device copy
+    int32_t *d_order = nullptr;     // global vertex of the device copy -> local id in the caller numbering
+    std::vector<char> renumbered;   // per graph: the device copy is in leaf order (else as loaded)
 
     uint32_t delta = 0;
     int hash_log2 = 11;

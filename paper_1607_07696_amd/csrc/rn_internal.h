@@ -153,6 +153,7 @@ struct JoinArgs {
     int32_t tier;               // 0 first table, 1 and 2 the re-run tables, 3 the global tier
     int32_t count_work;         // 1: accumulate ctl->arcs / ctl->settled
     int32_t big_deg;            // 1: some vertex has 2^16 or more arcs (searches reaching one move on)
+    const int32_t *order;       // global vertex of the device copy -> local id in the caller's numbering
 };
 
 // State of the global-memory tier: n slots (one per concurrent block), V the
@@ -197,12 +198,11 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 // the host then only waits for the stream, with no copy queued after the call.
 hipError_t launch_publish(const uint32_t *src, uint32_t *dst, uint32_t words, hipStream_t s);
 
-// Validate every query's R and S, set the S bitmaps and rank bitmaps, and list
-// the sources query by query (staging order) in rank order.
-// rank/order: per-graph vertex order (nullptr: identity).  max_elems: sum of
-// nS + nR over the queries.
-hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, const int32_t *rank,
-                        const int32_t *order, hipStream_t s);
+// Validate every query's R and S, set the S bitmaps and rank bitmaps (both in
+// the device copy's numbering), and list the sources query by query (staging
+// order) in that numbering.  rank: caller's global vertex -> local id in the
+// device copy (nullptr: identity).  max_elems: sum of nS + nR over the queries.
+hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, const int32_t *rank, hipStream_t s);
 size_t stage_scratch_words(size_t rwords);
 
 // Relaxation at the on-chip tier with table size 2^hash_log2.  generic =

@@ -274,6 +274,12 @@ __device__ __forceinline__ bool in_s(const SrcCtx &c, uint32_t y) {
     return (c.sbits[yl >> 5] >> (yl & 31u)) & 1u;
 }
 
+// The caller's local id of global vertex x of the device copy (which
+// rn_partition renumbers in leaf order).
+__device__ __forceinline__ int32_t caller_id(const JoinArgs &a, int32_t x, int32_t voff) {
+    return a.order ? a.order[x] : x - voff;
+}
+
 // Discoveries a query's searches count per tier before they stop: enough for
 // a close bound, few enough to keep the histogram atomics cheap.
 __device__ __forceinline__ uint32_t probe_cap(const SrcCtx &c) { return max(4u * c.k, 256u); }
@@ -509,7 +515,7 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
         if (idx < a.rec_cap) {
             Rec r;
             const uint2 e = stg[i];
-            const int32_t from = u - c.voff, to = static_cast<int32_t>(e.y) - c.voff;
+            const int32_t from = caller_id(a, u, c.voff), to = caller_id(a, static_cast<int32_t>(e.y), c.voff);
             r.u = c.swapped ? to : from;
             r.v = c.swapped ? from : to;
             r.d = e.x;
@@ -1306,8 +1312,10 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                 const unsigned long long idx = base + mbcnt(mm);
                 if (m && idx < a.rec_cap) {
                     Rec rr;
-                    rr.u = c.swapped ? static_cast<int32_t>(yl) : u - c.voff;
-                    rr.v = c.swapped ? u - c.voff : static_cast<int32_t>(yl);
+                    const int32_t cy = caller_id(a, static_cast<int32_t>(yl) + c.voff, c.voff);
+                    const int32_t cu = caller_id(a, u, c.voff);
+                    rr.u = c.swapped ? cy : cu;
+                    rr.v = c.swapped ? cu : cy;
                     rr.d = d;
                     rr.q = c.q;
                     a.recs[idx] = rr;
@@ -1369,10 +1377,11 @@ __global__ void k_mark(CallBuffers b, const int32_t *rank) {
     const unsigned long long j = i - b.ebase[p];
     uint32_t err = 0;
     if (j < static_cast<unsigned long long>(d.nS)) {
-        const int32_t s = d.S[j];
-        if (s < 0 || s >= d.V) {
+        const int32_t s0 = d.S[j];
+        if (s0 < 0 || s0 >= d.V) {
             err = kErrRange;
         } else {
+            const int32_t s = rank ? rank[d.voff + s0] : s0;   // local id in the device copy
             const uint32_t bit = 1u << (s & 31);
             if (atomicOr(&b.sbits[d.sbits + (s >> 5)], bit) & bit) err = kErrDupS;
         }
@@ -1394,7 +1403,7 @@ __global__ void k_mark(CallBuffers b, const int32_t *rank) {
 
 // R and S must be disjoint: element i of the flattened lists, if it is in
 // some R, must not be in that query's S.
-__device__ __forceinline__ void check_overlap(const CallBuffers &b, unsigned long long i) {
+__device__ __forceinline__ void check_overlap(const CallBuffers &b, const int32_t *rank, unsigned long long i) {
     const uint32_t nq = static_cast<uint32_t>(b.nq);
     if (i >= b.ebase[nq]) return;
     const uint32_t p = seg_of(b.ebase, nq, i);
@@ -1402,8 +1411,10 @@ __device__ __forceinline__ void check_overlap(const CallBuffers &b, unsigned lon
     const QueryDesc &d = b.qd[q];
     const unsigned long long j = i - b.ebase[p];
     if (j < static_cast<unsigned long long>(d.nS)) return;
-    const int32_t u = d.R[j - d.nS];
-    if (u >= 0 && u < d.V && ((b.sbits[d.sbits + (u >> 5)] >> (u & 31)) & 1u)) {
+    const int32_t u0 = d.R[j - d.nS];
+    if (u0 < 0 || u0 >= d.V) return;
+    const int32_t u = rank ? rank[d.voff + u0] : u0;   // local id in the device copy
+    if ((b.sbits[d.sbits + (u >> 5)] >> (u & 31)) & 1u) {
         atomicOr(&b.qs[q].err, kErrOverlap);
         atomicOr(&b.ctl->err, kErrOverlap);
     }
@@ -1430,9 +1441,9 @@ __device__ __forceinline__ uint32_t block_excl_scan_1024(uint32_t v, uint32_t *w
 // After the marks, in one launch: the disjointness check (thread i takes
 // element i of the flattened lists) and source listing pass 1, the marked
 // ranks per 1024-word block of the rank pool (the first nblk blocks).
-__global__ __launch_bounds__(1024) void k_overlap_count(CallBuffers b, uint32_t nblk) {
+__global__ __launch_bounds__(1024) void k_overlap_count(CallBuffers b, const int32_t *rank, uint32_t nblk) {
     __shared__ uint32_t wsum[16];
-    check_overlap(b, blockIdx.x * 1024ull + threadIdx.x);
+    check_overlap(b, rank, blockIdx.x * 1024ull + threadIdx.x);
     if (blockIdx.x >= nblk) return;
     const uint32_t i = blockIdx.x * 1024u + threadIdx.x;
     uint32_t total;
@@ -1443,7 +1454,7 @@ __global__ __launch_bounds__(1024) void k_overlap_count(CallBuffers b, uint32_t 
 // Source listing, pass 2: list the marked ranks in increasing pool order as
 // global vertex ids with their queries; the first word of each query records
 // where its sources start.
-__global__ __launch_bounds__(1024) void k_rank_emit(CallBuffers b, const uint32_t *bsum, const int32_t *order) {
+__global__ __launch_bounds__(1024) void k_rank_emit(CallBuffers b, const uint32_t *bsum) {
     __shared__ uint32_t wsum[16];
     const uint32_t tid = threadIdx.x;
     uint32_t acc = 0;
@@ -1464,7 +1475,7 @@ __global__ __launch_bounds__(1024) void k_rank_emit(CallBuffers b, const uint32_
         while (bits) {
             const uint32_t bt = __ffs(bits) - 1u;
             const int32_t r = static_cast<int32_t>(lw * 32u + bt);
-            b.src[pos] = voff + (order ? order[voff + r] : r);
+            b.src[pos] = voff + r;   // the rank is the local id in the device copy
             b.srcq[pos] = q;
             ++pos;
             bits &= bits - 1u;
@@ -1572,7 +1583,7 @@ __global__ __launch_bounds__(256) void k_kcp_direct(JoinArgs a) {
         if (!direct_pair(a, c, b, e, x, bound, r)) continue;
         atomicAdd(&c.hist[kHistEmit + dist_bin(r.w)], 1u);
         if (idx < a.rec_cap) {
-            const int32_t from = u - c.voff, to = r.y - c.voff;
+            const int32_t from = caller_id(a, u, c.voff), to = caller_id(a, r.y, c.voff);
             Rec o;
             o.u = c.swapped ? to : from;
             o.v = c.swapped ? from : to;
@@ -1981,14 +1992,13 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
 
 size_t stage_scratch_words(size_t rwords) { return (rwords + 1023) / 1024 + 1; }
 
-hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, const int32_t *rank,
-                        const int32_t *order, hipStream_t s) {
+hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, const int32_t *rank, hipStream_t s) {
     const uint32_t eblk = static_cast<uint32_t>((max_elems + 255) / 256);
     hipLaunchKernelGGL(k_mark, dim3(eblk), dim3(256), 0, s, b, rank);
     const uint32_t nblk = (b.rwords + 1023u) / 1024u;
     const uint32_t oblk = static_cast<uint32_t>((max_elems + 1023) / 1024);
-    hipLaunchKernelGGL(k_overlap_count, dim3(max(nblk, oblk)), dim3(1024), 0, s, b, nblk);
-    hipLaunchKernelGGL(k_rank_emit, dim3(nblk), dim3(1024), 0, s, b, b.stage_scratch, order);
+    hipLaunchKernelGGL(k_overlap_count, dim3(max(nblk, oblk)), dim3(1024), 0, s, b, rank, nblk);
+    hipLaunchKernelGGL(k_rank_emit, dim3(nblk), dim3(1024), 0, s, b, b.stage_scratch);
     return hipGetLastError();
 }
 

@@ -21,7 +21,7 @@ PAIR_DTYPE = np.dtype([("u", "<i4"), ("v", "<i4"), ("dist", "<u4")])
 # Every symbol include/rn.h declares.
 EXPORTS = (
     "rn_graph_load", "rn_graph_free", "rn_graph_num_vertices", "rn_graph_num_arcs",
-    "rn_partition_host", "rn_partition", "rn_dist_join", "rn_kcp_join",
+    "rn_partition_host", "rn_partition", "rn_graph_renumbered", "rn_dist_join", "rn_kcp_join",
     "rn_set_tuning", "rn_get_tuning", "rn_set_profiling", "rn_last_stats",
     "rn_last_error", "rn_version",
     "rn_graph_load_many", "rn_graph_count", "rn_graph_size", "rn_join_batch", "rn_autotune",
@@ -95,6 +95,7 @@ def load_library(path: str = LIB_PATH):
     lib.rn_partition_host.argtypes = [C.c_int32, C.c_int64, i32p, i32p, u32p, C.c_float, C.c_int32,
                                       i32p, i32p]
     lib.rn_partition.argtypes = [vp, C.c_float, C.c_int32, i32p]
+    lib.rn_graph_renumbered.argtypes = [vp, C.c_int32]
     lib.rn_dist_join.argtypes = [vp, vp, C.c_int32, vp, C.c_int32, C.c_uint32, vp, C.c_int64, i64p, vp]
     lib.rn_kcp_join.argtypes = [vp, vp, C.c_int32, vp, C.c_int32, C.c_int32, vp, C.c_int64, i64p, vp]
     lib.rn_set_tuning.argtypes = [vp, C.c_int64, C.c_int32]
@@ -120,7 +121,7 @@ def load_library(path: str = LIB_PATH):
     lib.rn_server_free.restype = None
     lib.rn_last_error.restype = C.c_char_p
     lib.rn_version.restype = C.c_char_p
-    for name in ("rn_graph_load", "rn_graph_num_vertices", "rn_partition_host", "rn_partition",
+    for name in ("rn_graph_load", "rn_graph_num_vertices", "rn_partition_host", "rn_partition", "rn_graph_renumbered",
                  "rn_dist_join", "rn_kcp_join", "rn_set_tuning", "rn_get_tuning",
                  "rn_set_profiling", "rn_last_stats", "rn_graph_load_many", "rn_graph_count",
                  "rn_graph_size", "rn_join_batch", "rn_autotune", "rn_plan_create", "rn_plan_run",
@@ -220,6 +221,10 @@ class RoadNetwork:
         _check(load_library().rn_partition(self._h, float(alpha), int(max_leaf),
                                            part.ctypes.data_as(C.POINTER(C.c_int32))))
         return part
+
+    def renumbered(self, graph: int = 0) -> bool:
+        """Whether rn_partition put the device copy of `graph` in leaf order."""
+        return bool(load_library().rn_graph_renumbered(self._h, int(graph)))
 
     def set_tuning(self, delta: int = -1, hash_log2: int = -1):
         _check(load_library().rn_set_tuning(self._h, int(delta), int(hash_log2)))

@@ -277,6 +277,23 @@ class Request:
     k: int          # 0 for a theta-join
 
 
+def shuffle_ids(g: Graph, seed: int) -> tuple[Graph, np.ndarray]:
+    """The same graph with its vertex ids permuted at random (no locality left
+    in the numbering); returns it and perm (old id -> new id)."""
+    perm = np.random.default_rng(seed).permutation(g.V).astype(np.int32)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(g.V, dtype=np.int32)
+    deg = np.diff(g.row_ptr)[inv]
+    row = np.concatenate([[0], np.cumsum(deg)]).astype(np.int32)
+    col = np.empty(g.A, np.int32)
+    w = np.empty(g.A, np.uint32)
+    for xn in range(g.V):
+        b, e = g.row_ptr[inv[xn]], g.row_ptr[inv[xn] + 1]
+        col[row[xn]:row[xn + 1]] = perm[g.col[b:e]]
+        w[row[xn]:row[xn + 1]] = g.w[b:e]
+    return Graph(row, col, w), perm
+
+
 def serving_stream(g: Graph, count: int, rate_hz: float, seed: int = 5, *,
                    kcp_frac: float = 0.4) -> list[Request]:
     """Poisson request stream: ``kcp_frac`` k-closest-pairs requests, the rest theta-joins.

@@ -264,3 +264,75 @@ def test_searches_from_the_smaller_side(rnmod, orc, rg, graph):
     with pytest.raises(rnmod.RnError) as ei:
         net.dist_join(R, S2, 100)
     assert "duplicate in S" in str(ei.value)
+
+
+def shuffled(rg, g, seed):
+    """The same graph with its vertex ids permuted (no locality left in them)."""
+    return rg.shuffle_ids(g, seed)[0]
+
+
+@pytest.mark.parametrize("graph", ["road", "directed"])
+def test_renumbered_device_copy(rnmod, orc, rg, graph):
+    # rn_partition renumbers the device copy in leaf order when that is more
+    # local than the loaded ids (shuffled ids here); R, S and the pairs stay in
+    # the caller's ids, also for searches from S over the reversed arcs
+    # (directed graph), through the global tier (theta = max) and for k closest
+    # pairs answered by direct arcs or by searches
+    if graph == "road":
+        g = shuffled(rg, rg.road_graph(96, 4), 40)
+    else:
+        g = rg.random_digraph(3000, 12000, 33, wmin=1, wmax=60, zero_frac=0.2)
+    net = rnmod.RoadNetwork.from_graph(g)
+    assert not net.renumbered(0)
+    net.partition(0.5, 64)
+    assert net.renumbered(0)
+    for nR, nS, seed in ((900, 60, 34), (60, 900, 35)):
+        R, S = rg.sample_disjoint(g.V, nR, nS, seed)
+        for theta in (0, 40, 1500, 0xFFFFFFFE):
+            assert_same(gpu_join(rnmod, net, R, S, theta), orc.dist_join(g, R, S, theta).pairs)
+        for k in (1, 77, 5000):
+            assert_same(rnmod.pairs_to_numpy(net.kcp_join(R, S, k)), orc.kcp_join(g, R, S, k))
+    # a second partition renumbers again, from the caller's numbering
+    net.partition(1.0, 256)
+    assert net.renumbered(0)
+    R, S = rg.sample_disjoint(g.V, 500, 500, 36)
+    assert_same(gpu_join(rnmod, net, R, S, 2000), orc.dist_join(g, R, S, 2000).pairs)
+
+
+def test_local_numbering_is_kept(rnmod, orc, rg):
+    # a road graph numbered row by row is already more local than leaf order
+    g = rg.road_graph(96, 4)
+    net = rnmod.RoadNetwork.from_graph(g)
+    net.partition(1.0, 64)
+    assert not net.renumbered(0)
+    R, S = rg.sample_disjoint(g.V, 400, 400, 39)
+    assert_same(gpu_join(rnmod, net, R, S, 2000), orc.dist_join(g, R, S, 2000).pairs)
+
+
+def test_renumbered_handle_of_several_graphs_and_plans(rnmod, orc, rg):
+    # per-graph id ranges of a multi-graph handle; a plan captured before the
+    # partition keeps answering correctly after it (the device copy is
+    # renumbered in place)
+    g1, g2 = rg.road_graph(64, 5), shuffled(rg, rg.road_graph(80, 6), 41)   # only g2 is renumbered
+    net = rnmod.RoadNetwork.from_graphs([g1, g2])
+    R1, S1 = rg.sample_disjoint(g1.V, 300, 200, 37)
+    R2, S2 = rg.sample_disjoint(g2.V, 200, 300, 38)
+    specs = [{"R": R1, "S": S1, "theta": 1800, "graph": 0}, {"R": R2, "S": S2, "theta": 2200, "graph": 1},
+             {"R": R2, "S": S2, "k": 40, "graph": 1}]
+    wants = [orc.dist_join(g1, R1, S1, 1800).pairs, orc.dist_join(g2, R2, S2, 2200).pairs,
+             orc.kcp_join(g2, R2, S2, 40)]
+    q, keep = net.make_queries(specs)
+    plan = net.plan(q)
+    for part in (None, (0.25, 32), (1.0, 128)):
+        if part:
+            net.partition(*part)
+            assert not net.renumbered(0) and net.renumbered(1)
+        out, off, status = net.join_batch(q)
+        assert not status.any()
+        for got, want in zip(rnmod.split_batch(out, off), wants):
+            assert_same(got, want)
+        out, off, status = plan.run()
+        assert not status.any()
+        for got, want in zip(rnmod.split_batch(out, off), wants):
+            assert_same(got, want)
+    plan.close()

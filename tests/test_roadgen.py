@@ -86,3 +86,15 @@ def test_batched_instances_shapes(rg):
         assert 16 <= len(it.R) <= 4096 and len(it.R) + len(it.S) <= it.graph.V
         assert 500 <= it.theta <= 5000
         assert (it.k > 0) == (i % 2 == 1)
+
+
+def test_shuffle_ids_relabels_the_same_graph(rg, orc):
+    g = rg.road_graph(48, 3)
+    gs, perm = rg.shuffle_ids(g, 9)
+    assert gs.V == g.V and gs.A == g.A and sorted(perm.tolist()) == list(range(g.V))
+    R, S = rg.sample_disjoint(g.V, 40, 40, 10)
+    a = orc.dist_join(g, R, S, 1500).pairs
+    b = orc.dist_join(gs, perm[R], perm[S], 1500).pairs
+    # the same pairs under the relabelling
+    mapped = sorted(zip(a["dist"].tolist(), perm[a["u"]].tolist(), perm[a["v"]].tolist()))
+    assert mapped == sorted(zip(b["dist"].tolist(), b["u"].tolist(), b["v"].tolist()))
