@@ -1195,8 +1195,9 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                 __syncthreads();
                 continue;
             }
+            // (s_nf is written again only after the round's last barrier; thread 0
+            // writes s_nfn here, which no other thread reads before the barrier below)
             const uint32_t nf = s_nf;
-            __syncthreads();   // every thread has read s_nf
             if (tid < 64 && c.hist != nullptr) probe_phase(c, pnew, probing, seen);
             if (tid == 0) {
                 s_nfn = 0;
