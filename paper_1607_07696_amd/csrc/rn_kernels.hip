@@ -1632,22 +1632,29 @@ __global__ void k_select(CallBuffers b) {
 }
 
 // ------------------------------------------------------------------ layout
-// Exclusive scan of 64-bit values over a 1024-thread block (s: 1024 words).
+// Exclusive scan of 64-bit values over a 1024-thread block: a shuffle scan
+// within each wave, then each thread adds the totals of the waves before it
+// (s: at least 16 words; two block barriers).
 __device__ __forceinline__ unsigned long long block_excl_scan_u64(unsigned long long v, unsigned long long *s,
                                                                   unsigned long long *total) {
-    const uint32_t tid = threadIdx.x;
-    s[tid] = v;
-    __syncthreads();
-    for (uint32_t o = 1; o < 1024; o <<= 1) {
-        const unsigned long long x = tid >= o ? s[tid - o] : 0ull;
-        __syncthreads();
-        s[tid] += x;
-        __syncthreads();
+    const uint32_t tid = threadIdx.x, lane = tid & 63u, w = tid >> 6;
+    unsigned long long incl = v;
+#pragma unroll
+    for (uint32_t o = 1; o < 64; o <<= 1) {
+        const unsigned long long x = __shfl_up(incl, o, 64);
+        incl += lane >= o ? x : 0ull;
     }
-    const unsigned long long incl = s[tid];
-    *total = s[1023];
+    if (lane == 63u) s[w] = incl;
     __syncthreads();
-    return incl - v;
+    unsigned long long off = 0, all = 0;
+    for (uint32_t i = 0; i < 16; ++i) {
+        const unsigned long long x = s[i];
+        off += i < w ? x : 0ull;
+        all += x;
+    }
+    __syncthreads();
+    *total = all;
+    return off + incl - v;
 }
 
 __device__ __forceinline__ uint32_t bitlen32(uint32_t x) { return x ? 32u - static_cast<uint32_t>(__clz(x)) : 0u; }
