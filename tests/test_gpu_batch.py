@@ -236,3 +236,34 @@ def test_kcp_within_theta(rnmod, orc, rg):
         cases.append((g, R, S, theta, k))
     out, off, status = net.join_batch(specs)
     check_batch(rnmod, orc, out, off, status, cases)
+
+
+@pytest.mark.parametrize("sort", ["bucket", "radix"])
+def test_more_than_1024_queries_in_one_call(rnmod, orc, rg, sort):
+    """2 100 small queries in one call: the per-query layout (kept counts,
+    segment starts, output offsets) is scanned 1 024 queries at a time with
+    totals carried between blocks, and the last block is ragged.  A random
+    digraph with weights 1..40 gives pairs at small theta.  "bucket":
+    theta-joins only with sum(theta + 1) <= 65 536 on a graph of varied
+    weights, so the (query, dist) bucket sort runs; "radix": every seventh
+    query asks for the k closest pairs, which sends the call to the radix
+    sort."""
+    g = rg.random_digraph(300, 1500, 21, wmin=1, wmax=40)
+    net = rnmod.RoadNetwork.from_graph(g)
+    rng = np.random.default_rng(77)
+    cases = []
+    for i in range(2100):
+        R, S = rg.sample_disjoint(g.V, int(rng.integers(1, 11)), int(rng.integers(1, 11)), 5000 + i)
+        if sort == "bucket":
+            theta, k = i % 40, 0
+        elif i % 7 == 3:
+            theta, k = MAX_DIST, int(rng.integers(1, 9))
+        else:
+            theta, k = int(rng.integers(0, 61)), 0
+        cases.append((g, R, S, theta, k))
+    if sort == "bucket":
+        assert sum(t + 1 for _, _, _, t, _ in cases) <= 65536
+    specs = [{"R": R, "S": S, "theta": t, "k": k} for _, R, S, t, k in cases]
+    out, off, status = net.join_batch(specs)
+    assert int(off[-1]) > 1000
+    check_batch(rnmod, orc, out, off, status, cases)
