@@ -135,6 +135,30 @@ def test_invalid_request_fails_alone(rnmod, orc, graph, rg):
     assert_same(rnmod.pairs_to_numpy(net.dist_join(R, S, 1500)), orc.dist_join(graph, R, S, 1500).pairs)
 
 
+def test_server_on_a_renumbered_graph(rnmod, orc, rg):
+    # a graph with shuffled ids, which rn_partition renumbers in leaf order:
+    # requests and answers stay in the ids it was loaded with, and the handle
+    # cannot be partitioned again while a server holds it
+    g, _ = rg.shuffle_ids(rg.road_graph(96, 3), 11)
+    net = rnmod.RoadNetwork.from_graph(g)
+    net.partition(1.0, 64)
+    assert net.renumbered(0)
+    srv = rnmod.Server(net, lanes=2, max_batch=4)
+    reqs = []
+    for i in range(10):
+        R, S = rg.sample_disjoint(g.V, 30 + 7 * i, 60 - 3 * i, 900 + i)
+        theta, k = (1500 + 300 * i, 0) if i % 3 else (MAX_DIST, 5 + 4 * i)
+        reqs.append((R, S, theta, k))
+    ids = [srv.submit(R, S, t, k) for R, S, t, k in reqs]
+    got = [srv.wait(x)[0] for x in ids]
+    with pytest.raises(rnmod.RnError) as ei:
+        net.partition(1.0, 64)
+    assert ei.value.status == rnmod.RN_ERR_BUSY
+    srv.close()
+    for i, (R, S, t, k) in enumerate(reqs):
+        assert_same(got[i], oracle_answer(orc, g, R, S, t, k), f"request {i}")
+
+
 def test_config5_stream_sample_full_size(rnmod, orc, rg):
     # the 2048x2048 serving workload, served as the benchmark serves it (2
     # lanes, batches of up to 8): sampled requests the oracle answers in
