@@ -502,6 +502,13 @@ __device__ __forceinline__ unsigned long long reserve_recs(const JoinArgs &a, co
            readlane(static_cast<uint32_t>(base), 0);
 }
 
+// theta-join calls sorted by bins: a record's place among its (query, dist)
+// bin's records, from the bin count it was added to, is kept in the upper 16
+// bits of its query field (queries are numbered below 2^16) until the scatter
+// moves it; places of kPlaceNone and more are stored as kPlaceNone.
+constexpr uint32_t kPlaceNone = 0xFFFFu;
+__device__ __forceinline__ uint32_t bin_place(uint32_t place) { return min(place, kPlaceNone) << 16; }
+
 // Write this wave's staged pairs ({dist, v} in stg) for source u.
 template <int HB>
 __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
@@ -520,8 +527,8 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
             r.v = c.swapped ? from : to;
             r.d = e.x;
             r.q = c.q;
+            if (a.bins) r.q |= bin_place(atomicAdd(&a.bins[bin0 + r.d], 1u));
             a.recs[idx] = r;
-            if (a.bins) atomicAdd(&a.bins[bin0 + r.d], 1u);
         }
     }
     wave_sync();
@@ -1319,8 +1326,8 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                     rr.v = c.swapped ? cu : cy;
                     rr.d = d;
                     rr.q = c.q;
+                    if (a.bins) rr.q |= bin_place(atomicAdd(&a.bins[a.binbase[c.q] + d], 1u));
                     a.recs[idx] = rr;
-                    if (a.bins) atomicAdd(&a.bins[a.binbase[c.q] + d], 1u);
                 }
             }
         }
@@ -1877,7 +1884,7 @@ __device__ __forceinline__ void bucket_scan_block(const CallBuffers &b, uint32_t
     const bool map = tc <= kSortHistWords;
     for (uint32_t i = lo; i < hi; ++i) {
         start[i] = er;
-        cursor[i] = er;
+        cursor[i] = er + kPlaceNone;   // records past the first kPlaceNone of a bin
         cstart[i] = ec;
         er += cnt[i];
         const uint32_t nch = (cnt[i] + 63u) / 64u;
@@ -1900,12 +1907,19 @@ __global__ __launch_bounds__(1024) void k_layout_bins(CallBuffers b, uint32_t qb
     bucket_scan_block(b, reinterpret_cast<uint32_t *>(s));
 }
 
+// Each record goes to its bin's start plus the place the relaxation kernel's
+// bin count gave it (records past the first kPlaceNone of a bin take slots
+// from the bin's cursor instead); the query field loses the place again.
 __global__ __launch_bounds__(256) void k_bucket_scatter(CallBuffers b) {
     const unsigned long long n = b.ctl->nsel;
+    const uint32_t *start = b.bins + b.nbins;
     uint32_t *cursor = b.bins + 2 * b.nbins;
     for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += gridDim.x * 256ull) {
-        const Rec r = b.recs[0][i];
-        b.recs[1][atomicAdd(&cursor[rec_bin(b, r)], 1u)] = r;
+        Rec r = b.recs[0][i];
+        const uint32_t place = r.q >> 16;
+        r.q &= 0xFFFFu;
+        const uint32_t bin = rec_bin(b, r);
+        b.recs[1][place != kPlaceNone ? start[bin] + place : atomicAdd(&cursor[bin], 1u)] = r;
     }
 }
 

@@ -127,6 +127,24 @@ def test_disconnected_graph(rnmod, orc, rg):
     assert_same(gpu_join(rnmod, net, R, S, 5000), orc.dist_join(g, R, S, 5000).pairs)
 
 
+def test_one_distance_bin_beyond_2_16_records(rnmod, orc, rg):
+    # 300 sources with an arc of weight 5 to each of 300 targets: 90 000 pairs
+    # in the one (query, dist = 5) bin of the bucket sort (the chain adds 19
+    # distinct weights, so the graph counts as varied and the bucket sort
+    # runs); places in a bin past 2^16 - 1 are assigned by the bin's cursor
+    R = np.arange(300, dtype=np.int32)
+    S = np.arange(300, 600, dtype=np.int32)
+    chain = np.arange(600, 619)
+    g = rg.from_edges(620, np.concatenate([np.repeat(R, 300), chain]),
+                      np.concatenate([np.tile(S, 300), chain + 1]),
+                      np.concatenate([np.full(90000, 5), np.arange(1, 20)]), symmetric=False)
+    net = rnmod.RoadNetwork.from_graph(g)
+    for theta in (5, 12):
+        want = orc.dist_join(g, R, S, theta).pairs
+        assert want.shape[0] == 90000
+        assert_same(gpu_join(rnmod, net, R, S, theta), want)
+
+
 def test_lattice_closed_form_at_scale(rnmod, rg):
     side, c = 1024, 100
     g = rg.full_lattice(side, c)
