@@ -56,7 +56,6 @@ void host_free(T *&p) {
 enum { EV_START, EV_STAGED, EV_TIER0, EV_RELAXED, EV_SELECTED, EV_DONE, EV_COUNT };
 
 constexpr int kSide = 2 * (kMaxHB - kMinHB + 1) - 1;   // side streams: one per first-tier launch beyond the first
-constexpr int32_t kMaxQueries = 65536;
 constexpr unsigned long long kRecCapMax = 1ull << 31;
 
 inline size_t round_up(size_t x, size_t m) { return (x + m - 1) / m * m; }

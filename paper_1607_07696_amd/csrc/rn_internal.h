@@ -240,10 +240,15 @@ hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_pass
 size_t sort_hist_words();
 constexpr uint32_t kSortPassesMax = 16;
 
+// Queries per call.  Query numbers fit in 16 bits: the bucket sort keeps a
+// record's place in its bin in the upper half of its 32-bit query field.
+constexpr int32_t kMaxQueries = 65536;
+
 // Bucket sort, for calls of theta-joins only whose bins (query, dist), theta+1
 // per query, number at most kMaxBins: the relaxation kernels count the records
-// per bin as they store them; the layout launch scans them; scatter the records into their bins, then
-// order each bin by (u, v) by counting the smaller
+// per bin as they store them (the count's old value is the record's place in
+// its bin); the layout launch scans the counts; the scatter copies each record
+// to its place, then order each bin by (u, v) by counting the smaller
 // keys of its records, one wave per 64 of them, writing each query's output
 // segment as the radix sort's last pass does.  Work per bin grows with the
 // square of its size, so it is chosen only for graphs with varied weights.

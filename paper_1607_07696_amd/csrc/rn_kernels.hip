@@ -507,6 +507,7 @@ __device__ __forceinline__ unsigned long long reserve_recs(const JoinArgs &a, co
 // bits of its query field (queries are numbered below 2^16) until the scatter
 // moves it; places of kPlaceNone and more are stored as kPlaceNone.
 constexpr uint32_t kPlaceNone = 0xFFFFu;
+static_assert(kMaxQueries <= 0x10000, "query numbers fit the low 16 bits of a record's query field");
 __device__ __forceinline__ uint32_t bin_place(uint32_t place) { return min(place, kPlaceNone) << 16; }
 
 // Write this wave's staged pairs ({dist, v} in stg) for source u.
