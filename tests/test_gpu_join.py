@@ -64,6 +64,18 @@ def test_config2_theta_join_full_size(rnmod, orc, rg, g1024):
     assert_same(gpu_join(rnmod, net, R, S, 3000), want)
     st = net.stats()
     assert st["settled"] == ref.settled and st["arcs"] == ref.arcs
+    # the launch configuration the benchmark times: sources in partition
+    # order (alpha 1, leaves of 256), the query captured once as a plan and
+    # replayed; every replay equals the oracle
+    net.set_profiling(times=False, work=False)
+    net.partition(1.0, 256)
+    q, keep = net.make_queries([{"R": R, "S": S, "theta": 3000}])
+    plan = net.plan(q, cap=len(want) + 1024)
+    for _ in range(3):
+        out, off, status = plan.run()
+        assert not status.any() and int(off[-1]) == len(want)
+        assert_same(rnmod.pairs_to_numpy(out), want)
+    plan.close()
 
 
 @pytest.mark.parametrize("theta", [0, 1, 41, 700, 1500, 2999])
