@@ -398,7 +398,7 @@ def partition_study(torch, rn, g, R, S, theta, arcs, steps):
     return rows
 
 
-def cpu_baseline(g, R, S, theta, arcs_total, budget_s):
+def cpu_baseline(g, R, S, theta, arcs_total, budget_s, gpu_pairs):
     from oracle import oracle
     times = []
     t_end = time.perf_counter() + budget_s
@@ -413,7 +413,9 @@ def cpu_baseline(g, R, S, theta, arcs_total, budget_s):
             "kind": "oracle",
             "sample": (f"full workload ({len(R)} sources, all host threads), median of "
                        f"{len(times)} runs of {best * 1e3:.1f} ms"),
-            "pairs_match_count": int(res.pairs.shape[0])}
+            "oracle_pairs": int(res.pairs.shape[0]),
+            # the full sorted pair list of the timed query, element by element
+            "matches_gpu": bool(np.array_equal(res.pairs, gpu_pairs))}
 
 
 def main():
@@ -568,7 +570,9 @@ def main():
         result["serve"] = serve_leg(torch, rn)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
-        result["cpu_baseline"] = cpu_baseline(g, R, S, theta, arcs, args.cpu_budget)
+        result["cpu_baseline"] = cpu_baseline(g, R, S, theta, arcs, args.cpu_budget, eager_pairs)
+        if not result["cpu_baseline"]["matches_gpu"]:
+            log("ERROR: the GPU pairs differ from the oracle's")
     print(json.dumps(result), flush=True)
 
 
