@@ -175,15 +175,25 @@ def batch_leg(torch, rn, steps):
                         "odd instances ask for the k closest pairs, k log-uniform in [1, 1024]"),
            "vertices": int(net.V), "arcs_resident": int(net.A), "pairs": total_pairs, "work_arcs": arcs}
     res["eager_ms"] = round(timed(lambda: net.join_batch(q), steps), 4)
+
+    def same_as_eager(plan):
+        # a replay's whole output and offsets against the eager call's
+        pout, poff, pstatus = plan.run()
+        return bool(not pstatus.any() and np.array_equal(poff, off)
+                    and np.array_equal(rn.pairs_to_numpy(pout), a))
     plan = net.plan(q)
     res["plan_ms"] = round(timed(plan.run, steps), 4)
+    res["plan_matches_eager"] = same_as_eager(plan)
     plan.close()
     t0 = time.perf_counter()
     net.autotune(q, sample=256)
     res["autotune_s"] = round(time.perf_counter() - t0, 2)
     plan = net.plan(q)
     res["plan_tuned_ms"] = round(timed(plan.run, steps), 4)
+    res["plan_tuned_matches_eager"] = same_as_eager(plan)
     plan.close()
+    if not (res["plan_matches_eager"] and res["plan_tuned_matches_eager"]):
+        log("ERROR: a captured batch plan's output differs from the eager call's")
     best = min(res["plan_ms"], res["plan_tuned_ms"])
     # the plain path: one handle per graph, single-query calls in sequence
     nets = [rn.RoadNetwork.from_graph(x.graph) for x in inst]
@@ -222,13 +232,21 @@ def batch_leg(torch, rn, steps):
     return res
 
 
-def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8):
+SERVE_ORACLE_SAMPLE = (1, 8, 9, 10, 11, 12, 14, 16)   # light requests the oracle answers in about a second
+
+
+def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8, budget_mib=256):
     """Poisson streams of joins on the resident 2048x2048 graph through the
     request server (continuous batching), against the same requests served
-    one at a time, in arrival order, by the single-query calls.  The server's
-    capacity C is measured first (every request submitted at once); the same
-    requests then arrive as Poisson streams at the given fractions of C (the
-    stream's inter-arrival draws only scale with the rate)."""
+    one at a time, in arrival order, by the single-query calls (a measured
+    first-come-first-served run on the same arrivals).  The server's capacity
+    C is measured first (every request submitted at once); the same requests
+    then arrive as Poisson streams at the given fractions of C (the stream's
+    inter-arrival draws only scale with the rate).  Every result of every
+    server run is compared with the same request's result from the plain
+    single-query call (a digest per request)."""
+    import hashlib
+    import queue
     import threading
     from paper_1607_07696_amd import roadgen
     MAX = rn.MAX_DIST
@@ -239,10 +257,11 @@ def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8):
     theta_of = [r.theta if r.k == 0 else MAX for r in reqs]
     srv_cfg = dict(lanes=2, max_batch=8, global_slots=128, hbm_budget=16 << 30)
     pct = lambda a, q: round(float(np.percentile(a, q)), 3)
+    digest = lambda a: hashlib.blake2b(np.ascontiguousarray(a).tobytes(), digest_size=16).digest()
 
-    def run_server(scale):
+    def run_server(scale, **over):
         """scale: seconds per unit of the 1/s arrival times (0: all at once)."""
-        srv = rn.Server(net, **srv_cfg)
+        srv = rn.Server(net, **dict(srv_cfg, **over))
         for r, t in zip(reqs[:8], theta_of[:8]):                # warm-up outside the timed stream
             srv.wait(srv.submit(r.R, r.S, t, r.k))
         ids = [None] * count
@@ -256,7 +275,7 @@ def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8):
                 ids[i] = srv.submit(r.R, r.S, t, r.k)
         th = threading.Thread(target=producer)
         th.start()
-        lat, dks, npairs = [], [], 0
+        lat, dks, npairs, digs, sample = [], [], 0, [], {}
         for i in range(count):
             while ids[i] is None:
                 time.sleep(0.0001)
@@ -266,27 +285,36 @@ def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8):
                 log(f"serve: {i + 1} answered, {time.perf_counter() - t0:.2f} s")
             npairs += out.shape[0]
             dks.append(int(out["dist"][-1]) if (reqs[i].k and out.shape[0]) else 0)
+            digs.append(digest(out))
+            if i in SERVE_ORACLE_SAMPLE:
+                sample[i] = out
         makespan = time.perf_counter() - t0
         th.join()
         st = srv.stats()
         srv.close()
-        return lat, makespan, st, dks, npairs
+        return lat, makespan, st, dks, npairs, digs, sample
 
-    log("serve: capacity (every request submitted at once)")
-    _, cap_span, _, dks, npairs = run_server(0.0)
-    capacity = count / cap_span
-    log(f"serve: capacity {capacity:.0f} requests/s; the same requests one at a time")
-    # the plain path: each request alone (upload, call, result to the host)
-    service = []
-    for i, (r, t) in enumerate(zip(reqs, theta_of)):
-        if (i + 1) % 500 == 0:
-            log(f"serve: plain {i + 1} done, {sum(service):.2f} s")
-        a = time.perf_counter()
+    def plain_call(i):
+        r, t = reqs[i], theta_of[i]
         Rd = torch.as_tensor(r.R, device="cuda")
         Sd = torch.as_tensor(r.S, device="cuda")
         out = net.kcp_join(Rd, Sd, r.k) if r.k else net.dist_join(Rd, Sd, t)
-        rn.pairs_to_numpy(out)
+        return rn.pairs_to_numpy(out)
+
+    log("serve: capacity (every request submitted at once)")
+    _, cap_span, cap_st, dks, npairs, cap_digs, sample = run_server(0.0)
+    capacity = count / cap_span
+    log(f"serve: capacity {capacity:.0f} requests/s; the same requests one at a time")
+    # the plain path: each request alone (upload, call, result to the host)
+    service, plain_digs = [], []
+    for i in range(count):
+        if (i + 1) % 500 == 0:
+            log(f"serve: plain {i + 1} done, {sum(service):.2f} s")
+        a = time.perf_counter()
+        out = plain_call(i)
         service.append(time.perf_counter() - a)
+        plain_digs.append(digest(out))
+    matches = lambda digs: int(sum(x == y for x, y in zip(digs, plain_digs)))
     # work: arcs out of every vertex within theta (theta-joins) or within the
     # k-th distance (k-closest pairs) of each source in R
     log("serve: counting work")
@@ -298,26 +326,59 @@ def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8):
         net.join_batch(specs)
         arcs += int(net.stats()["arcs"])
     net.set_profiling(times=False, work=False)
+
+    def plain_fifo(scale):
+        """The same arrivals served one at a time in arrival order by the
+        single-query calls, measured: a producer thread releases each request
+        at its arrival time, this thread serves them first come, first served."""
+        q = queue.Queue()
+        t0 = time.perf_counter()
+
+        def producer():
+            for i, r in enumerate(reqs):
+                delay = r.arrival_s * scale - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+                q.put(i)
+        th = threading.Thread(target=producer)
+        th.start()
+        lat = []
+        for _ in range(count):
+            i = q.get()
+            plain_call(i)
+            lat.append((time.perf_counter() - t0 - reqs[i].arrival_s * scale) * 1e3)
+        makespan = time.perf_counter() - t0
+        th.join()
+        return lat, makespan
+
     streams = {}
     for f in loads:
         rate = f * capacity
         log(f"serve: Poisson stream at {f:g} C = {rate:.0f}/s")
-        lat, makespan, st, _, _ = run_server(1.0 / rate)
-        done, plat = 0.0, []
-        for r, s_ in zip(reqs, service):                       # first come, first served
-            arr = r.arrival_s / rate
-            done = max(done, arr) + s_
-            plat.append((done - arr) * 1e3)
+        lat, makespan, st, _, _, digs, _ = run_server(1.0 / rate)
+        plat, pspan = plain_fifo(1.0 / rate)
         streams[f"{f:g}C"] = {
             "rate_rps": round(rate, 1),
             "server": {"latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": pct(lat, 100)},
                        "throughput_rps": round(count / makespan, 1), "makespan_s": round(makespan, 3),
-                       "gteps": round(arcs / makespan / 1e9, 3), "stats": st},
+                       "gteps": round(arcs / makespan / 1e9, 3), "matches_plain": matches(digs), "stats": st},
             "plain_fifo": {"latency_ms": {"p50": pct(plat, 50), "p99": pct(plat, 99), "max": pct(plat, 100)},
-                           "throughput_rps": round(count / done, 1), "makespan_s": round(done, 3),
-                           "gteps": round(arcs / done / 1e9, 3)}}
+                           "throughput_rps": round(count / pspan, 1), "makespan_s": round(pspan, 3),
+                           "gteps": round(arcs / pspan / 1e9, 3), "measured": True}}
+    # the headline rate again with an HBM budget small enough to bind:
+    # admission then waits for memory, not only for a free lane
+    rate = headline * capacity
+    log(f"serve: Poisson stream at {headline:g} C with an HBM budget of {budget_mib} MiB")
+    lat, makespan, st, _, _, digs, _ = run_server(1.0 / rate, hbm_budget=budget_mib << 20)
+    budget_stream = {"rate_rps": round(rate, 1), "hbm_budget_mib": budget_mib,
+                     "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": pct(lat, 100)},
+                     "throughput_rps": round(count / makespan, 1), "matches_plain": matches(digs), "stats": st}
     net.close()
     head = streams[f"{headline:g}C"]
+    ok = matches(cap_digs) == count and all(s["server"]["matches_plain"] == count for s in streams.values()) \
+        and budget_stream["matches_plain"] == count
+    if not ok:
+        log("ERROR: a served result differs from the same request's single-query result")
     return {"workload": (f"{count} requests on the 2048x2048 road graph (seed 0): 60% theta-joins with theta "
                          "uniform in [500, 8000], 40% k closest pairs with k log-uniform in [1, 4096]; |R|, |S| "
                          "log-uniform in [64, 32768]; Poisson arrivals (seed 5) at fractions of the server's "
@@ -325,10 +386,13 @@ def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8):
             "V": g.V, "A": g.A, "pairs": int(npairs), "work_arcs": arcs,
             "config": {"lanes": 2, "max_batch": 8, "global_slots": 128, "hbm_budget_gib": 16},
             "capacity_rps": round(capacity, 1), "capacity_gteps": round(arcs / cap_span / 1e9, 3),
+            "capacity_stats": cap_st,
             "plain_service_ms": {"p50": pct(np.array(service) * 1e3, 50), "p99": pct(np.array(service) * 1e3, 99),
                                  "total_s": round(float(np.sum(service)), 3)},
+            "results_match_plain": bool(ok), "matches_plain_capacity_run": matches(cap_digs),
             "headline": f"{headline:g}C", "server": head["server"], "plain_fifo": head["plain_fifo"],
-            "streams": streams}
+            "streams": streams, "budget_stream": budget_stream,
+            "_sample": {i: sample[i] for i in sorted(sample)}, "_reqs": reqs, "_graph": g}
 
 
 def partition_study(torch, rn, g, R, S, theta, arcs, steps):
@@ -416,6 +480,18 @@ def cpu_baseline(g, R, S, theta, arcs_total, budget_s, gpu_pairs):
             "oracle_pairs": int(res.pairs.shape[0]),
             # the full sorted pair list of the timed query, element by element
             "matches_gpu": bool(np.array_equal(res.pairs, gpu_pairs))}
+
+
+def served_sample_vs_oracle(g, reqs, sample):
+    """The served results of a fixed sample of light requests against the
+    oracle's answers (element by element); returns {request: bool}."""
+    from oracle import oracle
+    out = {}
+    for i, got in sample.items():
+        r = reqs[i]
+        want = oracle.kcp_join(g, r.R, r.S, r.k) if r.k else oracle.dist_join(g, r.R, r.S, r.theta).pairs
+        out[str(i)] = bool(np.array_equal(got, want))
+    return out
 
 
 def main():
@@ -573,6 +649,13 @@ def main():
         result["cpu_baseline"] = cpu_baseline(g, R, S, theta, arcs, args.cpu_budget, eager_pairs)
         if not result["cpu_baseline"]["matches_gpu"]:
             log("ERROR: the GPU pairs differ from the oracle's")
+        if "serve" in result:
+            log("checking the served sample against the oracle")
+            sv = result["serve"]
+            sv["sample_matches_oracle"] = served_sample_vs_oracle(sv["_graph"], sv["_reqs"], sv["_sample"])
+    if "serve" in result:
+        for key in ("_sample", "_reqs", "_graph"):
+            result["serve"].pop(key, None)
     print(json.dumps(result), flush=True)
 
 

@@ -83,6 +83,8 @@ typedef struct rn_graph rn_graph;
  *   out      receives the handle; *out is NULL on failure
  * The caller keeps ownership of its arrays.  Errors: RN_ERR_ARG on a malformed
  * CSR or null pointer, RN_ERR_NOMEM, RN_ERR_DEVICE.
+ * Node coordinates are not taken: both queries are defined on network
+ * distance alone (Section 1), so nothing on the device would read them.
  */
 rn_status rn_graph_load(int32_t V, int64_t A, const int32_t *row_ptr, const int32_t *col,
                         const uint32_t *w, rn_graph **out);
@@ -136,7 +138,9 @@ rn_status rn_partition(rn_graph *g, float alpha, int32_t max_leaf, int32_t *part
 int32_t rn_graph_renumbered(const rn_graph *g, int32_t graph);
 
 /*
- * rn_dist_join -- the theta-join (on graph 0 of the handle).
+ * rn_dist_join -- the theta-join (on graph 0 of the handle); the query as the
+ * Abstract and the opening of Section 4 define it: pairs of R x S whose
+ * network distance is within theta.
  *   R, nR   device int32[nR], nR >= 1: the left set; ids in [0, V), no duplicates
  *   S, nS   device int32[nS], nS >= 1: the right set; ids in [0, V), no
  *           duplicates, disjoint from R (the paper's sets are disjoint)
@@ -153,7 +157,9 @@ rn_status rn_dist_join(rn_graph *g, const int32_t *R, int32_t nR, const int32_t 
                        uint32_t theta, rn_pair *out, int64_t cap, int64_t *n_out, void *stream);
 
 /*
- * rn_kcp_join -- the k-closest-pairs join (on graph 0 of the handle).
+ * rn_kcp_join -- the k-closest-pairs join (on graph 0 of the handle); the
+ * query as the Abstract and Section 1 define it: k pairs of R x S such that no
+ * pair left out is closer than a pair returned.
  *   R, nR, S, nS  as for rn_dist_join
  *   k       1 <= k <= 2^24
  *   out     device rn_pair[cap]; cap >= min(k, nR * nS) always suffices
@@ -293,7 +299,12 @@ void rn_plan_free(rn_plan *p);
  * requests as one batch (the launch sequence of rn_join_batch) on the lane's
  * own stream and buffers.  Requests that arrive while others are on the
  * device are admitted as lanes and budget free up, and their work overlaps
- * with the batches already running.  Each request's result is exactly the
+ * with the batches already running.  The budget covers what requests add
+ * while in flight (their ids, records and output, estimated); the buffers
+ * each lane keeps between batches, among them the global-tier search slots
+ * it allocates when a search first needs them (global_slots slots of about
+ * 25 bytes per vertex each), are outside it and are reported in
+ * rn_server_stats.device_bytes.  Each request's result is exactly the
  * result of the same query run alone.  The server holds the handle for its
  * lifetime: other calls on it return RN_ERR_BUSY until rn_server_free.
  */
@@ -313,7 +324,7 @@ typedef struct rn_server_stats {
     int64_t batches;        /* batches launched */
     int64_t reruns;         /* batches re-run with larger buffers */
     int64_t peak_budget;    /* largest estimated footprint in flight, bytes */
-    int64_t device_bytes;   /* device memory held by the lanes, bytes */
+    int64_t device_bytes;   /* largest device memory held by the lanes (all their buffers), bytes */
     int32_t max_in_flight;  /* most requests in flight at once */
     int32_t max_lanes_busy; /* most lanes busy at once */
     int32_t max_batch_seen; /* largest batch launched */

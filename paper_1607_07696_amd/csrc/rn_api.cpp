@@ -160,9 +160,15 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         rw += words;
         if (sw >= 0xFFFFFFFFull || rw >= 0xFFFFFFFFull) return fail(RN_ERR_ARG, "too many vertices in one call");
         if (p.groups.empty() || p.groups.back().hb != hb[i] || p.groups.back().kcp != (x.k > 0))
-            p.groups.push_back(Group{hb[i], x.k > 0, s, s + 1, 0});
-        p.groups.back().end = s + 1;
-        p.groups.back().sources += static_cast<uint64_t>(d.nR);
+            p.groups.push_back(Group{hb[i], x.k > 0, true, s, s + 1, 0});
+        Group &gr = p.groups.back();
+        gr.end = s + 1;
+        gr.sources += static_cast<uint64_t>(d.nR);
+        // compact tables: local ids below 2^24, and (theta-joins) every
+        // distance within theta fits the compact word; a k-closest-pairs
+        // search whose bound is larger moves on if it meets such a distance
+        gr.compact = false && gr.compact && g->Vmax < kCompactVertices &&
+                     (x.k > 0 || x.theta <= compact_max_dist(hb[i]));
     }
     p.rbase[nq] = static_cast<uint32_t>(rw);
     p.total_elems = p.ebase[nq];
@@ -210,19 +216,22 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
     return RN_OK;
 }
 
-rn_status ensure_gslots(Workspace &ws, int32_t Vmax, uint32_t nslots) {
+rn_status ensure_gslots(Workspace &ws, int32_t Vmax, uint32_t want, hipStream_t s) {
     if (ws.d_gslots) return RN_OK;
-    // at most nslots concurrent global-tier searches, within 48 GiB
+    // one slot per concurrent global-tier search: as many as the call needs
+    // (at least 64, so that a later call with more such searches still runs
+    // them side by side), at most the workspace's cap and 48 GiB
     const size_t words = global_slot_words(Vmax);
-    size_t n = (size_t{48} << 30) / (4 * words);
-    n = std::max<size_t>(1, std::min<size_t>(n, nslots));
+    size_t n = std::max<size_t>(want, 64);
+    n = std::min<size_t>(n, std::max<uint32_t>(ws.gslot_cap, 1));
+    n = std::max<size_t>(1, std::min<size_t>(n, (size_t{48} << 30) / (4 * words)));
     RN_HIP(dev_alloc(&ws.d_gslots, n * words), "allocating global search slots");
     ws.n_gslots = static_cast<uint32_t>(n);
     const size_t V = static_cast<size_t>(Vmax);
-    RN_HIP(launch_fill_u32(ws.d_gslots, n * V, kInf, nullptr), "clearing search slots");
-    RN_HIP(launch_fill_u32(ws.d_gslots + n * V, n * V + n * global_bitmap_words(Vmax), 0u, nullptr),
+    RN_HIP(launch_fill_u32(ws.d_gslots, n * V, kInf, s), "clearing search slots");
+    RN_HIP(launch_fill_u32(ws.d_gslots + n * V, n * V + n * global_bitmap_words(Vmax), 0u, s),
            "clearing search slots");
-    RN_HIP(hipDeviceSynchronize(), "clearing search slots");
+    RN_HIP(hipStreamSynchronize(s), "clearing search slots");
     return RN_OK;
 }
 
@@ -381,6 +390,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     a.count_work = g->count_work ? 1 : 0;
     a.big_deg = g->big_deg ? 1 : 0;
     a.order = g->d_order;
+    a.first = g->d_first;
     if (p.any_kcp) {
         JoinArgs k = a;
         k.src = b.src;
@@ -412,7 +422,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.novf = &b.ctl->nlist[li];
         t.first_tier = 1;
         t.tier = 0;
-        RN_HIP(launch_join(t, gr.hb, gr.kcp, static_cast<uint32_t>(gr.sources), !shared, st),
+        RN_HIP(launch_join(t, gr.hb, gr.kcp, gr.compact, static_cast<uint32_t>(gr.sources), !shared, st),
                "launching the relaxation");
         if (gi > 0 && fork) RN_HIP(hipEventRecord(ws.join[gi - 1], st), "joining streams");
     }
@@ -433,10 +443,13 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.novf = &b.ctl->nlist[li + 1];
         t.first_tier = 0;
         t.tier = 1 + li;
-        RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, true, maxs, !shared, s), "launching the relaxation");
+        // the 2^11 re-run takes a compact table where the graphs allow it (its
+        // own overflows still reach the wide 2^14 tier); the 2^14 re-run is wide
+        RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, true, false && li == 0 && g->Vmax < kCompactVertices, maxs,
+                           !shared, s),
+               "launching the relaxation");
     }
-    {
-        if (!ws.d_gslots) return fail(RN_ERR_DEVICE, "global search slots missing");
+    if (ws.d_gslots) {   // (without slots the call is run again once they exist)
         JoinArgs t = a;
         t.src = b.list[2];
         t.srcq = b.listq[2];
@@ -467,7 +480,6 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
 
 namespace {
 
-constexpr uint32_t kDefaultSlots = 256;  // global-tier slots of a handle's calls and of a plan (one per CU)
 
 // The call's last kernel wrote its state into the mapped read-back buffer.
 rn_status read_back(Workspace &ws, const Prepared &p, hipStream_t s) {
@@ -487,15 +499,20 @@ float elapsed(const rn_graph *g, const Workspace &ws, int a, int b) {
 // Turn the read-back state into offsets / status / the return code.
 // Returns RN_ERR_NOMEM + sets *regrow when the records outgrew the buffer.
 rn_status finish(rn_graph *g, Workspace &ws, const Prepared &p, int64_t cap, int64_t *offsets, int32_t *status,
-                 bool timed, bool *regrow) {
+                 bool timed, bool *regrow, hipStream_t s) {
     const CallCtl &c = *reinterpret_cast<const CallCtl *>(ws.h_state);
     const QueryState *qs = reinterpret_cast<const QueryState *>(ws.h_state + sizeof(CallCtl));
     *regrow = false;
-    if (c.npairs > ws.rec_cap) {
+    if (c.nlist[2] > 0 && !ws.d_gslots) {
+        // some search needed the global tier, which had no slots yet
+        *regrow = true;
+        RN_TRY(ensure_gslots(ws, g->Vmax, c.nlist[2], s));
+    }
+    if (c.npairs > ws.rec_cap && !*regrow) {
         *regrow = true;
         RN_TRY(grow_recs(ws, c.npairs));
-        return RN_OK;
     }
+    if (*regrow) return RN_OK;
     if (timed) {
         rn_stats &st = g->stats;
         st = rn_stats{};
@@ -538,13 +555,13 @@ rn_status finish(rn_graph *g, Workspace &ws, const Prepared &p, int64_t cap, int
 rn_status run_eager(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *out, int64_t cap, int64_t *offsets,
                     int32_t *status, hipStream_t s, bool timed) {
     RN_TRY(ensure_buffers(ws, p));
-    for (int attempt = 0; attempt < 3; ++attempt) {
+    for (int attempt = 0; attempt < 4; ++attempt) {
         fill_host_desc(p, ws.h_desc);
         RN_HIP(hipMemcpyAsync(ws.d_desc, ws.h_desc, p.desc_bytes, hipMemcpyHostToDevice, s), "uploading queries");
         RN_TRY(enqueue_call(g, ws, p, out, cap, s, timed));
         RN_TRY(read_back(ws, p, s));
         bool regrow = false;
-        const rn_status st = finish(g, ws, p, cap, offsets, status, timed, &regrow);
+        const rn_status st = finish(g, ws, p, cap, offsets, status, timed, &regrow, s);
         if (!regrow) return st;
     }
     return fail(RN_ERR_NOMEM, "record buffer did not settle");
@@ -557,7 +574,6 @@ rn_status run_batch(rn_graph *g, const rn_query *q, int32_t nq, rn_pair *out, in
     RN_HIP(hipSetDevice(g->device), "selecting the device");
     Prepared p;
     RN_TRY(prepare(g, q, nq, p));
-    RN_TRY(ensure_gslots(g->ws, g->Vmax, kDefaultSlots));
     return run_eager(g, g->ws, p, out, cap, offsets, status, s, true);
 }
 
@@ -671,7 +687,41 @@ rn_status upload_csr(rn_graph *g, const int32_t *perm) {
     } catch (...) {
         return fail(RN_ERR_NOMEM, "building the device graph");
     }
+    // bit a: arc record a is the first lightest among the arcs from its tail
+    // to its target (k-closest pairs count a pair of parallel arcs once)
+    std::vector<uint32_t> first;
+    try {
+        first.assign((arcs.size() + 31) / 32, 0u);
+        std::vector<int64_t> idx;
+        const size_t nv = rp.size() - 1;   // forward rows, then the reversed ones
+        for (size_t x = 0; x < nv; ++x) {
+            const int64_t b = rp[x], e = rp[x + 1];
+            if (e <= b) continue;
+            if (e - b == 1) {
+                first[static_cast<size_t>(b) >> 5] |= 1u << (b & 31);
+                continue;
+            }
+            idx.resize(static_cast<size_t>(e - b));
+            for (int64_t a = b; a < e; ++a) idx[static_cast<size_t>(a - b)] = a;
+            std::sort(idx.begin(), idx.end(), [&](int64_t p, int64_t q) {
+                const ArcRec &rp_ = arcs[static_cast<size_t>(p)], &rq = arcs[static_cast<size_t>(q)];
+                if (rp_.y != rq.y) return rp_.y < rq.y;
+                if (rp_.w != rq.w) return rp_.w < rq.w;
+                return p < q;
+            });
+            for (size_t i = 0; i < idx.size(); ++i)
+                if (i == 0 || arcs[static_cast<size_t>(idx[i])].y != arcs[static_cast<size_t>(idx[i - 1])].y)
+                    first[static_cast<size_t>(idx[i]) >> 5] |= 1u << (idx[i] & 31);
+        }
+    } catch (...) {
+        return fail(RN_ERR_NOMEM, "building the device graph");
+    }
     hipError_t e = hipSuccess;
+    if (!g->d_first && (e = dev_alloc(&g->d_first, std::max<size_t>(first.size(), 1))) != hipSuccess)
+        return hip_fail(e, "uploading the graph");
+    if (!first.empty() &&
+        (e = hipMemcpy(g->d_first, first.data(), first.size() * sizeof(uint32_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(e, "uploading the graph");
     if (!g->d_row_ptr && (e = dev_alloc(&g->d_row_ptr, rp.size())) != hipSuccess)
         return hip_fail(e, "uploading the graph");
     if (!g->d_arcs && (e = dev_alloc(&g->d_arcs, arcs.size())) != hipSuccess) return hip_fail(e, "uploading the graph");
@@ -825,6 +875,7 @@ void rn_graph_free(rn_graph *g) {
     dev_free(g->d_arcs);
     dev_free(g->d_rank);
     dev_free(g->d_order);
+    dev_free(g->d_first);
     delete g;
 }
 
@@ -1037,7 +1088,6 @@ rn_status rn_autotune(rn_graph *g, rn_query *q, int32_t nq, int32_t sample, void
                 t.hash_log2 = hbs[hi];
                 Prepared p;
                 result = prepare(g, &t, 1, p);
-                if (result == RN_OK) result = ensure_gslots(g->ws, g->Vmax, kDefaultSlots);
                 if (result != RN_OK) break;
                 float ms = 3.4e38f;
                 for (int rep = 0; rep < 3 && result == RN_OK; ++rep) {
@@ -1084,7 +1134,6 @@ rn_status capture_plan(rn_plan *pl, const Prepared &p) {
     rn_graph *g = pl->g;
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec), pl->exec = nullptr;
     if (pl->graph) (void)hipGraphDestroy(pl->graph), pl->graph = nullptr;
-    RN_TRY(ensure_gslots(pl->ws, g->Vmax, kDefaultSlots));
     RN_HIP(hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal), "starting the capture");
     const rn_status st = enqueue_call(g, pl->ws, p, pl->out, pl->cap, pl->cap_stream, false);
     hipGraph_t graph = nullptr;
@@ -1101,7 +1150,6 @@ rn_status capture_plan(rn_plan *pl, const Prepared &p) {
 
 // Eager run to size the buffers, then capture.
 rn_status plan_build(rn_plan *pl, const Prepared &p, hipStream_t s, int64_t *offsets, int32_t *status) {
-    RN_TRY(ensure_gslots(pl->ws, pl->g->Vmax, kDefaultSlots));
     const rn_status st = run_eager(pl->g, pl->ws, p, pl->out, pl->cap, offsets, status, s, false);
     if (st != RN_OK && st != RN_ERR_CAPACITY && st != RN_ERR_ARG) return st;
     RN_TRY(capture_plan(pl, p));
@@ -1157,7 +1205,7 @@ rn_status rn_plan_run(rn_plan *pl, int64_t *offsets, int32_t *status, void *stre
     RN_HIP(hipGraphLaunch(pl->exec, s), "launching the graph");
     RN_TRY(read_back(pl->ws, p, s));
     bool regrow = false;
-    const rn_status st = finish(g, pl->ws, p, pl->cap, offsets, status, false, &regrow);
+    const rn_status st = finish(g, pl->ws, p, pl->cap, offsets, status, false, &regrow, s);
     if (!regrow) return st;
     // the records outgrew the buffer (grown by finish): run eagerly, re-capture
     return plan_build(pl, p, s, offsets, status);

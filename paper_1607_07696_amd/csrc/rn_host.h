@@ -91,8 +91,9 @@ struct Workspace {
     hipEvent_t fork = nullptr;
     hipEvent_t join[kSide] = {};
     hipEvent_t ev[EV_COUNT] = {};
-    uint32_t *d_gslots = nullptr;   // global_slot_words(Vmax) words per slot
-    uint32_t n_gslots = 0;
+    uint32_t *d_gslots = nullptr;   // global_slot_words(Vmax) words per slot, allocated when
+    uint32_t n_gslots = 0;          //   a call first sends a search to the global tier
+    uint32_t gslot_cap = 256;       // most slots this workspace allocates
 
     void release() {
         dev_free(d_gslots);
@@ -127,6 +128,7 @@ struct Workspace {
 struct Group {
     int hb;
     bool kcp;               // some query of the group asks for k closest pairs
+    bool compact;           // its launch uses compact on-chip tables
     int32_t first;          // staging positions [first, end)
     int32_t end;
     uint64_t sources;       // sum of nR
@@ -161,8 +163,16 @@ std::string describe_err(uint32_t err);
 // Host-side checks of a batch (status[i] marks the malformed queries).
 rn_status check_queries(const rn_graph *g, const rn_query *q, int32_t nq, int32_t *status);
 rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p);
-// Allocate (once) and clear nslots global-tier slots for graphs of up to Vmax vertices.
-rn_status ensure_gslots(Workspace &ws, int32_t Vmax, uint32_t nslots);
+// Global-tier slots are allocated on demand: a call enqueued while a
+// workspace has none skips the global tier, and if any of its searches needed
+// it (ctl.nlist[2] > 0) the call is run again once slots exist.  Allocate (once)
+// and clear slots for `want` concurrent searches (at most ws.gslot_cap, within
+// 48 GiB) for graphs of up to Vmax vertices; the clearing runs on s, which is
+// synchronised.
+rn_status ensure_gslots(Workspace &ws, int32_t Vmax, uint32_t want, hipStream_t s);
+inline size_t gslot_bytes(const Workspace &ws, int32_t Vmax) {
+    return static_cast<size_t>(ws.n_gslots) * global_slot_words(Vmax) * 4;
+}
 rn_status ensure_buffers(Workspace &ws, const Prepared &p);
 rn_status grow_recs(Workspace &ws, unsigned long long need);
 void fill_host_desc(const Prepared &p, uint8_t *h);
@@ -200,6 +210,7 @@ struct rn_graph {
     // allocated at load:
     int32_t *d_rank = nullptr;      // global vertex (caller numbering) -> local id in the device copy
     int32_t *d_order = nullptr;     // global vertex of the device copy -> local id in the caller numbering
+    uint32_t *d_first = nullptr;    // per arc record: first lightest arc of its (tail, target) pair
     std::vector<char> renumbered;   // per graph: the device copy is in leaf order (else as loaded)
 
     uint32_t delta = 0;

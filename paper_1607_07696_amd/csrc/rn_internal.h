@@ -154,6 +154,8 @@ struct JoinArgs {
     int32_t count_work;         // 1: accumulate ctl->arcs / ctl->settled
     int32_t big_deg;            // 1: some vertex has 2^16 or more arcs (searches reaching one move on)
     const int32_t *order;       // global vertex of the device copy -> local id in the caller's numbering
+    const uint32_t *first;      // bit a: arc a is the first lightest of the arcs from its tail to its
+                                //   target (parallel arcs give one pair, at that arc's weight)
 };
 
 // State of the global-memory tier: n slots (one per concurrent block), V the
@@ -207,11 +209,17 @@ size_t stage_scratch_words(size_t rwords);
 
 // Relaxation at the on-chip tier with table size 2^hash_log2.  generic =
 // false: every source belongs to a theta-join (the kernel variant without the
-// k-closest-pairs code).  persistent: a device-filling grid of blocks that
-// loop over the sources; else one block per source.
-hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, uint32_t max_sources, bool persistent,
-                       hipStream_t s);
+// k-closest-pairs code).  compact: the table packs each slot into one 32-bit
+// word (every graph of the call has fewer than kCompactVertices vertices; a
+// search reaching a distance above compact_max_dist(hash_log2), or a probe
+// sequence longer than the word records, is queued for the next tier like
+// one that outgrows its table).  persistent: a device-filling grid of blocks
+// that loop over the sources; else one block per source.
+constexpr int32_t kCompactVertices = 1 << 24;
+hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, bool compact, uint32_t max_sources,
+                       bool persistent, hipStream_t s);
 int join_tier_supported(int hash_log2);
+uint32_t compact_max_dist(int hash_log2);
 // The global-memory tier: one block per source, nslots slots of
 // global_slot_words(Vmax) words in the layout above.
 hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslots, int32_t Vmax,

@@ -145,23 +145,25 @@ __device__ __forceinline__ void lds_store(uint32_t *p, uint32_t v) {
 
 // ------------------------------------------------------------------ per-source search state
 // H: distance-table slots (open addressing, linear probing, filled to at most
-// 3/4).  PC: capacity of each vertex list (pending set, frontier).
-template <int HB>
+// 3/4).  PC: capacity of each vertex list (pending set, frontier).  CT: the
+// compact table (one 32-bit word per slot, below), else the wide one (a key
+// array and a distance-word array).
+template <int HB, bool CT>
 struct Tier {
     static constexpr int H = 1 << HB;
     // list capacity: the ring (2 PC entries) holds a search's pending set (at
     // most about 120 vertices for searches that fit 2^11 entries on road
-    // graphs, 250 for 2^13 and 370 for 2^14); sized so that every table from
-    // 2^11 on fits 8 waves per CU
+    // graphs, 250 for 2^13 and 370 for 2^14); sized so that every wide table
+    // from 2^11 on fits 8 waves per CU
     static constexpr int PC = HB <= 12 ? 128 : (HB == 13 ? 256 : 512);
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
     // waves per search: a large table leaves room for few searches per CU, so
-    // several waves share each one (a block): two for 2^12 (four searches per
-    // CU), four for 2^13 (two), eight for 2^14 (one); every wave takes 64
-    // vertices per step and has its own window of W arcs.  (More waves per
-    // search are slower where the pending set is smaller than a step: eight
-    // on 2^13, two on 2^11.)
-    static constexpr int NW = HB >= 14 ? 8 : (HB == 13 ? 4 : (HB == 12 ? 2 : 1));
+    // several waves share each one (a block): two for 2^12, four for 2^13,
+    // eight for a wide 2^14 table (one search per CU) and four for a compact
+    // one (two per CU); every wave takes 64 vertices per step and has its own
+    // window of W arcs.  (More waves per search are slower where the pending
+    // set is smaller than a step: eight on 2^13, two on 2^11.)
+    static constexpr int NW = HB >= 14 ? (CT ? 4 : 8) : (HB == 13 ? 4 : (HB == 12 ? 2 : 1));
     static constexpr int G = 1;
     static constexpr uint32_t W = kWin * G;
 };
@@ -182,30 +184,159 @@ __device__ __forceinline__ uint32_t wave_in_block() { return threadIdx.x >> 6; }
 // and marks the vertex pending only when nd is strictly smaller (an equal
 // distance over a zero-weight arc leaves the word alone); the lane that finds
 // the old word idle or empty appends the vertex.  Expansion clears the bit.
-// On-chip tables therefore hold distances up to 2^31 - 2; a search that needs
+// Wide tables therefore hold distances up to 2^31 - 2; a search that needs
 // longer ones moves on to the global tier.
 constexpr uint32_t kWordNone = 0xFFFFFFFFu;   // empty slot (above every stored word)
-constexpr uint32_t kPackMax = 0x7FFFFFFEu;    // largest distance an on-chip table holds
-constexpr uint32_t kNoKey = 0xFFFFFFFEu;      // compare value no stored key equals
+constexpr uint32_t kPackMax = 0x7FFFFFFEu;    // largest distance a wide table holds
+constexpr uint32_t kNoKey = 0xFFFFFFFEu;      // compare value no stored key (or compact word) equals
+
+// Compact tables hold a slot's distance word and the identity of its vertex
+// in one 32-bit word, which halves a search's LDS (8 KiB for 2^11 slots
+// instead of 16) so that more searches fit a CU.  The vertex's local id y
+// (below 2^24) is hashed by a bijection of 24-bit integers, z = y * kHash24 mod
+// 2^24 (Fibonacci hashing); the top HB bits of z give the home slot, and a
+// slot stores the other IDB = 24 - HB bits (the remainder) and the probe
+// distance from the home slot (DB bits), which together with the slot
+// determine z and so y.  Above them sits the distance word, (distance << 1) |
+// pending, in the remaining HB + 5 bits:
+//   [ distance | pending | probe distance | remainder ]
+// Words of one vertex differ only in the distance word, so atomicMin on a
+// slot known to hold the vertex acts as on the wide table's distance word,
+// and a compare-and-swap on an empty slot claims it with its first distance.
+// A search whose distance or probe sequence does not fit moves on to a
+// wide table.
+constexpr uint32_t kHash24 = 10368889u;       // odd, about 2^24 / golden ratio
+constexpr uint32_t inverse_mod_2_32(uint32_t a) {
+    uint32_t x = a;                            // Newton: each step doubles the correct low bits
+    for (int i = 0; i < 5; ++i) x *= 2u - a * x;
+    return x;
+}
+constexpr uint32_t kHash24Inv = inverse_mod_2_32(kHash24) & 0xFFFFFFu;
+static_assert(((kHash24 * kHash24Inv) & 0xFFFFFFu) == 1u, "24-bit hash inverse");
+static_assert(kCompactVertices == (1 << 24), "compact tables hash 24-bit local ids");
 
 template <int HB>
-struct SearchLds {
-    static constexpr int H = Tier<HB>::H;
-    static constexpr int PC = Tier<HB>::PC;
-    uint32_t key[H];            // vertex id, or kEmpty
+struct Compact {
+    static constexpr uint32_t IDB = 24u - HB;                 // remainder bits
+    static constexpr uint32_t DB = 3u;                        // probe distance bits (at most 7)
+    static constexpr uint32_t SH = IDB + DB;                  // position of the distance word
+    static constexpr uint32_t REM = (1u << IDB) - 1u;
+    static constexpr uint32_t IDM = (1u << SH) - 1u;          // identity: probe distance and remainder
+    static constexpr uint32_t PEND = 1u << SH;                // the pending bit
+    static constexpr uint32_t MAXP = (1u << DB) - 1u;         // longest probe distance
+    // largest distance: its word stays below kNoKey and kWordNone
+    static constexpr uint32_t MAXD = (1u << (HB + 4)) - 2u;
+};
+
+__device__ __forceinline__ uint32_t hash24(uint32_t y) { return (y * kHash24) & 0xFFFFFFu; }
+
+template <int HB, bool CT>
+struct SearchLds;
+
+template <int HB>
+struct SearchLds<HB, false> {
+    static constexpr int H = Tier<HB, false>::H;
+    static constexpr int PC = Tier<HB, false>::PC;
+    uint32_t key[H];            // vertex id (global), or kEmpty
     uint32_t dw[H];             // distance word, kWordNone when empty
     uint2 lst[2][PC];           // two vertex lists of {slot | (arc count << 16), first arc} (with
                                 //   delta = 0, one ring of 2 PC entries over the same words)
-    uint2 win[Tier<HB>::W * Tier<HB>::NW];   // per wave: window arc -> {arc index, distance of the
-                                //   arc's tail}; outside a window step, entry lane is the write
-                                //   sink of lanes with nothing to store (distinct addresses, no
-                                //   serialised writes) and the staging area of emitted pairs
+    uint2 win[Tier<HB, false>::W * Tier<HB, false>::NW];   // per wave: window arc -> {arc index,
+                                //   distance of the arc's tail}; outside a window step, entry
+                                //   lane is the write sink of lanes with nothing to store
+                                //   (distinct addresses, no serialised writes) and the staging
+                                //   area of emitted pairs
     __device__ uint2 *wwin() {
-        if constexpr (Tier<HB>::NW == 1) return win;
-        else return win + wave_in_block() * Tier<HB>::W;
+        if constexpr (Tier<HB, false>::NW == 1) return win;
+        else return win + wave_in_block() * Tier<HB, false>::W;
     }
     __device__ uint2 *sink() { return wwin() + lane_id(); }
 };
+
+template <int HB>
+struct SearchLds<HB, true> {
+    static constexpr int H = Tier<HB, true>::H;
+    static constexpr int PC = Tier<HB, true>::PC;
+    uint32_t t[H];              // compact word, kWordNone when empty
+    uint2 lst[2][PC];           // as in the wide table
+    uint2 win[Tier<HB, true>::W * Tier<HB, true>::NW];
+    __device__ uint2 *wwin() {
+        if constexpr (Tier<HB, true>::NW == 1) return win;
+        else return win + wave_in_block() * Tier<HB, true>::W;
+    }
+    __device__ uint2 *sink() { return wwin() + lane_id(); }
+};
+
+// ---- table access shared by both layouts
+// Distance held in slot s.
+template <int HB, bool CT>
+__device__ __forceinline__ uint32_t slot_dist(SearchLds<HB, CT> &L, uint32_t s) {
+    if constexpr (CT) return L.t[s] >> (Compact<HB>::SH + 1u);
+    else return L.dw[s] >> 1;
+}
+
+// Clear the pending bit of slot s (lanes with !valid issue a no-op on their own slot).
+template <int HB, bool CT>
+__device__ __forceinline__ void clear_pending(SearchLds<HB, CT> &L, uint32_t s, bool valid) {
+    if constexpr (CT) atomicAnd(&L.t[valid ? s : lane_id()], valid ? ~Compact<HB>::PEND : 0xFFFFFFFFu);
+    else atomicAnd(&L.dw[valid ? s : lane_id()], valid ? ~1u : 0xFFFFFFFFu);
+}
+
+// Set slot s pending again; returns whether it already was.
+template <int HB, bool CT>
+__device__ __forceinline__ bool mark_pending(SearchLds<HB, CT> &L, uint32_t s, bool valid) {
+    if constexpr (CT)
+        return (atomicOr(&L.t[valid ? s : lane_id()], valid ? Compact<HB>::PEND : 0u) & Compact<HB>::PEND) != 0u;
+    else
+        return (atomicOr(&L.dw[valid ? s : lane_id()], valid ? 1u : 0u) & 1u) != 0u;
+}
+
+// Empty slot s.
+template <int HB, bool CT>
+__device__ __forceinline__ void clear_slot(SearchLds<HB, CT> &L, uint32_t s) {
+    if constexpr (CT) {
+        lds_store(&L.t[s], kWordNone);
+    } else {
+        lds_store(&L.key[s], kEmpty);
+        L.dw[s] = kWordNone;
+    }
+}
+
+// Vertex (global id) and distance in slot s; false if the slot is empty.
+template <int HB, bool CT>
+__device__ __forceinline__ bool read_slot(SearchLds<HB, CT> &L, uint32_t s, int32_t voff, uint32_t &y,
+                                          uint32_t &d) {
+    if constexpr (CT) {
+        using K = Compact<HB>;
+        const uint32_t w = lds_load(&L.t[s]);
+        const uint32_t home = (s - ((w >> K::IDB) & K::MAXP)) & (Tier<HB, true>::H - 1u);
+        y = ((((home << K::IDB) | (w & K::REM)) * kHash24Inv) & 0xFFFFFFu) + static_cast<uint32_t>(voff);
+        d = w >> (K::SH + 1u);
+        return w != kWordNone;
+    } else {
+        y = lds_load(&L.key[s]);
+        d = L.dw[s] >> 1;
+        return y != kEmpty;
+    }
+}
+
+// Put source u (global id) at distance 0, pending, into the empty table;
+// returns its slot.
+template <int HB, bool CT>
+__device__ __forceinline__ uint32_t put_source(SearchLds<HB, CT> &L, int32_t u, int32_t voff) {
+    if constexpr (CT) {
+        using K = Compact<HB>;
+        const uint32_t z = hash24(static_cast<uint32_t>(u - voff));
+        const uint32_t h0 = z >> K::IDB;
+        lds_store(&L.t[h0], K::PEND | (z & K::REM));
+        return h0;
+    } else {
+        const uint32_t h0 = slot_hash<HB>(static_cast<uint32_t>(u));
+        lds_store(&L.key[h0], static_cast<uint32_t>(u));
+        L.dw[h0] = 1u;
+        return h0;
+    }
+}
 
 struct WaveState {
     uint32_t np;    // entries queued (pending list, or the ring between head and tail)
@@ -274,6 +405,13 @@ __device__ __forceinline__ bool in_s(const SrcCtx &c, uint32_t y) {
     return (c.sbits[yl >> 5] >> (yl & 31u)) & 1u;
 }
 
+// Whether arc x is the first lightest of the arcs joining its tail to its
+// target: parallel arcs make one pair, at the lightest weight (bits computed
+// on the host when the graph is uploaded).
+__device__ __forceinline__ bool first_of_pair(const JoinArgs &a, int32_t x) {
+    return (a.first[static_cast<uint32_t>(x) >> 5] >> (x & 31)) & 1u;
+}
+
 // The caller's local id of global vertex x of the device copy (which
 // rn_partition renumbers in leaf order).
 __device__ __forceinline__ int32_t caller_id(const JoinArgs &a, int32_t x, int32_t voff) {
@@ -308,75 +446,142 @@ __device__ __forceinline__ void probe_phase(const SrcCtx &c, uint32_t &pnew, boo
 // (compare-and-swap on an empty home slot doubles as the first probe), then
 // the packed atomicMin.  Idle lanes issue no-op atomics instead of branching.
 // Called by all 64 lanes; st.ovf is wave-uniform afterwards.
-template <int HB, int NJ>
-__device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, const SrcCtx &c,
+template <int HB, bool CT, int NJ>
+__device__ __forceinline__ void relax_window(SearchLds<HB, CT> &L, WaveState &st, const SrcCtx &c,
                                              const ArcRec *r, const uint32_t *nd, uint32_t bound) {
-    constexpr uint32_t H = Tier<HB>::H;
-    // slot states: 0 idle, 1 slot holds y, 2 slot claimed for y, 3 keep probing
+    constexpr uint32_t H = Tier<HB, CT>::H;
+    // slot states: 0 idle, 1 slot holds y, 2 slot claimed for y, 3 keep probing;
+    // after the min: 4 improved a pending vertex, 5 improved an idle or new
+    // one, which this lane appends
     uint32_t h[NJ], stt[NJ], old[NJ];
-    // a distance the packed word cannot hold (possible only when the bound
+    bool fresh[NJ];   // the slot was empty before this window: a new table entry
+    // a distance the table's word cannot hold (possible only when the bound
     // itself is that large) sends the search on to the next tier
-    const uint32_t lim = min(bound, kPackMax);
+    constexpr uint32_t kMaxWord = CT ? Compact<HB>::MAXD : kPackMax;
+    const uint32_t lim = min(bound, kMaxWord);
     bool lost = false;
-    if (bound > kPackMax) {
+    if (bound > kMaxWord) {
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) lost |= nd[j] <= bound && nd[j] > kPackMax;
+        for (int j = 0; j < NJ; ++j) lost |= nd[j] <= bound && nd[j] > kMaxWord;
     }
+    if constexpr (CT) {
+        using K = Compact<HB>;
+        // compare-and-swap of the vertex's word (distance nd, pending, probe
+        // distance 0) into its home slot: an empty slot is claimed with its
+        // first distance at once; a slot of the same identity holds y (then
+        // the atomicMin below); any other identity sends y one slot on
+        uint32_t nw[NJ];
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        // idle lanes aim their no-op atomics at distinct slots: a shared address would serialise
-        h[j] = nd[j] <= lim ? slot_hash<HB>(static_cast<uint32_t>(r[j].y)) : lane_id();
-    }
+        for (int j = 0; j < NJ; ++j) {
+            const bool act = nd[j] <= lim;
+            const uint32_t z = hash24(static_cast<uint32_t>(r[j].y - c.voff));
+            // idle lanes aim their no-op atomics at distinct slots: a shared address would serialise
+            h[j] = act ? z >> K::IDB : lane_id();
+            nw[j] = act ? ((((nd[j] << 1) | 1u) << K::SH) | (z & K::REM)) : kWordNone;
+        }
 #pragma unroll
-    for (int j = 0; j < NJ; ++j)
-        old[j] = atomicCAS(&L.key[h[j]], nd[j] <= lim ? kEmpty : kNoKey, static_cast<uint32_t>(r[j].y));
-    __builtin_amdgcn_sched_barrier(0);   // every claim is issued before the first result is used
-    bool probe = false;
+        for (int j = 0; j < NJ; ++j) old[j] = atomicCAS(&L.t[h[j]], nd[j] <= lim ? kWordNone : kNoKey, nw[j]);
+        __builtin_amdgcn_sched_barrier(0);   // every claim is issued before the first result is used
+        bool probe = false;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const uint32_t y = static_cast<uint32_t>(r[j].y);
-        stt[j] = nd[j] > lim ? 0u : (old[j] == kEmpty ? 2u : (old[j] == y ? 1u : 3u));
-        probe |= stt[j] == 3u;
-    }
-    if (__ballot(probe) != 0) {
-        // linear probing past an occupied home slot, in rounds: each round
-        // moves every slot still searching one place on and issues all their
-        // compare-and-swaps (no-ops for the rest) before any result is used.
-        // (Linear probing beats double hashing here: the ids of a ball are
-        // clustered, and multiplicative hashing spreads runs of them evenly.)
-        for (uint32_t round = 1;; ++round) {
+        for (int j = 0; j < NJ; ++j) {
+            stt[j] = nd[j] > lim ? 0u : (old[j] == kWordNone ? 2u : (((old[j] ^ nw[j]) & K::IDM) == 0u ? 1u : 3u));
+            probe |= stt[j] == 3u;
+        }
+        if (__ballot(probe) != 0) {
+            // linear probing in rounds, as in the wide table; the probe
+            // distance is part of the identity, so it is raised with the slot
+            for (uint32_t round = 1;; ++round) {
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const bool act = stt[j] == 3u;
-                h[j] = act ? ((h[j] + 1u) & (H - 1)) : h[j];
-                old[j] = atomicCAS(&L.key[act ? h[j] : lane_id()], act ? kEmpty : kNoKey,
-                                   static_cast<uint32_t>(r[j].y));
-            }
-            bool more = false;
+                for (int j = 0; j < NJ; ++j) {
+                    const bool act = stt[j] == 3u;
+                    h[j] = act ? ((h[j] + 1u) & (H - 1)) : h[j];
+                    nw[j] += act ? (1u << K::IDB) : 0u;
+                    old[j] = atomicCAS(&L.t[act ? h[j] : lane_id()], act ? kWordNone : kNoKey, nw[j]);
+                }
+                bool more = false;
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const uint32_t y = static_cast<uint32_t>(r[j].y);
-                if (stt[j] == 3u) stt[j] = old[j] == kEmpty ? 2u : (old[j] == y ? 1u : 3u);
-                more |= stt[j] == 3u;
-            }
-            if (__ballot(more) == 0) break;
-            if (round >= H) {   // every slot visited: the table is full
-                lost = lost || more;
-                break;
+                for (int j = 0; j < NJ; ++j) {
+                    if (stt[j] == 3u)
+                        stt[j] = old[j] == kWordNone ? 2u : (((old[j] ^ nw[j]) & K::IDM) == 0u ? 1u : 3u);
+                    more |= stt[j] == 3u;
+                }
+                if (__ballot(more) == 0) break;
+                if (round >= K::MAXP) {   // the probe distance field is full
+                    lost = lost || more;
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) stt[j] = stt[j] == 3u ? 0u : stt[j];
+                    break;
+                }
             }
         }
-    }
-    uint32_t v[NJ];
+        // the min on slots found to hold y; claimed slots already hold nd
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        v[j] = (stt[j] == 1u || stt[j] == 2u) ? (nd[j] << 1) | 1u : kWordNone;   // nd <= lim here
-        old[j] = atomicMin(&L.dw[h[j]], v[j]);
-    }
-    __builtin_amdgcn_sched_barrier(0);   // every min is issued before the first result is used
+        for (int j = 0; j < NJ; ++j) old[j] = atomicMin(&L.t[stt[j] == 1u ? h[j] : lane_id()], stt[j] == 1u ? nw[j] : kWordNone);
+        __builtin_amdgcn_sched_barrier(0);   // every min is issued before the first result is used
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        // 4: improved a pending vertex; 5: improved an idle or new one, which this lane appends
-        stt[j] = (v[j] < old[j]) ? ((old[j] == kWordNone || (old[j] & 1u) == 0u) ? 5u : 4u) : stt[j];
+        for (int j = 0; j < NJ; ++j) {
+            fresh[j] = stt[j] == 2u;
+            if (stt[j] == 1u && nw[j] < old[j]) stt[j] = (old[j] & K::PEND) == 0u ? 5u : 4u;
+            else if (stt[j] == 2u) stt[j] = 5u;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            // idle lanes aim their no-op atomics at distinct slots: a shared address would serialise
+            h[j] = nd[j] <= lim ? slot_hash<HB>(static_cast<uint32_t>(r[j].y)) : lane_id();
+        }
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            old[j] = atomicCAS(&L.key[h[j]], nd[j] <= lim ? kEmpty : kNoKey, static_cast<uint32_t>(r[j].y));
+        __builtin_amdgcn_sched_barrier(0);   // every claim is issued before the first result is used
+        bool probe = false;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const uint32_t y = static_cast<uint32_t>(r[j].y);
+            stt[j] = nd[j] > lim ? 0u : (old[j] == kEmpty ? 2u : (old[j] == y ? 1u : 3u));
+            probe |= stt[j] == 3u;
+        }
+        if (__ballot(probe) != 0) {
+            // linear probing past an occupied home slot, in rounds: each round
+            // moves every slot still searching one place on and issues all their
+            // compare-and-swaps (no-ops for the rest) before any result is used.
+            // (Linear probing beats double hashing here: the ids of a ball are
+            // clustered, and multiplicative hashing spreads runs of them evenly.)
+            for (uint32_t round = 1;; ++round) {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    const bool act = stt[j] == 3u;
+                    h[j] = act ? ((h[j] + 1u) & (H - 1)) : h[j];
+                    old[j] = atomicCAS(&L.key[act ? h[j] : lane_id()], act ? kEmpty : kNoKey,
+                                       static_cast<uint32_t>(r[j].y));
+                }
+                bool more = false;
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    const uint32_t y = static_cast<uint32_t>(r[j].y);
+                    if (stt[j] == 3u) stt[j] = old[j] == kEmpty ? 2u : (old[j] == y ? 1u : 3u);
+                    more |= stt[j] == 3u;
+                }
+                if (__ballot(more) == 0) break;
+                if (round >= H) {   // every slot visited: the table is full
+                    lost = lost || more;
+                    break;
+                }
+            }
+        }
+        uint32_t v[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            v[j] = (stt[j] == 1u || stt[j] == 2u) ? (nd[j] << 1) | 1u : kWordNone;   // nd <= lim here
+            old[j] = atomicMin(&L.dw[h[j]], v[j]);
+        }
+        __builtin_amdgcn_sched_barrier(0);   // every min is issued before the first result is used
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            stt[j] = (v[j] < old[j]) ? ((old[j] == kWordNone || (old[j] & 1u) == 0u) ? 5u : 4u) : stt[j];
+            fresh[j] = old[j] == kWordNone && stt[j] >= 4u;
+        }
     }
     uint64_t mA[NJ];
     uint32_t nadd = 0;
@@ -393,21 +598,21 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, co
     }
     uint32_t ins = 0;
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) ins += popc(__ballot(old[j] == kWordNone && stt[j] >= 4u));
-    if constexpr (Tier<HB>::NW == 1) st.nins += ins;
+    for (int j = 0; j < NJ; ++j) ins += popc(__ballot(fresh[j]));
+    if constexpr (Tier<HB, CT>::NW == 1) st.nins += ins;
     if (st.probing && ins != 0) {
         // k-closest pairs: a first discovery of an S member is a pair with a
         // path of length nd
         uint32_t *ph = probe_hist(c);
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const bool fresh = old[j] == kWordNone && stt[j] >= 4u && in_s(c, static_cast<uint32_t>(r[j].y));
-            if (fresh) atomicAdd(&ph[dist_bin(nd[j])], 1u);
-            st.pnew += popc(__ballot(fresh));
+            const bool found = fresh[j] && in_s(c, static_cast<uint32_t>(r[j].y));
+            if (found) atomicAdd(&ph[dist_bin(nd[j])], 1u);
+            st.pnew += popc(__ballot(found));
         }
     }
     uint2 *q = &L.lst[0][0];
-    if constexpr (Tier<HB>::NW > 1) {
+    if constexpr (Tier<HB, CT>::NW > 1) {
         // a block search: reserve ring entries and count table entries in
         // the block's shared state (one atomic each per wave)
         uint32_t base = 0, fill = 0;
@@ -451,8 +656,8 @@ __device__ __forceinline__ void relax_window(SearchLds<HB> &L, WaveState &st, co
 
 // Load window arcs j*64 + lane (j < NJ) and relax them.  Every load is issued
 // before any is used; lanes past the window's end load arc 0 and stay idle.
-template <int HB, int NJ>
-__device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, const SrcCtx &c,
+template <int HB, bool CT, int NJ>
+__device__ __forceinline__ void window_step(SearchLds<HB, CT> &L, WaveState &st, const SrcCtx &c,
                                             const ArcRec *__restrict__ arcs, uint32_t cnt,
                                             uint32_t bound) {
     const uint32_t lane = lane_id();
@@ -474,7 +679,7 @@ __device__ __forceinline__ void window_step(SearchLds<HB> &L, WaveState &st, con
 #pragma unroll
     for (int j = 0; j < NJ; ++j) nd[j] = sat_add(od[j], r[j].w) | (j * 64 + lane < cnt ? 0u : kInf);
     wave_sync();  // window map fully read before the next window rewrites it
-    relax_window<HB, NJ>(L, st, c, r, nd, bound);
+    relax_window<HB, CT, NJ>(L, st, c, r, nd, bound);
 }
 
 // k-closest pairs: once the query has emitted k records, bound its k-th
@@ -511,8 +716,8 @@ static_assert(kMaxQueries <= 0x10000, "query numbers fit the low 16 bits of a re
 __device__ __forceinline__ uint32_t bin_place(uint32_t place) { return min(place, kPlaceNone) << 16; }
 
 // Write this wave's staged pairs ({dist, v} in stg) for source u.
-template <int HB>
-__device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
+template <int HB, bool CT>
+__device__ __forceinline__ void flush_pairs(SearchLds<HB, CT> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
                                             uint32_t &nst, const uint2 *stg) {
     if (nst == 0) return;
     const unsigned long long base = reserve_recs(a, c, nst);
@@ -538,14 +743,14 @@ __device__ __forceinline__ void flush_pairs(SearchLds<HB> &L, const JoinArgs &a,
 
 // Expand up to 64 G queued vertices (G per lane: list entries eb[g], valid[g],
 // distances d[g] read from the table just before, so that improvements made
-// since a vertex was queued are used): clear their pending flags, then relax
-// their arcs, windows of 256 G at a time.  Whole wave.
-template <int HB, int G>
-__device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, const SrcCtx &c, const JoinArgs &a,
+// since a vertex was queued are used): clear their pending flags (unless the
+// caller has: CLR = false), then relax their arcs, windows of 256 G at a
+// time.  Whole wave.
+template <int HB, bool CT, int G, bool CLR = true>
+__device__ __forceinline__ void expand_chunk(SearchLds<HB, CT> &L, WaveState &st, const SrcCtx &c, const JoinArgs &a,
                                              const uint2 *eb, const bool *valid, const uint32_t *d,
                                              uint32_t bound) {
     constexpr uint32_t W = kWin * G;
-    const uint32_t lane = lane_id();
     uint32_t deg[G];
     int32_t b[G];
     uint32_t sum = 0;
@@ -554,7 +759,7 @@ __device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, co
         const uint32_t e = eb[g].x;
         const uint32_t sl = e & 0xFFFFu;
         b[g] = static_cast<int32_t>(eb[g].y);
-        atomicAnd(&L.dw[valid[g] ? sl : lane], valid[g] ? ~1u : 0xFFFFFFFFu);  // expanded now: not pending
+        if constexpr (CLR) clear_pending(L, sl, valid[g]);   // expanded now: not pending
         deg[g] = (valid[g] && d[g] <= bound) ? (e >> 16) : 0u;
         sum += deg[g];
     }
@@ -572,17 +777,17 @@ __device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, co
         wave_sync();
         const uint32_t cnt = min(W, total - wb);
         switch ((cnt + 63u) / 64u) {
-            case 1: window_step<HB, 1>(L, st, c, a.arcs, cnt, bound); break;
-            case 2: window_step<HB, 2>(L, st, c, a.arcs, cnt, bound); break;
-            case 3: window_step<HB, 3>(L, st, c, a.arcs, cnt, bound); break;
-            case 4: window_step<HB, 4>(L, st, c, a.arcs, cnt, bound); break;
+            case 1: window_step<HB, CT, 1>(L, st, c, a.arcs, cnt, bound); break;
+            case 2: window_step<HB, CT, 2>(L, st, c, a.arcs, cnt, bound); break;
+            case 3: window_step<HB, CT, 3>(L, st, c, a.arcs, cnt, bound); break;
+            case 4: window_step<HB, CT, 4>(L, st, c, a.arcs, cnt, bound); break;
             default:
                 if constexpr (G > 1) {
                     switch ((cnt + 63u) / 64u) {
-                        case 5: window_step<HB, 5>(L, st, c, a.arcs, cnt, bound); break;
-                        case 6: window_step<HB, 6>(L, st, c, a.arcs, cnt, bound); break;
-                        case 7: window_step<HB, 7>(L, st, c, a.arcs, cnt, bound); break;
-                        default: window_step<HB, 8>(L, st, c, a.arcs, cnt, bound); break;
+                        case 5: window_step<HB, CT, 5>(L, st, c, a.arcs, cnt, bound); break;
+                        case 6: window_step<HB, CT, 6>(L, st, c, a.arcs, cnt, bound); break;
+                        case 7: window_step<HB, CT, 7>(L, st, c, a.arcs, cnt, bound); break;
+                        default: window_step<HB, CT, 8>(L, st, c, a.arcs, cnt, bound); break;
                     }
                 }
                 break;
@@ -596,10 +801,10 @@ __device__ __forceinline__ void expand_chunk(SearchLds<HB> &L, WaveState &st, co
 // the direct arcs from u into S no heavier than the bound, at the weight of
 // the lightest arc of each pair (parallel arcs: the first lightest).  The
 // source emits those without a search.  Whole wave.
-template <int HB>
-__device__ __forceinline__ void direct_pairs(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
+template <int HB, bool CT>
+__device__ __forceinline__ void direct_pairs(SearchLds<HB, CT> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
                                              unsigned long long &tseen) {
-    constexpr uint32_t PC = Tier<HB>::PC;
+    constexpr uint32_t PC = Tier<HB, CT>::PC;
     const uint32_t lane = lane_id();
     const uint32_t bound = current_bound(c);
     const int32_t ub = a.row_ptr[c.rpo + u], ue = a.row_ptr[c.rpo + u + 1];
@@ -610,11 +815,7 @@ __device__ __forceinline__ void direct_pairs(SearchLds<HB> &L, const JoinArgs &a
         ArcRec r{0, 0, 0, 0};
         if (x < ue) {
             r = a.arcs[x];
-            m = r.w <= bound && in_s(c, static_cast<uint32_t>(r.y));
-            for (int32_t z = ub; z < ue && m; ++z) {
-                const ArcRec o = a.arcs[z];
-                if (o.y == r.y && (o.w < r.w || (o.w == r.w && z < x))) m = false;
-            }
+            m = r.w <= bound && first_of_pair(a, x) && in_s(c, static_cast<uint32_t>(r.y));
         }
         const uint64_t mM = __ballot(m);
         if (m) atomicAdd(&c.hist[kHistEmit + dist_bin(r.w)], 1u);
@@ -623,11 +824,11 @@ __device__ __forceinline__ void direct_pairs(SearchLds<HB> &L, const JoinArgs &a
         nst += popc(mM);
         if (nst + 64 > PC) {
             wave_sync();
-            flush_pairs<HB>(L, a, c, u, nst, &L.lst[0][0]);
+            flush_pairs<HB, CT>(L, a, c, u, nst, &L.lst[0][0]);
         }
     }
     wave_sync();
-    flush_pairs<HB>(L, a, c, u, nst, &L.lst[0][0]);
+    flush_pairs<HB, CT>(L, a, c, u, nst, &L.lst[0][0]);
     if (emitted != 0) tighten_bound(c, tseen);
     wave_sync();
 }
@@ -642,19 +843,17 @@ __device__ __forceinline__ void direct_pairs(SearchLds<HB> &L, const JoinArgs &a
 // up behind the rest at once, so no window waits for a phase to end.  The
 // search ends when nothing is pending; every table entry then holds its exact
 // distance, and entries in S become pairs.
-template <int HB>
-__device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
+template <int HB, bool CT>
+__device__ void search_source(SearchLds<HB, CT> &L, const JoinArgs &a, const SrcCtx &c, int32_t u,
                               unsigned long long &tseen) {
-    constexpr int H = Tier<HB>::H;
-    constexpr int PC = Tier<HB>::PC;
-    constexpr int U = Tier<HB>::U;
+    constexpr int H = Tier<HB, CT>::H;
+    constexpr int PC = Tier<HB, CT>::PC;
+    constexpr int U = Tier<HB, CT>::U;
     const uint32_t lane = lane_id();
     const int32_t ub = a.row_ptr[c.rpo + u];
     const int32_t ue = a.row_ptr[c.rpo + u + 1];
     if (lane == 0) {
-        const uint32_t h0 = slot_hash<HB>(static_cast<uint32_t>(u));   // table is empty
-        lds_store(&L.key[h0], static_cast<uint32_t>(u));
-        L.dw[h0] = 1u;                                                // distance 0, pending
+        const uint32_t h0 = put_source(L, u, c.voff);   // the table is empty
         L.lst[0][0] = make_uint2(h0 | (static_cast<uint32_t>(min(ue - ub, 0xFFFF)) << 16), static_cast<uint32_t>(ub));
     }
     wave_sync();
@@ -684,7 +883,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
             if (c.hist != nullptr && phase >= 2) probe_phase(c, st.pnew, st.probing, seen);
             ++phase;
             bound = current_bound(c);
-            constexpr int G = Tier<HB>::G;
+            constexpr int G = Tier<HB, CT>::G;
             const uint32_t m = min(64u * G, st.np);
             uint2 eb[G];
             bool valid[G];
@@ -698,7 +897,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
             wave_sync();  // the taken entries are read before appends reuse their slots
             uint32_t dd[G];
 #pragma unroll
-            for (int g = 0; g < G; ++g) dd[g] = L.dw[valid[g] ? (eb[g].x & 0xFFFFu) : lane] >> 1;
+            for (int g = 0; g < G; ++g) dd[g] = slot_dist(L, valid[g] ? (eb[g].x & 0xFFFFu) : lane);
             if (c.slack != kInf) {
                 // a vertex far above the step's least distance goes back to
                 // the tail, still pending: its distance is likely to improve
@@ -719,7 +918,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 st.np += base - st.tail;
                 st.tail = base;
             }
-            expand_chunk<HB, G>(L, st, c, a, eb, valid, dd, bound);
+            expand_chunk<HB, CT, G>(L, st, c, a, eb, valid, dd, bound);
         }
     } else {
         uint32_t P = 0;      // list receiving appends (the pending list)
@@ -738,13 +937,13 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 const uint32_t ic = valid ? i : 0u;
                 const uint2 eb = L.lst[P][ic];
                 const uint32_t e = eb.x;
-                const uint32_t d = L.dw[e & 0xFFFFu] >> 1;
+                const uint32_t d = slot_dist(L, e & 0xFFFFu);
                 const bool isF = valid && d < thr && d <= bound;
                 const bool isK = valid && d >= thr && d <= bound;
                 const bool drop = valid && d > bound;
                 const uint64_t mF = __ballot(isF), mK = __ballot(isK);
                 wave_sync();  // every lane has read its entry before the in-place compaction
-                atomicAnd(&L.dw[valid ? (e & 0xFFFFu) : lane], drop ? ~1u : 0xFFFFFFFFu);  // dropped: not pending
+                clear_pending(L, e & 0xFFFFu, drop);   // dropped: not pending
                 *(isF ? &L.lst[F][nf + mbcnt(mF)] : L.sink()) = eb;
                 *(isK ? &L.lst[P][nk + mbcnt(mK)] : L.sink()) = eb;
                 kmin = min(kmin, isK ? d : kInf);
@@ -761,8 +960,8 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
                 const uint32_t f = fb + lane;
                 const bool valid = f < nf;
                 const uint2 eb = L.lst[F][valid ? f : 0u];
-                const uint32_t dd = L.dw[valid ? (eb.x & 0xFFFFu) : lane] >> 1;
-                expand_chunk<HB, 1>(L, st, c, a, &eb, &valid, &dd, bound);
+                const uint32_t dd = slot_dist(L, valid ? (eb.x & 0xFFFFu) : lane);
+                expand_chunk<HB, CT, 1>(L, st, c, a, &eb, &valid, &dd, bound);
             }
             if (st.ovf) break;
             pmin = min(wave_min(kmin), wave_min(st.imin));
@@ -776,28 +975,23 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
     uint32_t wsettled = 0;
     for (uint32_t g0 = 0; g0 < static_cast<uint32_t>(H); g0 += 64 * U) {
         uint32_t k[U], d[U];
-        bool sb[U];
+        bool occ[U], sb[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const uint32_t slot = g0 + j * 64 + lane;
-            k[j] = lds_load(&L.key[slot]);
-            d[j] = L.dw[slot] >> 1;
-            sb[j] = !st.ovf && k[j] != kEmpty && in_s(c, k[j]);
+            occ[j] = read_slot(L, slot, c.voff, k[j], d[j]);
+            sb[j] = !st.ovf && occ[j] && in_s(c, k[j]);
         }
         if (a.count_work && !st.ovf) {
 #pragma unroll
             for (int j = 0; j < U; ++j)
-                if (k[j] != kEmpty && d[j] <= bound) {
+                if (occ[j] && d[j] <= bound) {
                     warcs += static_cast<unsigned long long>(a.row_ptr[c.rpo + k[j] + 1] - a.row_ptr[c.rpo + k[j]]);
                     wsettled += 1;
                 }
         }
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const uint32_t slot = g0 + j * 64 + lane;
-            lds_store(&L.key[slot], kEmpty);
-            L.dw[slot] = kWordNone;
-        }
+        for (int j = 0; j < U; ++j) clear_slot(L, g0 + j * 64 + lane);
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const bool m = sb[j] && d[j] <= bound;
@@ -808,12 +1002,12 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
             nst += popc(mM);
             if (nst + 64 > static_cast<uint32_t>(PC)) {
                 wave_sync();
-                flush_pairs<HB>(L, a, c, u, nst, &L.lst[0][0]);
+                flush_pairs<HB, CT>(L, a, c, u, nst, &L.lst[0][0]);
             }
         }
     }
     wave_sync();
-    flush_pairs<HB>(L, a, c, u, nst, &L.lst[0][0]);
+    flush_pairs<HB, CT>(L, a, c, u, nst, &L.lst[0][0]);
     if (c.k && emitted != 0) tighten_bound(c, tseen);
     if (a.count_work && !st.ovf) {
         for (int o = 32; o > 0; o >>= 1) {
@@ -836,7 +1030,7 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
     wave_sync();
 }
 
-// The same search by a block of Tier<HB>::NW waves sharing one table (tables
+// The same search by a block of Tier<HB, CT>::NW waves sharing one table (tables
 // of 2^12 entries and more, which leave room for few searches per CU):
 // the ring of pending vertices is shared, each step the waves take 64
 // vertices at most each (dealt round-robin), put back the ones far above the
@@ -846,21 +1040,19 @@ __device__ void search_source(SearchLds<HB> &L, const JoinArgs &a, const SrcCtx 
 // LDS after a barrier, so the waves always agree.  The delta of the query
 // is not used (one bucket, as with delta = 0: the distances are the same),
 // nor the one-hop shortcut of k-closest pairs (the search finds those pairs).
-template <int HB>
-__device__ void search_source_block(SearchLds<HB> &L, BlockRing &B, const JoinArgs &a, const SrcCtx &c,
+template <int HB, bool CT>
+__device__ void search_source_block(SearchLds<HB, CT> &L, BlockRing &B, const JoinArgs &a, const SrcCtx &c,
                                     int32_t u, unsigned long long &tseen) {
-    constexpr int H = Tier<HB>::H;
-    constexpr int NW = Tier<HB>::NW;
-    constexpr int U = Tier<HB>::U;
-    constexpr uint32_t RC = 2u * Tier<HB>::PC;
+    constexpr int H = Tier<HB, CT>::H;
+    constexpr int NW = Tier<HB, CT>::NW;
+    constexpr int U = Tier<HB, CT>::U;
+    constexpr uint32_t RC = 2u * Tier<HB, CT>::PC;
     const uint32_t lane = lane_id(), wv = wave_in_block();
     const int32_t ub = a.row_ptr[c.rpo + u];
     const int32_t ue = a.row_ptr[c.rpo + u + 1];
     uint2 *q = &L.lst[0][0];
     if (threadIdx.x == 0) {
-        const uint32_t h0 = slot_hash<HB>(static_cast<uint32_t>(u));   // table is empty
-        lds_store(&L.key[h0], static_cast<uint32_t>(u));
-        L.dw[h0] = 1u;                                                // distance 0, pending
+        const uint32_t h0 = put_source(L, u, c.voff);   // the table is empty
         q[0] = make_uint2(h0 | (static_cast<uint32_t>(min(ue - ub, 0xFFFF)) << 16), static_cast<uint32_t>(ub));
         B.tail = 1;
         B.nins = 1;
@@ -896,7 +1088,13 @@ __device__ void search_source_block(SearchLds<HB> &L, BlockRing &B, const JoinAr
         const uint32_t mine = lane * NW + wv;
         bool valid = mine < m;
         const uint2 eb = q[(head + mine) & (RC - 1u)];
-        uint32_t dd = L.dw[valid ? (eb.x & 0xFFFFu) : lane] >> 1;
+        const uint32_t es = valid ? (eb.x & 0xFFFFu) : lane;
+        uint32_t dd = slot_dist(L, es);
+        // taken entries stop being pending before the barrier: nothing is
+        // relaxed between the last step's barrier and this one, so dd is the
+        // distance the expansion uses, and a wave that improves one of these
+        // vertices after the barrier finds it idle and queues it again
+        clear_pending(L, es, valid);
         head += m;
         st.head = head;
         if (c.slack != kInf) {
@@ -907,17 +1105,21 @@ __device__ void search_source_block(SearchLds<HB> &L, BlockRing &B, const JoinAr
         if (threadIdx.x == 0) B.dmin[par ^ 1u] = kInf;   // for the next step (read after the next barrier)
         if (c.slack != kInf) {
             const uint32_t lim = sat_add(B.dmin[par], c.slack);
-            const bool later = valid && dd > lim && dd <= bound;
-            const uint64_t mL = __ballot(later);
-            if (mL != 0) {
+            bool later = valid && dd > lim && dd <= bound;
+            if (__ballot(later) != 0) {
+                // put back, pending again, unless a relaxation since the
+                // barrier has queued the vertex already
+                const bool queued = mark_pending(L, es, later);
+                const bool app = later && !queued;
+                const uint64_t mL = __ballot(app);
                 uint32_t base = 0;
-                if (lane == 0) base = atomicAdd(&B.tail, popc(mL));
+                if (lane == 0 && mL != 0) base = atomicAdd(&B.tail, popc(mL));
                 base = readlane(base, 0);
-                *(later ? q + ((base + mbcnt(mL)) & (RC - 1u)) : L.sink()) = eb;
+                *(app ? q + ((base + mbcnt(mL)) & (RC - 1u)) : L.sink()) = eb;
             }
             valid = valid && !later;
         }
-        expand_chunk<HB, 1>(L, st, c, a, &eb, &valid, &dd, bound);
+        expand_chunk<HB, CT, 1, false>(L, st, c, a, &eb, &valid, &dd, bound);
         __syncthreads();   // every append of the step is done
     }
     const bool ovf = B.ovf != 0;
@@ -934,28 +1136,23 @@ __device__ void search_source_block(SearchLds<HB> &L, BlockRing &B, const JoinAr
     constexpr uint32_t SL = static_cast<uint32_t>(H / NW);
     for (uint32_t g0 = wv * SL; g0 < (wv + 1) * SL; g0 += 64 * U) {
         uint32_t k[U], d[U];
-        bool sb[U];
+        bool occ[U], sb[U];
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const uint32_t slot = g0 + j * 64 + lane;
-            k[j] = lds_load(&L.key[slot]);
-            d[j] = L.dw[slot] >> 1;
-            sb[j] = !ovf && k[j] != kEmpty && in_s(c, k[j]);
+            occ[j] = read_slot(L, slot, c.voff, k[j], d[j]);
+            sb[j] = !ovf && occ[j] && in_s(c, k[j]);
         }
         if (a.count_work && !ovf) {
 #pragma unroll
             for (int j = 0; j < U; ++j)
-                if (k[j] != kEmpty && d[j] <= bound) {
+                if (occ[j] && d[j] <= bound) {
                     warcs += static_cast<unsigned long long>(a.row_ptr[c.rpo + k[j] + 1] - a.row_ptr[c.rpo + k[j]]);
                     wsettled += 1;
                 }
         }
 #pragma unroll
-        for (int j = 0; j < U; ++j) {
-            const uint32_t slot = g0 + j * 64 + lane;
-            lds_store(&L.key[slot], kEmpty);
-            L.dw[slot] = kWordNone;
-        }
+        for (int j = 0; j < U; ++j) clear_slot(L, g0 + j * 64 + lane);
 #pragma unroll
         for (int j = 0; j < U; ++j) {
             const bool mm = sb[j] && d[j] <= bound;
@@ -966,12 +1163,12 @@ __device__ void search_source_block(SearchLds<HB> &L, BlockRing &B, const JoinAr
             nst += popc(mM);
             if (nst + 64 > SC) {
                 wave_sync();
-                flush_pairs<HB>(L, a, c, u, nst, stg);
+                flush_pairs<HB, CT>(L, a, c, u, nst, stg);
             }
         }
     }
     wave_sync();
-    flush_pairs<HB>(L, a, c, u, nst, stg);
+    flush_pairs<HB, CT>(L, a, c, u, nst, stg);
     if (c.k && emitted != 0) tighten_bound(c, tseen);
     if (a.count_work && !ovf) {
         for (int o = 32; o > 0; o >>= 1) {
@@ -1006,21 +1203,18 @@ __device__ __forceinline__ void launch_range(const JoinArgs &a, uint32_t &b, uin
 // source order and keeps its part of the graph in its own L2.  GEN = false:
 // every source belongs to a theta-join, and the k-closest-pairs code is
 // compiled out.
-template <int HB, bool GEN>
-__global__ __launch_bounds__(64 * Tier<HB>::NW) void k_join(JoinArgs a) {
-    __shared__ SearchLds<HB> L;
-    constexpr int H = Tier<HB>::H;
-    constexpr int NW = Tier<HB>::NW;
+template <int HB, bool GEN, bool CT>
+__global__ __launch_bounds__((64 * Tier<HB, CT>::NW)) void k_join(JoinArgs a) {
+    __shared__ SearchLds<HB, CT> L;
+    constexpr int H = Tier<HB, CT>::H;
+    constexpr int NW = Tier<HB, CT>::NW;
     uint32_t b, n;
     launch_range(a, b, n);
     const uint32_t per = (n + 7u) / 8u;
     if (blockIdx.x >= 8u * per) return;
     // one k-query answered by k_kcp_direct: nothing to search
     if (GEN && a.srcq[b] == a.srcq[b + n - 1] && a.qs[a.srcq[b]].direct) return;
-    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(H); i += 64 * NW) {
-        lds_store(&L.key[i], kEmpty);
-        L.dw[i] = kWordNone;
-    }
+    for (uint32_t i = threadIdx.x; i < static_cast<uint32_t>(H); i += 64 * NW) clear_slot(L, i);
     if constexpr (NW > 1) {
         __shared__ BlockRing B;
         __syncthreads();
@@ -1039,7 +1233,7 @@ __global__ __launch_bounds__(64 * Tier<HB>::NW) void k_join(JoinArgs a) {
                 tq = c.q;
                 tseen = 0;
             }
-            search_source_block<HB>(L, B, a, c, a.src[b + si], tseen);
+            search_source_block<HB, CT>(L, B, a, c, a.src[b + si], tseen);
         }
     } else {
         wave_sync();
@@ -1060,9 +1254,9 @@ __global__ __launch_bounds__(64 * Tier<HB>::NW) void k_join(JoinArgs a) {
             }
             if (GEN && c.k != 0 && !a.count_work &&
                 static_cast<uint64_t>(current_bound(c)) < 2ull * static_cast<uint64_t>(c.wmin))
-                direct_pairs<HB>(L, a, c, a.src[b + si], tseen);
+                direct_pairs<HB, CT>(L, a, c, a.src[b + si], tseen);
             else
-                search_source<HB>(L, a, c, a.src[b + si], tseen);
+                search_source<HB, CT>(L, a, c, a.src[b + si], tseen);
         }
     }
 }
@@ -1520,13 +1714,8 @@ __global__ __launch_bounds__(256) void k_kcp_seed_hist(JoinArgs a) {
             const int32_t b = a.row_ptr[c.rpo + u], e = a.row_ptr[c.rpo + u + 1];
             for (int32_t x = b; x < e; ++x) {
                 const ArcRec r = a.arcs[x];
-                if (!in_s(c, static_cast<uint32_t>(r.y))) continue;
-                bool lightest = true;
-                for (int32_t z = b; z < e && lightest; ++z) {
-                    const ArcRec o = a.arcs[z];
-                    if (o.y == r.y && (o.w < r.w || (o.w == r.w && z < x))) lightest = false;
-                }
-                if (lightest) atomicAdd(one ? &h[dist_bin(r.w)] : &seed[dist_bin(r.w)], 1u);
+                if (!first_of_pair(a, x) || !in_s(c, static_cast<uint32_t>(r.y))) continue;
+                atomicAdd(one ? &h[dist_bin(r.w)] : &seed[dist_bin(r.w)], 1u);
             }
         }
     }
@@ -1562,13 +1751,10 @@ __global__ __launch_bounds__(64) void k_kcp_seed_bound(const QueryDesc *qd, Quer
 // count, reserve, then write.  The query's searches are skipped.
 __device__ __forceinline__ bool direct_pair(const JoinArgs &a, const SrcCtx &c, int32_t b, int32_t e, int32_t x,
                                             uint32_t bound, ArcRec &r) {
+    (void)b;
+    (void)e;
     r = a.arcs[x];
-    if (r.w > bound || !in_s(c, static_cast<uint32_t>(r.y))) return false;
-    for (int32_t z = b; z < e; ++z) {
-        const ArcRec o = a.arcs[z];
-        if (o.y == r.y && (o.w < r.w || (o.w == r.w && z < x))) return false;
-    }
-    return true;
+    return r.w <= bound && first_of_pair(a, x) && in_s(c, static_cast<uint32_t>(r.y));
 }
 
 __global__ __launch_bounds__(256) void k_kcp_direct(JoinArgs a) {
@@ -1966,7 +2152,7 @@ __global__ __launch_bounds__(256) void k_bucket_rank(CallBuffers b, rn_pair *out
     }
 }
 
-template <int HB, bool GEN>
+template <int HB, bool GEN, bool CT>
 hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, bool persistent, hipStream_t s) {
     static int resident = 0;  // blocks per CU, per device this process uses first
     static int cus = 0;
@@ -1978,7 +2164,7 @@ hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, bool persis
         e = hipGetDeviceProperties(&prop, dev);
         if (e != hipSuccess) return e;
         int occ = 0;
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_join<HB, GEN>, 64 * Tier<HB>::NW, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_join<HB, GEN, CT>, 64 * Tier<HB, CT>::NW, 0);
         if (e != hipSuccess) return e;
         cus = prop.multiProcessorCount;
         resident = occ > 0 ? occ : 1;
@@ -1991,7 +2177,7 @@ hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, bool persis
     const uint64_t want = (static_cast<uint64_t>(max_sources) + 7) / 8 * 8;
     if (want < grid || !persistent) grid = want;
     if (grid == 0) grid = 8;
-    hipLaunchKernelGGL((k_join<HB, GEN>), dim3(static_cast<uint32_t>(grid)), dim3(64 * Tier<HB>::NW), 0, s, a);
+    hipLaunchKernelGGL((k_join<HB, GEN, CT>), dim3(static_cast<uint32_t>(grid)), dim3(64 * Tier<HB, CT>::NW), 0, s, a);
     return hipGetLastError();
 }
 
@@ -2027,12 +2213,17 @@ hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, cons
 
 int join_tier_supported(int hash_log2) { return hash_log2 >= kMinHB && hash_log2 <= kMaxHB; }
 
-hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, uint32_t max_sources, bool persistent,
-                       hipStream_t s) {
-#define RN_TIER(HB)                                                                   \
-    case HB:                                                                          \
-        return generic ? launch_join_tier<HB, true>(a, max_sources, persistent, s)    \
-                       : launch_join_tier<HB, false>(a, max_sources, persistent, s);
+uint32_t compact_max_dist(int hash_log2) { return (1u << (hash_log2 + 4)) - 2u; }
+
+hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, bool compact, uint32_t max_sources,
+                       bool persistent, hipStream_t s) {
+#define RN_TIER(HB)                                                                                   \
+    case HB:                                                                                          \
+        if (compact)                                                                                  \
+            return generic ? launch_join_tier<HB, true, true>(a, max_sources, persistent, s)          \
+                           : launch_join_tier<HB, false, true>(a, max_sources, persistent, s);        \
+        return generic ? launch_join_tier<HB, true, false>(a, max_sources, persistent, s)             \
+                       : launch_join_tier<HB, false, false>(a, max_sources, persistent, s);
     switch (hash_log2) {
         RN_TIER(8)
         RN_TIER(9)

@@ -79,9 +79,11 @@ struct Lane {
         if (ev_copy) (void)hipEventDestroy(ev_copy), ev_copy = nullptr;
         if (stream) (void)hipStreamDestroy(stream), stream = nullptr;
     }
-    size_t device_bytes() const {
+    // every device buffer of the lane, the global-tier slots included
+    size_t device_bytes(int32_t Vmax) const {
         return ws.block_words * 4 + ws.desc_bytes + ws.stage_words * 4 + ws.src_cap * 8 * (1 + kLists) +
-               static_cast<size_t>(ws.rec_cap) * 2 * sizeof(Rec) + ids_cap * 4 + out_cap * sizeof(rn_pair);
+               static_cast<size_t>(ws.rec_cap) * 2 * sizeof(Rec) + ids_cap * 4 + out_cap * sizeof(rn_pair) +
+               gslot_bytes(ws, Vmax);
     }
 };
 
@@ -188,7 +190,6 @@ rn_status launch_lane(rn_server *s, Lane &L) {
            "uploading request ids");
     RN_TRY(prepare(s->g, L.q.data(), static_cast<int32_t>(L.q.size()), L.prep));
     RN_TRY(ensure_buffers(L.ws, L.prep));
-    RN_TRY(ensure_gslots(L.ws, s->g->Vmax, static_cast<uint32_t>(s->cfg.global_slots)));
     if (L.out_cap == 0) {
         L.out_cap = 1u << 16;
         RN_HIP(dev_alloc(&L.d_out, L.out_cap), "allocating the output");
@@ -212,7 +213,11 @@ bool progress_lane(rn_server *s, Lane &L) {
         const CallCtl c = *reinterpret_cast<const CallCtl *>(L.ws.h_state);
         rn_status st = RN_OK;
         bool rerun = false;
-        if (c.npairs > L.ws.rec_cap) {
+        if (c.nlist[2] > 0 && !L.ws.d_gslots) {
+            // a search needed the global tier, whose slots this lane allocates on first need
+            st = ensure_gslots(L.ws, s->g->Vmax, c.nlist[2], L.stream);
+            rerun = true;
+        } else if (c.npairs > L.ws.rec_cap) {
             st = grow_recs(L.ws, c.npairs);
             rerun = true;
         } else if (c.nout > L.out_cap) {
@@ -267,14 +272,18 @@ bool progress_lane(rn_server *s, Lane &L) {
         for (size_t i = 0; i < L.batch.size(); ++i) {
             Request *r = L.batch[i];
             r->result.assign(L.h_out + qs[i].off, L.h_out + qs[i].off + qs[i].nout);
+        }
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (size_t i = 0; i < L.batch.size(); ++i) {
+            const Request *r = L.batch[i];
             if (r->k == 0 && qs[i].err == 0 && r->theta > 0 && r->theta < kMaxDist) {
-                // learn the ball-size estimate from what theta-joins really produced
+                // learn the ball-size estimate from what theta-joins really
+                // produced (read by rn_server_submit under the same lock)
                 const double c = static_cast<double>(qs[i].npairs) * s->V /
                                  (static_cast<double>(r->R.size()) * r->S.size() * double(r->theta) * r->theta);
                 s->c_ball = 0.8 * s->c_ball + 0.2 * c;
             }
         }
-        std::lock_guard<std::mutex> lk(s->mu);
         for (size_t i = 0; i < L.batch.size(); ++i) {
             Request *r = L.batch[i];
             if (qs[i].err) finish_request(s, r, RN_ERR_ARG, "invalid node sets:" + describe_err(qs[i].err));
@@ -339,9 +348,9 @@ void server_loop(rn_server *s) {
             const rn_status st = launch_lane(s, *L);
             if (st != RN_OK) fail_batch(s, *L, st, last_error());
         }
-        if (!to_launch.empty()) {
+        if (!to_launch.empty() || moved) {
             size_t bytes = 0;
-            for (const Lane &L : s->lanes) bytes += L.device_bytes();
+            for (const Lane &L : s->lanes) bytes += L.device_bytes(s->g->Vmax);
             std::lock_guard<std::mutex> lk(s->mu);
             s->stats.device_bytes = std::max<int64_t>(s->stats.device_bytes, static_cast<int64_t>(bytes));
         }
@@ -390,7 +399,7 @@ rn_status rn_server_create(rn_graph *g, const rn_server_config *cfg, rn_server *
             (e = hipEventCreateWithFlags(&L.ev_state, hipEventDisableTiming)) != hipSuccess ||
             (e = hipEventCreateWithFlags(&L.ev_copy, hipEventDisableTiming)) != hipSuccess)
             st = hip_fail(e, "creating lane streams");
-        if (st == RN_OK) st = ensure_gslots(L.ws, g->Vmax, static_cast<uint32_t>(cfg->global_slots));
+        L.ws.gslot_cap = static_cast<uint32_t>(cfg->global_slots);
     }
     if (st == RN_OK) {
         try {

@@ -261,14 +261,16 @@ class RoadNetwork:
             self._out = torch.empty((max(n, 1024), 3), dtype=torch.int32, device="cuda")
         return self._out
 
-    def _call(self, fn, R, S, arg, stream):
+    def _call(self, fn, R, S, arg, stream, guess):
         import torch
         R, S = self._dev_ids(R), self._dev_ids(S)
         if stream is None:
             stream = torch.cuda.current_stream()
         sptr = C.c_void_p(stream.cuda_stream)
         n = C.c_int64()
-        out = self._out_buffer(0)
+        # a first buffer large enough for most calls, so that a call is rarely
+        # issued twice (the second time only after RN_ERR_CAPACITY)
+        out = self._out_buffer(min(int(guess), R.numel() * S.numel()))
         st = fn(self._h, C.c_void_p(R.data_ptr()), R.numel(), C.c_void_p(S.data_ptr()), S.numel(),
                 arg, C.c_void_p(out.data_ptr()), out.shape[0], C.byref(n), sptr)
         if st == RN_ERR_CAPACITY and n.value > out.shape[0]:
@@ -282,11 +284,11 @@ class RoadNetwork:
         """Theta-join on the device: int32 tensor [n, 3] of (u, v, dist) sorted by (dist, u, v).
 
         The returned view aliases an internal buffer reused by the next call."""
-        return self._call(load_library().rn_dist_join, R, S, C.c_uint32(int(theta)), stream)
+        return self._call(load_library().rn_dist_join, R, S, C.c_uint32(int(theta)), stream, 1 << 22)
 
     def kcp_join(self, R, S, k: int, stream=None):
         """k closest pairs on the device: int32 tensor [n, 3], n = min(k, reachable pairs)."""
-        return self._call(load_library().rn_kcp_join, R, S, C.c_int32(int(k)), stream)
+        return self._call(load_library().rn_kcp_join, R, S, C.c_int32(int(k)), stream, int(k))
 
     # -------------------------------------------------------------- batches
     def make_queries(self, specs, keep: list | None = None):

@@ -267,3 +267,26 @@ def test_more_than_1024_queries_in_one_call(rnmod, orc, rg, sort):
     out, off, status = net.join_batch(specs)
     assert int(off[-1]) > 1000
     check_batch(rnmod, orc, out, off, status, cases)
+
+
+def test_config4_autotuned_plan_all_instances(rnmod, orc, instances, torch_cuda):
+    # the batched workload's headline form: all 128 instances autotuned (the
+    # benchmark's sample of 256 sources per query), captured as one plan and
+    # replayed, every replay checked against the oracle, with eager work and a
+    # synchronisation between replays
+    torch = torch_cuda
+    net = rnmod.RoadNetwork.from_graphs([x.graph for x in instances])
+    q, keep = net.make_queries([spec(x, i) for i, x in enumerate(instances)])
+    net.autotune(q, sample=256)
+    plan = net.plan(q)
+    cases = [(x.graph, x.R, x.S, x.theta if x.k == 0 else MAX_DIST, x.k) for x in instances]
+    wants = [oracle_answer(orc, *c) for c in cases]
+    for rep in range(3):
+        out, off, status = plan.run()
+        assert not status.any()
+        got = rnmod.split_batch(out, off)
+        for i, w in enumerate(wants):
+            assert_same(got[i], w, f"replay {rep}, instance {i}")
+        net.join_batch([spec(instances[3], 3)])
+        torch.cuda.synchronize()
+    plan.close()

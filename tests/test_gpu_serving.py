@@ -176,3 +176,66 @@ def test_config5_stream_sample_full_size(rnmod, orc, rg):
         r = reqs[i]
         want = orc.kcp_join(g, r.R, r.S, r.k) if r.k else orc.dist_join(g, r.R, r.S, r.theta).pairs
         assert_same(a, want, f"request {i}")
+
+
+@pytest.fixture(scope="module")
+def stream5(rg):
+    g = rg.road_graph(2048, 0)
+    return g, rg.serving_stream(g, 2000, 300.0, 5)
+
+
+def kcp_by_definition(orc, g, R, S, k):
+    # the first k pairs of the (dist, u, v) order over every reachable pair
+    # (Abstract / Section 1 definition): the multithreaded theta-join at an
+    # unbounded theta, cut to k, so whole-graph searches stay fast
+    return orc.dist_join(g, R, S, MAX_DIST).pairs[:k]
+
+
+def test_config5_heaviest_theta_joins_full_size(rnmod, orc, stream5):
+    # the five theta-join requests with the most pairs on the 2048x2048
+    # serving workload (request 860 alone emits over 2^20 records, more than a
+    # fresh lane's record buffer, so its batch takes the re-run path), served
+    # as the benchmark serves them, each checked against the oracle
+    g, reqs = stream5
+    sample = [860, 924, 1341, 744, 1662]
+    net = rnmod.RoadNetwork.from_graph(g)
+    srv = rnmod.Server(net, lanes=2, max_batch=8, global_slots=128)
+    ids = [srv.submit(reqs[i].R, reqs[i].S, reqs[i].theta, 0) for i in sample]
+    got = [srv.wait(x, guess=1 << 21)[0] for x in ids]
+    st = srv.stats()
+    srv.close()
+    assert st["reruns"] >= 1, st
+    assert got[0].shape[0] > (1 << 20)
+    for i, a in zip(sample, got):
+        r = reqs[i]
+        print(f"request {i}: |R|={len(r.R)} |S|={len(r.S)} theta={r.theta}: {a.shape[0]} pairs", flush=True)
+        assert_same(a, orc.dist_join(g, r.R, r.S, r.theta).pairs, f"request {i}")
+
+
+def test_config5_whole_graph_kcp_full_size(rnmod, orc, stream5):
+    # the k-closest-pairs requests whose k is close to |R| |S| (1400: 113 x 102,
+    # k = 4001; 1478: 76 x 129, k = 2894; 1409: 100 x 95, k = 2366): their
+    # searches span most of the graph and overflow every on-chip table into
+    # the global-memory tier.  Served in one mix with light requests, and one
+    # of them also through the single-query call, whose statistics show the
+    # global tier ran.
+    g, reqs = stream5
+    heavy = [1400, 1478, 1409]
+    light = [1, 8, 9, 10]
+    net = rnmod.RoadNetwork.from_graph(g)
+    srv = rnmod.Server(net, lanes=2, max_batch=8, global_slots=128)
+    order = [heavy[0], light[0], heavy[1], light[1], light[2], heavy[2], light[3]]
+    ids = {i: srv.submit(reqs[i].R, reqs[i].S, reqs[i].theta if reqs[i].k == 0 else MAX_DIST, reqs[i].k)
+           for i in order}
+    got = {i: srv.wait(x)[0] for i, x in ids.items()}
+    srv.close()
+    for i in order:
+        r = reqs[i]
+        want = kcp_by_definition(orc, g, r.R, r.S, r.k) if r.k else orc.dist_join(g, r.R, r.S, r.theta).pairs
+        print(f"request {i}: |R|={len(r.R)} |S|={len(r.S)} k={r.k}: {got[i].shape[0]} pairs", flush=True)
+        assert_same(got[i], want, f"request {i}")
+    r = reqs[heavy[0]]
+    net.set_profiling(times=True)
+    one = rnmod.pairs_to_numpy(net.kcp_join(r.R, r.S, r.k))
+    assert net.stats()["global_searches"] > 0
+    assert_same(one, got[heavy[0]], "single-query call")
