@@ -89,6 +89,31 @@ typedef struct rn_graph rn_graph;
 rn_status rn_graph_load(int32_t V, int64_t A, const int32_t *row_ptr, const int32_t *col,
                         const uint32_t *w, rn_graph **out);
 
+/*
+ * rn_objects_graph -- objects on the edges of a road network (Section 1:
+ * objects that move along edges, given by their distances from the two ends
+ * of their edge, may take the place of nodes in R or S).  Returns a new
+ * handle whose graph is graph `graph` of g with object i inserted into its
+ * edge as vertex V + i (V: that graph's vertex count); every join call then
+ * takes objects, nodes or both in R and S, and the pairs name object i as
+ * V + i.  Snapshot semantics: a moved object needs a new handle.
+ *   arc, offset  host int32[n], uint32[n]: object i lies on arc arc[i] =
+ *            (a -> b, weight w) of that graph (local arc index, 0 .. A-1), at
+ *            distance offset[i] <= w from a
+ * The object's edge is the road of that arc; parallel arcs of equal ends and
+ * weight are one road (the first of them carries the object), and the road
+ * is two-way when an arc b -> a of weight w exists (the first such arc, not
+ * the road's own arc for a loop, is the same road traversed back, so an
+ * object named on it lies on the same road at w - offset from a).  The road's arcs become a chain through its
+ * objects in order of position: one-way, objects move and are reached in the
+ * arc's direction only; two-way, both ways.  Distances between the graph's
+ * own vertices do not change.  The caller keeps its arrays; free the new
+ * handle with rn_graph_free.  Errors: RN_ERR_ARG (bad handle, index, arc or
+ * offset), RN_ERR_NOMEM, RN_ERR_DEVICE.
+ */
+rn_status rn_objects_graph(const rn_graph *g, int32_t graph, const int32_t *arc, const uint32_t *offset, int32_t n,
+                           rn_graph **out);
+
 /* Free a handle and all its device memory.  NULL is accepted. */
 void rn_graph_free(rn_graph *g);
 

@@ -58,6 +58,9 @@ def open_library(path: str):
     lib.orc_kcp_join.restype = C.c_int
     lib.orc_sssp.argtypes = [C.c_int32, i32p, i32p, u32p, C.c_int32, C.c_uint32, u32p]
     lib.orc_sssp.restype = C.c_int
+    lib.orc_object_join.argtypes = [C.c_int32, i32p, i32p, u32p, i32p, u32p, C.c_int32, i32p, u32p, C.c_int32,
+                                    C.c_uint32, pp, i64p]
+    lib.orc_object_join.restype = C.c_int
     lib.orc_free.argtypes = [C.c_void_p]
     lib.orc_num_cores.restype = C.c_int
     return lib
@@ -128,6 +131,25 @@ def kcp_join(g, R, S, k: int, lib=None) -> np.ndarray:
     rc = lib.orc_kcp_join(*gargs, Rp, len(R), Sp, len(S), int(k), C.byref(out), C.byref(n))
     if rc != 0:
         raise ValueError("oracle k-closest-pairs join rejected its arguments")
+    del keep
+    return _take_pairs(lib, out, n.value)
+
+
+def object_join(g, R_arc, R_off, S_arc, S_off, theta: int, lib=None) -> np.ndarray:
+    """Theta-join of objects on edges (object = arc index + distance from its
+    tail; see ``rn_oracle.c``): (i, j, dist) for R object i and S object j with
+    dist <= theta, sorted by (dist, i, j)."""
+    lib = lib or _load()
+    keep, gargs = _graph_args(g)
+    Ra, Rap = _arr(R_arc, np.int32)
+    Ro, Rop = _arr(R_off, np.uint32)
+    Sa, Sap = _arr(S_arc, np.int32)
+    So, Sop = _arr(S_off, np.uint32)
+    out, n = C.c_void_p(), C.c_int64()
+    rc = lib.orc_object_join(*gargs, Rap, Rop, len(Ra), Sap, Sop, len(Sa), C.c_uint32(int(theta)),
+                             C.byref(out), C.byref(n))
+    if rc != 0:
+        raise ValueError("oracle object join rejected its arguments")
     del keep
     return _take_pairs(lib, out, n.value)
 

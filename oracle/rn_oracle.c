@@ -373,4 +373,122 @@ int orc_sssp(int32_t V, const int32_t *row_ptr, const int32_t *col, const uint32
     return rc;
 }
 
+/* ---------------- objects on edges ----------------
+ * Section 1: objects that move along the road network's edges, each given by
+ * its distances from the two ends of the edge it is on, may form R or S.
+ * Reading taken here (the paper gives no formula):
+ *   - An object is named by an arc e = (a -> b, weight w) and its distance o
+ *     from a along that arc, 0 <= o <= w.  Parallel arcs of equal tail, head
+ *     and weight are one road: the object is on the first of them.
+ *   - The road is two-way when an arc b -> a of the same weight exists (its
+ *     twin: the first such arc other than the road's own, for a loop).  A road and its twin are one edge; an
+ *     object on either is placed on the one with the smaller arc index, f,
+ *     at distance s from f's tail (s = o, or w - o when it named the twin).
+ *   - From an object on f = (a -> b, w) at s, b is reached at s' = w - s, and
+ *     a at s when the road is two-way.  An object q on f_q = (c -> d, w_q) at
+ *     s_q is reached from c by s_q more and, two-way, from d by w_q - s_q.
+ *     Two objects on the same edge are also s_q - s_p apart along it when
+ *     that is >= 0, and |s_p - s_q| apart on a two-way road.
+ * dist(p, q) is the least of these: a path leaves p's edge at one of its
+ * ends, follows the network (dist between vertices as for the vertex joins)
+ * and enters q's edge at one of its ends, or stays on a shared edge.  The
+ * object theta-join returns (i, j, dist) for R object i and S object j with
+ * dist <= theta, sorted by (dist, i, j).
+ */
+typedef struct { int32_t f; uint32_t s, w; int32_t tail, head; int two_way; } orc_obj;
+
+/* Place object (arc e, offset o); returns -1 for a bad arc or offset. */
+static int obj_place(int32_t V, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+                     int64_t A, int32_t e, uint32_t o, orc_obj *ob) {
+    if (e < 0 || (int64_t)e >= A || o > w[e]) return -1;
+    /* tail of e: the row holding it (binary search over row_ptr) */
+    int32_t lo = 0, hi = V;
+    while (hi - lo > 1) { int32_t mid = lo + (hi - lo) / 2; if (row_ptr[mid] <= e) lo = mid; else hi = mid; }
+    int32_t a = lo, b = col[e];
+    uint32_t wt = w[e];
+    int32_t ec = e;                              /* first parallel arc of equal weight */
+    for (int32_t x = row_ptr[a]; x < row_ptr[a + 1]; x++)
+        if (col[x] == b && w[x] == wt) { ec = x; break; }
+    int32_t tw = -1;                             /* first b -> a arc of the same weight, */
+    for (int32_t x = row_ptr[b]; x < row_ptr[b + 1]; x++)   /* not the road's own arc (a loop) */
+        if (col[x] == a && w[x] == wt && x != ec) { tw = x; break; }
+    ob->w = wt;
+    ob->two_way = tw >= 0;
+    if (tw >= 0 && tw < ec) {                    /* the twin names the edge */
+        ob->f = tw; ob->s = wt - o; ob->tail = b; ob->head = a;
+    } else {
+        ob->f = ec; ob->s = o; ob->tail = a; ob->head = b;
+    }
+    return 0;
+}
+
+int orc_object_join(int32_t V, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
+                    const int32_t *Rarc, const uint32_t *Roff, int32_t nR,
+                    const int32_t *Sarc, const uint32_t *Soff, int32_t nS, uint32_t theta,
+                    orc_pair **out, int64_t *n_out) {
+    *out = NULL; *n_out = 0;
+    if (V < 1 || nR < 0 || nS < 0) return -1;
+    const int64_t A = row_ptr[V];
+    orc_obj *ro = (orc_obj *)malloc((size_t)(nR > 0 ? nR : 1) * sizeof(orc_obj));
+    orc_obj *so = (orc_obj *)malloc((size_t)(nS > 0 ? nS : 1) * sizeof(orc_obj));
+    search_ws ws;
+    int rc = (ro && so) ? ws_init(&ws, V, row_ptr, col, w) : -1;
+    if (rc) { free(ro); free(so); return -1; }
+    for (int32_t i = 0; i < nR && !rc; i++) rc = obj_place(V, row_ptr, col, w, A, Rarc[i], Roff[i], &ro[i]);
+    for (int32_t j = 0; j < nS && !rc; j++) rc = obj_place(V, row_ptr, col, w, A, Sarc[j], Soff[j], &so[j]);
+    pairvec pv = {NULL, 0, 0};
+    const uint64_t th = theta;
+    for (int32_t i = 0; i < nR && !rc; i++) {
+        const orc_obj *p = &ro[i];
+        /* Dijkstra from the object's exits: its edge's head at w - s, and its
+         * tail at s on a two-way road; cut off at theta */
+        const uint64_t eh = (uint64_t)p->w - p->s, et = p->s;
+        if (eh <= th) {
+            ws.dist[p->head] = eh;
+            ws.touched[ws.ntouched++] = p->head;
+            if (mh_push(&ws.heap, eh, p->head)) rc = -1;
+        }
+        if (!rc && p->two_way && et <= th && et < ws.dist[p->tail]) {
+            if (ws.dist[p->tail] == ORC_UNREACH) ws.touched[ws.ntouched++] = p->tail;
+            ws.dist[p->tail] = et;
+            if (mh_push(&ws.heap, et, p->tail)) rc = -1;
+        }
+        while (!rc && ws.heap.n > 0) {
+            hitem it = mh_pop(&ws.heap);
+            if (it.d != ws.dist[it.x]) continue;
+            if (it.d > th) break;
+            for (int32_t a = row_ptr[it.x]; a < row_ptr[it.x + 1]; a++) {
+                int32_t y = col[a];
+                uint64_t nd = it.d + w[a];
+                if (nd > th || nd >= ws.dist[y]) continue;
+                if (ws.dist[y] == ORC_UNREACH) ws.touched[ws.ntouched++] = y;
+                ws.dist[y] = nd;
+                if (mh_push(&ws.heap, nd, y)) { rc = -1; break; }
+            }
+        }
+        /* every S object: enter its edge at either end, or share p's edge */
+        for (int32_t j = 0; j < nS && !rc; j++) {
+            const orc_obj *q = &so[j];
+            uint64_t best = ORC_UNREACH;
+            if (ws.dist[q->tail] != ORC_UNREACH && ws.dist[q->tail] + q->s < best) best = ws.dist[q->tail] + q->s;
+            if (q->two_way && ws.dist[q->head] != ORC_UNREACH && ws.dist[q->head] + (q->w - q->s) < best)
+                best = ws.dist[q->head] + (q->w - q->s);
+            if (q->f == p->f) {
+                if (q->s >= p->s && (uint64_t)(q->s - p->s) < best) best = q->s - p->s;
+                if (p->two_way && p->s >= q->s && (uint64_t)(p->s - q->s) < best) best = p->s - q->s;
+            }
+            if (best <= th && pv_push(&pv, i, j, (uint32_t)best)) rc = -1;
+        }
+        /* dist entries beyond theta were never set, so the reset covers all */
+        ws_reset(&ws);
+    }
+    ws_free(&ws);
+    free(ro);
+    free(so);
+    if (rc) { free(pv.a); return -1; }
+    qsort(pv.a, (size_t)pv.n, sizeof(orc_pair), pair_cmp);
+    *out = pv.a; *n_out = pv.n;
+    return 0;
+}
+
 void orc_free(void *p) { free(p); }

@@ -106,7 +106,22 @@ uint32_t ring_slack(double wmean) {
 }
 
 rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p) {
+    // reset in place: the vectors keep their capacity, so a Prepared reused for
+    // calls of the same shape allocates nothing after its first call
+    auto qd = std::move(p.qd);
+    auto ebase = std::move(p.ebase);
+    auto rbase = std::move(p.rbase);
+    auto perm = std::move(p.perm);
+    auto groups = std::move(p.groups);
+    auto binbase = std::move(p.binbase);
     p = Prepared{};
+    p.qd = std::move(qd);
+    p.ebase = std::move(ebase);
+    p.rbase = std::move(rbase);
+    p.perm = std::move(perm);
+    p.groups = std::move(groups);
+    p.binbase = std::move(binbase);
+    p.groups.clear();
     p.nq = nq;
     p.qd.resize(nq);
     p.ebase.assign(nq + 1, 0);
@@ -167,7 +182,7 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         // compact tables: local ids below 2^24, and (theta-joins) every
         // distance within theta fits the compact word; a k-closest-pairs
         // search whose bound is larger moves on if it meets such a distance
-        gr.compact = false && gr.compact && g->Vmax < kCompactVertices &&
+        gr.compact = gr.compact && hb[i] >= kCompactMinHB && g->Vmax < kCompactVertices &&
                      (x.k > 0 || x.theta <= compact_max_dist(hb[i]));
     }
     p.rbase[nq] = static_cast<uint32_t>(rw);
@@ -443,10 +458,10 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.novf = &b.ctl->nlist[li + 1];
         t.first_tier = 0;
         t.tier = 1 + li;
-        // the 2^11 re-run takes a compact table where the graphs allow it (its
-        // own overflows still reach the wide 2^14 tier); the 2^14 re-run is wide
-        RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, true, false && li == 0 && g->Vmax < kCompactVertices, maxs,
-                           !shared, s),
+        // the re-run tiers take wide tables: they must hold any search the
+        // first tiers sent on, whatever its distances (a compact 2^14 re-run
+        // could only send those on to the global tier)
+        RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, true, false, maxs, !shared, s),
                "launching the relaxation");
     }
     if (ws.d_gslots) {   // (without slots the call is run again once they exist)
@@ -864,6 +879,131 @@ rn_status rn_graph_load_many(int32_t n, const int32_t *V, const int64_t *A, cons
 rn_status rn_graph_load(int32_t V, int64_t A, const int32_t *row_ptr, const int32_t *col, const uint32_t *w,
                         rn_graph **out) {
     return rn_graph_load_many(1, &V, &A, &row_ptr, &col, &w, out);
+}
+
+rn_status rn_objects_graph(const rn_graph *g, int32_t graph, const int32_t *arc, const uint32_t *offset, int32_t n,
+                           rn_graph **out) {
+    if (!out) return fail(RN_ERR_ARG, "out is NULL");
+    *out = nullptr;
+    if (!g) return fail(RN_ERR_ARG, "graph handle is NULL");
+    if (graph < 0 || graph >= g->ngraphs) return fail(RN_ERR_ARG, "graph index out of range");
+    if (n < 0 || (n > 0 && (!arc || !offset))) return fail(RN_ERR_ARG, "need n >= 0 objects and their arrays");
+    const int32_t vo = g->voff[graph], V = g->voff[graph + 1] - vo;
+    const int64_t ao = g->aoff[graph], A = g->aoff[graph + 1] - ao;
+    if (static_cast<int64_t>(V) + n >= 0x7FFFFFFF) return fail(RN_ERR_ARG, "too many objects");
+    if (A + 2 * static_cast<int64_t>(n) >= 0x7FFFFFFFLL) return fail(RN_ERR_ARG, "too many objects");
+    // the graph's own CSR (local ids)
+    auto rp = [&](int32_t x) { return static_cast<int64_t>(g->row_ptr[vo + x]) - ao; };
+    auto cl = [&](int64_t a) { return g->col[ao + a] - vo; };
+    auto wt = [&](int64_t a) { return g->w[ao + a]; };
+    // where each object sits: the arc naming its edge (of a road and its
+    // two-way twin, the one with the smaller index; of parallel arcs with
+    // equal ends and weight, the first), and its distance from that arc's tail
+    struct Place {
+        int64_t f, twin;
+        uint32_t s;
+    };
+    std::vector<Place> pl;
+    std::vector<std::vector<std::pair<uint32_t, int32_t>>> on_edge;   // per edge: (s, object)
+    std::vector<int64_t> edge_of_arc;   // arc -> edge slot (-1: no object), for f and its twin
+    try {
+        pl.resize(static_cast<size_t>(n));
+        edge_of_arc.assign(static_cast<size_t>(A), -1);
+        for (int32_t i = 0; i < n; ++i) {
+            const int64_t e = arc[i];
+            if (e < 0 || e >= A) return fail(RN_ERR_ARG, "object " + std::to_string(i) + ": arc out of range");
+            if (offset[i] > wt(e)) return fail(RN_ERR_ARG, "object " + std::to_string(i) + ": offset beyond its arc");
+            const int32_t a = static_cast<int32_t>(std::upper_bound(g->row_ptr.begin() + vo, g->row_ptr.begin() + vo + V + 1,
+                                                                    static_cast<int32_t>(ao + e)) -
+                                                   (g->row_ptr.begin() + vo)) - 1;
+            const int32_t b = cl(e);
+            const uint32_t w = wt(e);
+            int64_t ec = e, tw = -1;
+            for (int64_t x = rp(a); x < rp(a + 1); ++x)
+                if (cl(x) == b && wt(x) == w) { ec = x; break; }
+            for (int64_t x = rp(b); x < rp(b + 1); ++x)
+                if (cl(x) == a && wt(x) == w && x != ec) { tw = x; break; }
+            Place &p = pl[static_cast<size_t>(i)];
+            if (tw >= 0 && tw < ec) p = Place{tw, ec, w - offset[i]};
+            else p = Place{ec, tw, offset[i]};
+            if (edge_of_arc[static_cast<size_t>(p.f)] < 0) {
+                edge_of_arc[static_cast<size_t>(p.f)] = static_cast<int64_t>(on_edge.size());
+                if (p.twin >= 0) edge_of_arc[static_cast<size_t>(p.twin)] = static_cast<int64_t>(on_edge.size());
+                on_edge.emplace_back();
+            }
+            on_edge[static_cast<size_t>(edge_of_arc[static_cast<size_t>(p.f)])].emplace_back(p.s, i);
+        }
+    } catch (...) {
+        return fail(RN_ERR_NOMEM, "placing the objects");
+    }
+    for (auto &lst : on_edge) std::sort(lst.begin(), lst.end());
+    // the subdivided graph: object i is vertex V + i; an edge's arc (and its
+    // twin) is replaced by a chain through its objects in order of position
+    const int32_t Vn = V + n;
+    std::vector<int32_t> nrp, ncol;
+    std::vector<uint32_t> nw;
+    try {
+        nrp.assign(static_cast<size_t>(Vn) + 1, 0);
+        ncol.reserve(static_cast<size_t>(A + 2 * static_cast<int64_t>(n)));
+        nw.reserve(static_cast<size_t>(A + 2 * static_cast<int64_t>(n)));
+        for (int32_t x = 0; x < V; ++x) {
+            for (int64_t e = rp(x); e < rp(x + 1); ++e) {
+                const int64_t k = edge_of_arc[static_cast<size_t>(e)];
+                if (k < 0) {
+                    ncol.push_back(cl(e));
+                    nw.push_back(wt(e));
+                    continue;
+                }
+                const auto &lst = on_edge[static_cast<size_t>(k)];
+                const Place &p0 = pl[static_cast<size_t>(lst.front().second)];
+                if (e == p0.f) {           // tail -> first object
+                    ncol.push_back(V + lst.front().second);
+                    nw.push_back(lst.front().first);
+                } else {                   // the twin: head -> last object
+                    ncol.push_back(V + lst.back().second);
+                    nw.push_back(wt(e) - lst.back().first);
+                }
+            }
+            nrp[static_cast<size_t>(x) + 1] = static_cast<int32_t>(ncol.size());
+        }
+        // object rows: forward along the edge, then (two-way) back
+        std::vector<std::pair<int64_t, size_t>> where(static_cast<size_t>(n));   // (edge, rank)
+        for (size_t k = 0; k < on_edge.size(); ++k)
+            for (size_t r = 0; r < on_edge[k].size(); ++r)
+                where[static_cast<size_t>(on_edge[k][r].second)] = {static_cast<int64_t>(k), r};
+        for (int32_t i = 0; i < n; ++i) {
+            const Place &p = pl[static_cast<size_t>(i)];
+            const auto &lst = on_edge[static_cast<size_t>(where[static_cast<size_t>(i)].first)];
+            const size_t r = where[static_cast<size_t>(i)].second;
+            const uint32_t w = wt(p.f);
+            const int32_t tail = static_cast<int32_t>(std::upper_bound(g->row_ptr.begin() + vo,
+                                                                      g->row_ptr.begin() + vo + V + 1,
+                                                                      static_cast<int32_t>(ao + p.f)) -
+                                                     (g->row_ptr.begin() + vo)) - 1;
+            const int32_t head = cl(p.f);
+            if (r + 1 < lst.size()) {
+                ncol.push_back(V + lst[r + 1].second);
+                nw.push_back(lst[r + 1].first - p.s);
+            } else {
+                ncol.push_back(head);
+                nw.push_back(w - p.s);
+            }
+            if (p.twin >= 0) {
+                if (r > 0) {
+                    ncol.push_back(V + lst[r - 1].second);
+                    nw.push_back(p.s - lst[r - 1].first);
+                } else {
+                    ncol.push_back(tail);
+                    nw.push_back(p.s);
+                }
+            }
+            nrp[static_cast<size_t>(V) + i + 1] = static_cast<int32_t>(ncol.size());
+        }
+    } catch (...) {
+        return fail(RN_ERR_NOMEM, "building the graph with the objects");
+    }
+    const int64_t An = static_cast<int64_t>(ncol.size());
+    return rn_graph_load(Vn, An, nrp.data(), ncol.data(), nw.data(), out);
 }
 
 void rn_graph_free(rn_graph *g) {

@@ -216,10 +216,19 @@ size_t stage_scratch_words(size_t rwords);
 // one that outgrows its table).  persistent: a device-filling grid of blocks
 // that loop over the sources; else one block per source.
 constexpr int32_t kCompactVertices = 1 << 24;
+// bits of a compact word that hold a slot's probe distance (longer probe
+// sequences send the search on), and the largest distance the word holds
+constexpr uint32_t compact_disp_bits(int hash_log2) { return hash_log2 >= 14 ? 5u : 4u; }
+constexpr uint32_t compact_max_dist(int hash_log2) {
+    return (1u << (7u + static_cast<uint32_t>(hash_log2) - compact_disp_bits(hash_log2))) - 2u;
+}
+// Compact tables are used from this size on: below it the one-wave searches
+// are bound by instruction issue, not by residency, and the wide table's
+// simpler arithmetic is faster (2^11 at theta = 3000: 0.266 against 0.285 ms).
+constexpr int kCompactMinHB = 12;
 hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, bool compact, uint32_t max_sources,
                        bool persistent, hipStream_t s);
 int join_tier_supported(int hash_log2);
-uint32_t compact_max_dist(int hash_log2);
 // The global-memory tier: one block per source, nslots slots of
 // global_slot_words(Vmax) words in the layout above.
 hipError_t launch_join_global(const JoinArgs &a, uint32_t *slots, uint32_t nslots, int32_t Vmax,

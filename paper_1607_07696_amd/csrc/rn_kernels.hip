@@ -159,11 +159,12 @@ struct Tier {
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
     // waves per search: a large table leaves room for few searches per CU, so
     // several waves share each one (a block): two for 2^12, four for 2^13,
-    // eight for a wide 2^14 table (one search per CU) and four for a compact
-    // one (two per CU); every wave takes 64 vertices per step and has its own
-    // window of W arcs.  (More waves per search are slower where the pending
-    // set is smaller than a step: eight on 2^13, two on 2^11.)
-    static constexpr int NW = HB >= 14 ? (CT ? 4 : 8) : (HB == 13 ? 4 : (HB == 12 ? 2 : 1));
+    // eight for a wide 2^14 table (one search per CU) and three for a compact
+    // one (two searches per CU fit the LDS); every wave takes 64 vertices per
+    // step and has its own window of W arcs.  (More waves per search are
+    // slower where the pending set is smaller than a step: eight on 2^13, two
+    // on 2^11.)
+    static constexpr int NW = HB >= 14 ? (CT ? 3 : 8) : (HB == 13 ? 4 : (HB == 12 ? 2 : 1));
     static constexpr int G = 1;
     static constexpr uint32_t W = kWin * G;
 };
@@ -218,14 +219,15 @@ static_assert(kCompactVertices == (1 << 24), "compact tables hash 24-bit local i
 template <int HB>
 struct Compact {
     static constexpr uint32_t IDB = 24u - HB;                 // remainder bits
-    static constexpr uint32_t DB = 3u;                        // probe distance bits (at most 7)
+    static constexpr uint32_t DB = compact_disp_bits(HB);     // probe distance bits
     static constexpr uint32_t SH = IDB + DB;                  // position of the distance word
     static constexpr uint32_t REM = (1u << IDB) - 1u;
     static constexpr uint32_t IDM = (1u << SH) - 1u;          // identity: probe distance and remainder
     static constexpr uint32_t PEND = 1u << SH;                // the pending bit
     static constexpr uint32_t MAXP = (1u << DB) - 1u;         // longest probe distance
     // largest distance: its word stays below kNoKey and kWordNone
-    static constexpr uint32_t MAXD = (1u << (HB + 4)) - 2u;
+    static constexpr uint32_t MAXD = compact_max_dist(HB);
+    static_assert(((((MAXD << 1) | 1u) << SH) | IDM) < kNoKey, "a compact word never equals kNoKey");
 };
 
 __device__ __forceinline__ uint32_t hash24(uint32_t y) { return (y * kHash24) & 0xFFFFFFu; }
@@ -1124,17 +1126,19 @@ __device__ void search_source_block(SearchLds<HB, CT> &L, BlockRing &B, const Jo
     }
     const bool ovf = B.ovf != 0;
 
-    // ---- emit table entries in S (each wave a slice of the table, staged in
-    // its slice of the ring, free once the search has ended; the window areas
-    // take the sink writes), and clear the table for the next source
+    // ---- emit table entries in S (the waves take the table's chunks of 64 U
+    // slots in turn, staged in each wave's slice of the ring, free once the
+    // search has ended; the window areas take the sink writes), and clear the
+    // table for the next source
     const uint32_t bound = current_bound(c);
     constexpr uint32_t SC = RC / NW;   // staging entries per wave
+    static_assert(SC >= 128, "a wave's staging slice holds a flush threshold plus a chunk row");
+    static_assert(H % (64 * U) == 0, "the table is a whole number of chunks");
     uint2 *stg = q + wv * SC;
     uint32_t nst = 0, emitted = 0;
     unsigned long long warcs = 0;
     uint32_t wsettled = 0;
-    constexpr uint32_t SL = static_cast<uint32_t>(H / NW);
-    for (uint32_t g0 = wv * SL; g0 < (wv + 1) * SL; g0 += 64 * U) {
+    for (uint32_t g0 = wv * 64u * U; g0 < static_cast<uint32_t>(H); g0 += NW * 64u * U) {
         uint32_t k[U], d[U];
         bool occ[U], sb[U];
 #pragma unroll
@@ -2213,15 +2217,16 @@ hipError_t launch_stage(const CallBuffers &b, unsigned long long max_elems, cons
 
 int join_tier_supported(int hash_log2) { return hash_log2 >= kMinHB && hash_log2 <= kMaxHB; }
 
-uint32_t compact_max_dist(int hash_log2) { return (1u << (hash_log2 + 4)) - 2u; }
 
 hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, bool compact, uint32_t max_sources,
                        bool persistent, hipStream_t s) {
 #define RN_TIER(HB)                                                                                   \
     case HB:                                                                                          \
-        if (compact)                                                                                  \
-            return generic ? launch_join_tier<HB, true, true>(a, max_sources, persistent, s)          \
-                           : launch_join_tier<HB, false, true>(a, max_sources, persistent, s);        \
+        if constexpr (HB >= kCompactMinHB) {                                                          \
+            if (compact)                                                                              \
+                return generic ? launch_join_tier<HB, true, true>(a, max_sources, persistent, s)      \
+                               : launch_join_tier<HB, false, true>(a, max_sources, persistent, s);    \
+        }                                                                                             \
         return generic ? launch_join_tier<HB, true, false>(a, max_sources, persistent, s)             \
                        : launch_join_tier<HB, false, false>(a, max_sources, persistent, s);
     switch (hash_log2) {

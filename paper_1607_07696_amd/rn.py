@@ -27,6 +27,7 @@ EXPORTS = (
     "rn_graph_load_many", "rn_graph_count", "rn_graph_size", "rn_join_batch", "rn_autotune",
     "rn_plan_create", "rn_plan_run", "rn_plan_free",
     "rn_server_create", "rn_server_submit", "rn_server_wait", "rn_server_get_stats", "rn_server_free",
+    "rn_objects_graph",
 )
 RN_DELTA_DEFAULT = 0xFFFFFFFF
 RN_QUERY_FORWARD = 1
@@ -119,13 +120,15 @@ def load_library(path: str = LIB_PATH):
     lib.rn_server_get_stats.argtypes = [vp, C.POINTER(ServerStats)]
     lib.rn_server_free.argtypes = [vp]
     lib.rn_server_free.restype = None
+    lib.rn_objects_graph.argtypes = [vp, C.c_int32, i32p, u32p, C.c_int32, C.POINTER(vp)]
     lib.rn_last_error.restype = C.c_char_p
     lib.rn_version.restype = C.c_char_p
     for name in ("rn_graph_load", "rn_graph_num_vertices", "rn_partition_host", "rn_partition", "rn_graph_renumbered",
                  "rn_dist_join", "rn_kcp_join", "rn_set_tuning", "rn_get_tuning",
                  "rn_set_profiling", "rn_last_stats", "rn_graph_load_many", "rn_graph_count",
                  "rn_graph_size", "rn_join_batch", "rn_autotune", "rn_plan_create", "rn_plan_run",
-                 "rn_server_create", "rn_server_submit", "rn_server_wait", "rn_server_get_stats"):
+                 "rn_server_create", "rn_server_submit", "rn_server_wait", "rn_server_get_stats",
+                 "rn_objects_graph"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
@@ -199,6 +202,22 @@ class RoadNetwork:
         self = cls.__new__(cls)
         self._load([(g.row_ptr, g.col, g.w) for g in graphs])
         return self
+
+    def with_objects(self, arcs, offsets, graph: int = 0) -> "RoadNetwork":
+        """A new handle: graph `graph` with object i (on arc arcs[i], at
+        offsets[i] from its tail) inserted as vertex V + i (rn_objects_graph)."""
+        lib = load_library()
+        a, ap = _host(arcs, np.int32)
+        o, op = _host(offsets, np.uint32)
+        h = C.c_void_p()
+        _check(lib.rn_objects_graph(self._h, int(graph), ap, op, int(a.shape[0]), C.byref(h)))
+        V, A = C.c_int32(), C.c_int64()
+        _check(lib.rn_graph_size(h, 0, C.byref(V), C.byref(A)))
+        net = RoadNetwork.__new__(RoadNetwork)
+        net._h, net._out, net._bout = h, None, None
+        net.sizes = [(int(V.value), int(A.value))]
+        net.V, net.A = int(V.value), int(A.value)
+        return net
 
     @property
     def num_graphs(self) -> int:
