@@ -385,6 +385,27 @@ rn_status rn_server_get_stats(rn_server *s, rn_server_stats *out);
 /* Finish every submitted request, stop the server and free it (NULL accepted). */
 void rn_server_free(rn_server *s);
 
+/*
+ * rn_dist_join_noalloc -- rn_dist_join for callers that cannot allocate
+ * device memory (code under stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, results and errors as
+ * rn_dist_join, but every device buffer of the call (call state, staging,
+ * source lists, record buffers and, when a search needs them, global-tier
+ * slots) is carved out of one static device array of
+ * RN_NOALLOC_SCRATCH_BYTES per GPU, held by the library from its first use
+ * on that GPU until the process ends; nothing is allocated per call.  Limits:
+ * the call's records must fit that array (RN_ERR_NOMEM otherwise, with a
+ * message giving both counts: about 4 million records), and a search that
+ * outgrows every on-chip table runs with at most 8 global-tier slots, or fails
+ * with RN_ERR_NOMEM when one slot does not fit.  Every call on a GPU uses that
+ * GPU's array: calls that overlap on one GPU (from several threads or
+ * streams) race and must not be issued.  The call waits for its work before
+ * returning, as rn_dist_join does.
+ */
+#define RN_NOALLOC_SCRATCH_BYTES (128u << 20)
+rn_status rn_dist_join_noalloc(rn_graph *g, const int32_t *R, int32_t nR, const int32_t *S, int32_t nS,
+                               uint32_t theta, rn_pair *out, int64_t cap, int64_t *n_out, void *stream);
+
 /* Per-call statistics of the most recent join on a handle. */
 typedef struct rn_stats {
     float stage_ms;      /* validation and source staging kernels */

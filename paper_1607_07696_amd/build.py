@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 LIB = os.path.join(HERE, "librn.so")
-SOURCES = ["rn_api.cpp", "rn_kernels.hip", "rn_partition.cpp", "rn_server.cpp"]
+SOURCES = ["rn_api.cpp", "rn_kernels.hip", "rn_partition.cpp", "rn_server.cpp", "rn_noalloc.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

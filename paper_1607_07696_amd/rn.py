@@ -27,7 +27,7 @@ EXPORTS = (
     "rn_graph_load_many", "rn_graph_count", "rn_graph_size", "rn_join_batch", "rn_autotune",
     "rn_plan_create", "rn_plan_run", "rn_plan_free",
     "rn_server_create", "rn_server_submit", "rn_server_wait", "rn_server_get_stats", "rn_server_free",
-    "rn_objects_graph",
+    "rn_objects_graph", "rn_dist_join_noalloc",
 )
 RN_DELTA_DEFAULT = 0xFFFFFFFF
 RN_QUERY_FORWARD = 1
@@ -99,6 +99,7 @@ def load_library(path: str = LIB_PATH):
     lib.rn_graph_renumbered.argtypes = [vp, C.c_int32]
     lib.rn_dist_join.argtypes = [vp, vp, C.c_int32, vp, C.c_int32, C.c_uint32, vp, C.c_int64, i64p, vp]
     lib.rn_kcp_join.argtypes = [vp, vp, C.c_int32, vp, C.c_int32, C.c_int32, vp, C.c_int64, i64p, vp]
+    lib.rn_dist_join_noalloc.argtypes = [vp, vp, C.c_int32, vp, C.c_int32, C.c_uint32, vp, C.c_int64, i64p, vp]
     lib.rn_set_tuning.argtypes = [vp, C.c_int64, C.c_int32]
     lib.rn_get_tuning.argtypes = [vp, u32p, i32p]
     lib.rn_set_profiling.argtypes = [vp, C.c_int32]
@@ -128,7 +129,7 @@ def load_library(path: str = LIB_PATH):
                  "rn_set_profiling", "rn_last_stats", "rn_graph_load_many", "rn_graph_count",
                  "rn_graph_size", "rn_join_batch", "rn_autotune", "rn_plan_create", "rn_plan_run",
                  "rn_server_create", "rn_server_submit", "rn_server_wait", "rn_server_get_stats",
-                 "rn_objects_graph"):
+                 "rn_objects_graph", "rn_dist_join_noalloc"):
         getattr(lib, name).restype = C.c_int32
     _lib = lib
     return lib
