@@ -401,9 +401,7 @@ def partition_study(torch, rn, g, R, S, theta, arcs, steps):
     id order (no partition).  Results never depend on it (tested)."""
     Rd = torch.as_tensor(R, device="cuda")
     Sd = torch.as_tensor(S, device="cuda")
-    # (alpha = 0 leaves the two clusters of a bisection unbalanced, so the
-    # recursion runs deep: about 100 s on this graph against 5 s for alpha > 0)
-    alphas = tuple(float(x) for x in os.environ.get("RN_STUDY_ALPHAS", "0.25,0.5,0.75,1").split(","))
+    alphas = tuple(float(x) for x in os.environ.get("RN_STUDY_ALPHAS", "0,0.25,0.5,0.75,1").split(","))
     settings = [("none", None, None)] + [(f"{a:g},{leaf}", a, leaf) for leaf in (64, 256, 1024)
                                          for a in alphas]
     rows = []

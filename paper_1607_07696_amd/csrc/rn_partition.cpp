@@ -32,9 +32,13 @@
 #include "rn_partition.h"
 
 #include <algorithm>
+#include <atomic>
+#include <condition_variable>
 #include <cstdint>
+#include <mutex>
 #include <new>
 #include <queue>
+#include <thread>
 #include <utility>
 
 namespace rn {
@@ -91,7 +95,9 @@ class Partitioner {
     }
 
     // Farthest vertex (weighted, inside the stamped part) from s; ties to lowest id.
-    int32_t farthest(int32_t s, uint32_t st) {
+    // Parts being split at once are disjoint, so the per-vertex arrays are
+    // shared by the worker threads; `touched` is the caller's own.
+    int32_t farthest(int32_t s, uint32_t st, std::vector<int32_t> &touched_) {
         using P = std::pair<uint64_t, int32_t>;
         std::priority_queue<P, std::vector<P>, std::greater<P>> pq;
         touched_.clear();
@@ -123,6 +129,47 @@ class Partitioner {
         return best;
     }
 
+    // Stamp the part perm[b, e) with st and, if it is not connected (arcs
+    // read as undirected edges), reorder it as its connected pieces, ordered
+    // by their lowest vertex id, and return their ranges (true).  A connected
+    // part returns false, stamped, for bisect.
+    bool split_components(std::vector<int32_t> &perm, size_t b, size_t e, uint32_t st, std::vector<int32_t> &tmp,
+                          std::vector<std::pair<size_t, size_t>> &ranges) {
+        for (size_t i = b; i < e; ++i) {
+            stamp_[perm[i]] = st;
+            cl_[perm[i]] = 0;
+        }
+        // breadth-first pieces from the lowest unvisited id; cl_ marks visited vertices
+        std::sort(perm.begin() + static_cast<std::ptrdiff_t>(b), perm.begin() + static_cast<std::ptrdiff_t>(e));
+        tmp.clear();
+        std::vector<size_t> starts;
+        for (size_t i = b; i < e; ++i) {
+            const int32_t s0 = perm[i];
+            if (cl_[s0] != 0) continue;
+            starts.push_back(tmp.size());
+            cl_[s0] = 1;
+            size_t head = tmp.size();
+            tmp.push_back(s0);
+            while (head < tmp.size()) {
+                const int32_t x = tmp[head++];
+                for (int64_t a = g_.off[x]; a < g_.off[x + 1]; ++a) {
+                    const int32_t y = g_.adj[a];
+                    if (stamp_[y] == st && cl_[y] == 0) {
+                        cl_[y] = 1;
+                        tmp.push_back(y);
+                    }
+                }
+            }
+            if (starts.size() == 1 && tmp.size() == e - b) break;   // connected
+        }
+        for (size_t i = b; i < e; ++i) cl_[perm[i]] = 0;
+        if (starts.size() <= 1) return false;
+        std::copy(tmp.begin(), tmp.end(), perm.begin() + static_cast<std::ptrdiff_t>(b));
+        for (size_t c = 0; c < starts.size(); ++c)
+            ranges.emplace_back(b + starts[c], b + (c + 1 < starts.size() ? starts[c + 1] : tmp.size()));
+        return true;
+    }
+
     void push_edges(MinHeap &h, int32_t x, uint32_t st) {
         for (int64_t e = g_.off[x]; e < g_.off[x + 1]; ++e) {
             const int32_t y = g_.adj[e];
@@ -131,11 +178,14 @@ class Partitioner {
     }
 
     // Algorithm 1 on the part perm[b, e): sets cl_ to 1 (left), 2 (right) or 0.
-    void bisect(const std::vector<int32_t> &perm, size_t b, size_t e, uint32_t st, float alpha) {
+    // A cluster holding `cap` vertices stops growing (the other one, or a third
+    // child of what neither reaches, takes the rest).
+    void bisect(const std::vector<int32_t> &perm, size_t b, size_t e, uint32_t st, float alpha, size_t cap,
+                std::vector<int32_t> &touched) {
         int32_t lowest = perm[b];
         for (size_t i = b; i < e; ++i) lowest = std::min(lowest, perm[i]);
-        const int32_t sa = farthest(lowest, st);
-        int32_t sb = farthest(sa, st);
+        const int32_t sa = farthest(lowest, st, touched);
+        int32_t sb = farthest(sa, st, touched);
         if (sb == sa) {  // seed component is a single vertex: take any other vertex
             sb = perm[b] != sa ? perm[b] : perm[b + 1];
         }
@@ -147,11 +197,14 @@ class Partitioner {
         push_edges(L, sa, st);
         push_edges(R, sb, st);
         const double al = alpha;
-        while (!L.empty() || !R.empty()) {
+        const double capd = static_cast<double>(cap);
+        while (true) {
+            const bool lok = !L.empty() && n1 < capd, rok = !R.empty() && n2 < capd;
+            if (!lok && !rok) break;
             bool left;
-            if (R.empty()) {
+            if (!rok) {
                 left = true;
-            } else if (L.empty()) {
+            } else if (!lok) {
                 left = false;
             } else {
                 const double w1 = n1 / (n1 + al * n2) * static_cast<double>(L.top().w);
@@ -168,48 +221,118 @@ class Partitioner {
         }
     }
 
+    // The recursion: parts are split by several host threads at once (a
+    // part's split depends only on its own vertices, so the result does not
+    // depend on the schedule); leaves are numbered afterwards by a
+    // left-to-right walk of the tree.
     void run(float alpha, int32_t max_leaf, std::vector<int32_t> &part, std::vector<int32_t> &order) {
+        struct Node {
+            size_t b, e;
+            int32_t first;      // first child (children are consecutive), -1 for a leaf
+            int32_t nchild;
+        };
         std::vector<int32_t> perm(static_cast<size_t>(V_));
         for (int32_t i = 0; i < V_; ++i) perm[i] = i;
-        std::vector<int32_t> tmp;
-        std::vector<std::pair<size_t, size_t>> stack;
-        stack.push_back({0, perm.size()});
-        uint32_t next_stamp = 1;
-        int32_t leaf = 0;
+        std::vector<Node> nodes;
+        // every split makes at least two non-empty children, so a tree over V
+        // vertices has fewer than 2V nodes: reserved once, never reallocated
+        // while workers read it
+        nodes.reserve(static_cast<size_t>(V_) * 2 + 2);
+        nodes.push_back(Node{0, perm.size(), -1, 0});
+        std::mutex mu;
+        std::condition_variable cv;
+        std::vector<int32_t> todo{0};
+        size_t busy = 0;
+        std::atomic<uint32_t> next_stamp{1};
+        bool failed = false;
+        auto worker = [&]() {
+            std::vector<int32_t> tmp, touched;
+            try {
+                while (true) {
+                    int32_t id;
+                    size_t b, e;
+                    {
+                        std::unique_lock<std::mutex> lk(mu);
+                        cv.wait(lk, [&] { return !todo.empty() || busy == 0 || failed; });
+                        if (todo.empty() || failed) return;
+                        id = todo.back();
+                        todo.pop_back();
+                        ++busy;
+                        b = nodes[static_cast<size_t>(id)].b;
+                        e = nodes[static_cast<size_t>(id)].e;
+                    }
+                    std::vector<std::pair<size_t, size_t>> ranges;
+                    if (e - b <= static_cast<size_t>(max_leaf) || e - b < 2) {
+                        std::sort(perm.begin() + static_cast<std::ptrdiff_t>(b),
+                                  perm.begin() + static_cast<std::ptrdiff_t>(e));
+                    } else if (const uint32_t st = next_stamp++; split_components(perm, b, e, st, tmp, ranges)) {
+                        // a disconnected part: its connected pieces are its children
+                    } else {
+                        // parts of more than two leaves: neither cluster takes more
+                        // than 3/4 of the part, which bounds the depth of the
+                        // recursion (with alpha = 0 nothing evens the clusters out,
+                        // and lopsided splits peel a few vertices off a large part
+                        // level after level)
+                        const size_t n = e - b;
+                        const size_t ml = static_cast<size_t>(max_leaf);
+                        const size_t cap = n > ml + ml / 4 + 1 ? (3 * n + 3) / 4 : n;
+                        bisect(perm, b, e, st, alpha, cap, touched);
+                        tmp.clear();
+                        for (int c : {1, 2, 0})
+                            for (size_t i = b; i < e; ++i)
+                                if (cl_[perm[i]] == c) tmp.push_back(perm[i]);
+                        size_t n1 = 0, n2 = 0;
+                        for (size_t i = b; i < e; ++i) {
+                            n1 += cl_[perm[i]] == 1;
+                            n2 += cl_[perm[i]] == 2;
+                        }
+                        std::copy(tmp.begin(), tmp.end(), perm.begin() + static_cast<std::ptrdiff_t>(b));
+                        const size_t m1 = b + n1, m2 = m1 + n2;
+                        const size_t cut[4] = {b, m1, m2, e};
+                        for (int c = 0; c < 3; ++c)
+                            if (cut[c + 1] > cut[c]) ranges.emplace_back(cut[c], cut[c + 1]);
+                    }
+                    std::lock_guard<std::mutex> lk(mu);
+                    Node &nd = nodes[static_cast<size_t>(id)];
+                    nd.first = ranges.empty() ? -1 : static_cast<int32_t>(nodes.size());
+                    nd.nchild = static_cast<int32_t>(ranges.size());
+                    for (const auto &r : ranges) {
+                        todo.push_back(static_cast<int32_t>(nodes.size()));
+                        nodes.push_back(Node{r.first, r.second, -1, 0});
+                    }
+                    --busy;
+                    cv.notify_all();
+                }
+            } catch (...) {
+                std::lock_guard<std::mutex> lk(mu);
+                failed = true;
+                cv.notify_all();
+            }
+        };
+        const unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+        std::vector<std::thread> pool;
+        for (unsigned t = 1; t < nt; ++t) pool.emplace_back(worker);
+        worker();
+        for (auto &t : pool) t.join();
+        if (failed) throw std::bad_alloc();
+        // leaves in a left-to-right walk of the tree
         order.clear();
         order.reserve(static_cast<size_t>(V_));
         part.assign(static_cast<size_t>(V_), 0);
+        int32_t leaf = 0;
+        std::vector<int32_t> stack{0};
         while (!stack.empty()) {
-            auto [b, e] = stack.back();
+            const Node &nd = nodes[static_cast<size_t>(stack.back())];
             stack.pop_back();
-            if (e - b <= static_cast<size_t>(max_leaf) || e - b < 2) {
-                std::sort(perm.begin() + static_cast<std::ptrdiff_t>(b),
-                          perm.begin() + static_cast<std::ptrdiff_t>(e));
-                for (size_t i = b; i < e; ++i) {
+            if (nd.first < 0) {
+                for (size_t i = nd.b; i < nd.e; ++i) {
                     part[perm[i]] = leaf;
                     order.push_back(perm[i]);
                 }
                 ++leaf;
                 continue;
             }
-            const uint32_t st = next_stamp++;
-            for (size_t i = b; i < e; ++i) stamp_[perm[i]] = st;
-            bisect(perm, b, e, st, alpha);
-            tmp.clear();
-            for (int c : {1, 2, 0})
-                for (size_t i = b; i < e; ++i)
-                    if (cl_[perm[i]] == c) tmp.push_back(perm[i]);
-            size_t n1 = 0, n2 = 0;
-            for (size_t i = b; i < e; ++i) {
-                n1 += cl_[perm[i]] == 1;
-                n2 += cl_[perm[i]] == 2;
-            }
-            std::copy(tmp.begin(), tmp.end(), perm.begin() + static_cast<std::ptrdiff_t>(b));
-            const size_t m1 = b + n1, m2 = m1 + n2;
-            // push in reverse so the left child is processed (and numbered) first
-            if (m2 < e) stack.push_back({m2, e});
-            stack.push_back({m1, m2});
-            stack.push_back({b, m1});
+            for (int32_t c = nd.nchild - 1; c >= 0; --c) stack.push_back(nd.first + c);
         }
     }
 
@@ -219,7 +342,6 @@ class Partitioner {
     std::vector<uint32_t> stamp_;
     std::vector<uint8_t> cl_;
     std::vector<uint64_t> dist_;
-    std::vector<int32_t> touched_;
 };
 
 }  // namespace
