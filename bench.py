@@ -235,7 +235,7 @@ def batch_leg(torch, rn, steps):
 SERVE_ORACLE_SAMPLE = (1, 8, 9, 10, 11, 12, 14, 16)   # light requests the oracle answers in about a second
 
 
-def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8, budget_mib=256):
+def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8, budget_mib=32):
     """Poisson streams of joins on the resident 2048x2048 graph through the
     request server (continuous batching), against the same requests served
     one at a time, in arrival order, by the single-query calls (a measured
@@ -255,7 +255,7 @@ def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8, budget
     log(f"serve: graph V={g.V} A={g.A}, {count} requests")
     net = rn.RoadNetwork.from_graph(g)
     theta_of = [r.theta if r.k == 0 else MAX for r in reqs]
-    srv_cfg = dict(lanes=2, max_batch=8, global_slots=128, hbm_budget=16 << 30)
+    srv_cfg = dict(lanes=2, max_batch=8, global_slots=128, hbm_budget=16 << 30, heavy_lane=True)
     pct = lambda a, q: round(float(np.percentile(a, q)), 3)
     digest = lambda a: hashlib.blake2b(np.ascontiguousarray(a).tobytes(), digest_size=16).digest()
 
@@ -365,6 +365,14 @@ def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8, budget
             "plain_fifo": {"latency_ms": {"p50": pct(plat, 50), "p99": pct(plat, 99), "max": pct(plat, 100)},
                            "throughput_rps": round(count / pspan, 1), "makespan_s": round(pspan, 3),
                            "gteps": round(arcs / pspan / 1e9, 3), "measured": True}}
+    # the headline rate again with every lane taking requests in arrival order
+    # (no lane set aside for heavy requests)
+    rate = headline * capacity
+    log(f"serve: Poisson stream at {headline:g} C, all lanes in arrival order")
+    lat, makespan, st, _, _, digs, _ = run_server(1.0 / rate, heavy_lane=False)
+    fifo_lanes = {"rate_rps": round(rate, 1),
+                  "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "max": pct(lat, 100)},
+                  "throughput_rps": round(count / makespan, 1), "matches_plain": matches(digs), "stats": st}
     # the headline rate again with an HBM budget small enough to bind:
     # admission then waits for memory, not only for a free lane
     rate = headline * capacity
@@ -376,7 +384,7 @@ def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8, budget
     net.close()
     head = streams[f"{headline:g}C"]
     ok = matches(cap_digs) == count and all(s["server"]["matches_plain"] == count for s in streams.values()) \
-        and budget_stream["matches_plain"] == count
+        and budget_stream["matches_plain"] == count and fifo_lanes["matches_plain"] == count
     if not ok:
         log("ERROR: a served result differs from the same request's single-query result")
     return {"workload": (f"{count} requests on the 2048x2048 road graph (seed 0): 60% theta-joins with theta "
@@ -384,14 +392,14 @@ def serve_leg(torch, rn, count=2000, loads=(0.5, 0.8, 1.2), headline=0.8, budget
                          "log-uniform in [64, 32768]; Poisson arrivals (seed 5) at fractions of the server's "
                          f"measured capacity, headline {headline:g} C"),
             "V": g.V, "A": g.A, "pairs": int(npairs), "work_arcs": arcs,
-            "config": {"lanes": 2, "max_batch": 8, "global_slots": 128, "hbm_budget_gib": 16},
+            "config": {"lanes": 2, "max_batch": 8, "global_slots": 128, "hbm_budget_gib": 16, "heavy_lane": True},
             "capacity_rps": round(capacity, 1), "capacity_gteps": round(arcs / cap_span / 1e9, 3),
             "capacity_stats": cap_st,
             "plain_service_ms": {"p50": pct(np.array(service) * 1e3, 50), "p99": pct(np.array(service) * 1e3, 99),
                                  "total_s": round(float(np.sum(service)), 3)},
             "results_match_plain": bool(ok), "matches_plain_capacity_run": matches(cap_digs),
             "headline": f"{headline:g}C", "server": head["server"], "plain_fifo": head["plain_fifo"],
-            "streams": streams, "budget_stream": budget_stream,
+            "streams": streams, "budget_stream": budget_stream, "arrival_order_lanes": fifo_lanes,
             "_sample": {i: sample[i] for i in sorted(sample)}, "_reqs": reqs, "_graph": g}
 
 

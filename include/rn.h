@@ -318,7 +318,9 @@ void rn_plan_free(rn_plan *p);
  *
  * A server keeps one graph of a handle resident and answers join requests
  * as they arrive.  A host thread of the library admits waiting requests, in
- * arrival order, into free lanes whenever the estimated device footprint of
+ * arrival order (with heavy_lane: in arrival order within the heavy and the
+ * light requests, heavy ones one at a time, on the last lane first), into free lanes
+ * whenever the estimated device footprint of
  * the requests in flight stays within hbm_budget (one request is admitted
  * whenever nothing is in flight, however large), and runs each lane's
  * requests as one batch (the launch sequence of rn_join_batch) on the lane's
@@ -326,9 +328,9 @@ void rn_plan_free(rn_plan *p);
  * device are admitted as lanes and budget free up, and their work overlaps
  * with the batches already running.  The budget covers what requests add
  * while in flight (their ids, records and output, estimated); the buffers
- * each lane keeps between batches, among them the global-tier search slots
- * it allocates when a search first needs them (global_slots slots of about
- * 25 bytes per vertex each), are outside it and are reported in
+ * each lane keeps between batches, among them its global-tier search slots
+ * (global_slots slots of 24 bytes per vertex each, allocated when the
+ * server starts), are outside it and are reported in
  * rn_server_stats.device_bytes.  Each request's result is exactly the
  * result of the same query run alone.  The server holds the handle for its
  * lifetime: other calls on it return RN_ERR_BUSY until rn_server_free.
@@ -341,6 +343,11 @@ typedef struct rn_server_config {
     int32_t max_batch;      /* most requests in one batch, 1..65536 */
     int32_t global_slots;   /* global-tier searches each lane runs at once, 1..256 */
     int64_t hbm_budget;     /* bytes of estimated device footprint in flight, > 0 */
+    int32_t heavy_lane;     /* 1 (with lanes >= 2): requests of large estimated search work run one
+                               at a time on the last lane, the other lanes take the rest (and the
+                               first heavy request while the last lane is busy and no light request
+                               waits); 0: every lane takes requests in arrival order */
+    int32_t reserved;
 } rn_server_config;
 
 typedef struct rn_server_stats {
@@ -353,7 +360,7 @@ typedef struct rn_server_stats {
     int32_t max_in_flight;  /* most requests in flight at once */
     int32_t max_lanes_busy; /* most lanes busy at once */
     int32_t max_batch_seen; /* largest batch launched */
-    int32_t reserved;
+    int32_t budget_waits;   /* requests held back at least once because they did not fit the budget */
 } rn_server_stats;
 
 /* Start a server on graph cfg->graph of g (device work runs on lane streams

@@ -207,6 +207,16 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         p.nbins = ok ? static_cast<uint32_t>(nb) : 0u;
         if (ok) p.binbase[nq] = p.nbins;
     }
+    // the small sort: k-closest-pairs queries only, few candidates expected
+    {
+        bool all_kcp = nq > 0;
+        uint64_t ksum = 0;
+        for (int32_t i = 0; i < nq; ++i) {
+            all_kcp = all_kcp && q[i].k > 0;
+            ksum += static_cast<uint64_t>(std::max(q[i].k, 0));
+        }
+        p.small_sort = all_kcp && ksum <= kSmallSort / 2;
+    }
     p.qb = nq > 1 ? bitlen(static_cast<uint64_t>(nq - 1)) : 0u;
     p.vb = std::max<uint32_t>(1u, bitlen(static_cast<uint64_t>(std::max(g->Vmax - 1, 0))));
     p.max_passes = std::max<uint32_t>(1u, (p.qb + std::max<uint32_t>(bitlen(dmax), 1u) + 2u * p.vb + 7u) / 8u);
@@ -215,12 +225,14 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
     p.off_sbits = round_up(p.off_qs + static_cast<size_t>(nq) * (sizeof(QueryState) / 4), 64);
     p.off_rbits = round_up(p.off_sbits + sw, 64);
     p.off_hists = round_up(p.off_rbits + rw, 64);
-    p.off_bins = round_up(p.off_hists + static_cast<size_t>(nkcp) * kHistWords, 64);
+    p.off_work = round_up(p.off_hists + static_cast<size_t>(nkcp) * kHistWords, 64);   // one 256-byte line
+    p.off_bins = p.off_work + 64;
     p.off_sort = round_up(p.off_bins + (p.nbins ? bucket_words(p.nbins) : 0), 64);
     p.block_words = p.off_sort + sort_hist_words();
     // the pass-0 histogram is written whole and the digit totals before use;
     // the histograms later passes accumulate start at zero; the bucket sort
-    // needs only its bin counts cleared
+    // needs only its bin counts cleared (either way the clearing covers the
+    // call state, histograms and the global tier's counter before them)
     p.zero_words = p.nbins ? p.off_bins + p.nbins
                            : p.off_sort + static_cast<size_t>(p.max_passes + 1) * 256u * 256u;
     p.off_ebase = round_up(static_cast<size_t>(nq) * sizeof(QueryDesc), 16);
@@ -242,9 +254,7 @@ rn_status ensure_gslots(Workspace &ws, int32_t Vmax, uint32_t want, hipStream_t 
     n = std::max<size_t>(1, std::min<size_t>(n, (size_t{48} << 30) / (4 * words)));
     RN_HIP(dev_alloc(&ws.d_gslots, n * words), "allocating global search slots");
     ws.n_gslots = static_cast<uint32_t>(n);
-    const size_t V = static_cast<size_t>(Vmax);
-    RN_HIP(launch_fill_u32(ws.d_gslots, n * V, kInf, s), "clearing search slots");
-    RN_HIP(launch_fill_u32(ws.d_gslots + n * V, n * V + n * global_bitmap_words(Vmax), 0u, s),
+    RN_HIP(launch_fill_u32(ws.d_gslots, global_clear_words(ws.n_gslots, Vmax), 0xFFFFFFFFu, s),
            "clearing search slots");
     RN_HIP(hipStreamSynchronize(s), "clearing search slots");
     return RN_OK;
@@ -471,6 +481,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         t.sbeg = nullptr;
         t.send = &b.ctl->nlist[2];
         t.tier = 3;
+        t.work = ws.d_block + p.off_work;
         RN_HIP(launch_join_global(t, ws.d_gslots, ws.n_gslots, g->Vmax, maxs, s), "launching the global relaxation");
     }
     record(g, ws, timed, EV_RELAXED, s);
@@ -479,6 +490,8 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     record(g, ws, timed, EV_SELECTED, s);
     if (p.nbins)
         RN_HIP(launch_bucket_sort(b, out, static_cast<unsigned long long>(cap), s), "sorting pairs");
+    else if (p.small_sort)
+        RN_HIP(launch_sort_small(b, p.qb, p.vb, out, static_cast<unsigned long long>(cap), s), "sorting pairs");
     else
         RN_HIP(launch_sort_out(b, p.any_kcp ? 1 : 0, p.max_passes, p.vb, out, static_cast<unsigned long long>(cap), s),
                "sorting pairs");
@@ -487,6 +500,16 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     RN_HIP(launch_publish(reinterpret_cast<const uint32_t *>(ws.d_block), ws.d_state_map,
                           static_cast<uint32_t>(state_bytes / 4), s),
            "publishing the call state");
+    return RN_OK;
+}
+
+rn_status enqueue_sort_fallback(const Workspace &ws, const Prepared &p, rn_pair *out, int64_t cap, hipStream_t s) {
+    const CallBuffers b = call_buffers(ws, p);
+    // the radix sort's histograms start cleared (the bucket scan kept its
+    // chunk map there)
+    RN_HIP(launch_fill_u32(b.sort_hist, static_cast<uint64_t>(p.max_passes + 1) * 256u * 256u, 0u, s),
+           "clearing the sort histograms");
+    RN_HIP(launch_sort_out(b, 1, p.max_passes, p.vb, out, static_cast<unsigned long long>(cap), s), "sorting pairs");
     return RN_OK;
 }
 
@@ -511,10 +534,12 @@ float elapsed(const rn_graph *g, const Workspace &ws, int a, int b) {
     return ms;
 }
 
-// Turn the read-back state into offsets / status / the return code.
-// Returns RN_ERR_NOMEM + sets *regrow when the records outgrew the buffer.
-rn_status finish(rn_graph *g, Workspace &ws, const Prepared &p, int64_t cap, int64_t *offsets, int32_t *status,
-                 bool timed, bool *regrow, hipStream_t s) {
+// Turn the read-back state into offsets / status / the return code (after
+// the radix sort of a bucket-sorted call that found an oversized bin).
+// Sets *regrow when the call must run again (records outgrew the buffer, or
+// a search needed global-tier slots that did not exist yet).
+rn_status finish(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *out, int64_t cap, int64_t *offsets,
+                 int32_t *status, bool timed, bool *regrow, hipStream_t s) {
     const CallCtl &c = *reinterpret_cast<const CallCtl *>(ws.h_state);
     const QueryState *qs = reinterpret_cast<const QueryState *>(ws.h_state + sizeof(CallCtl));
     *regrow = false;
@@ -528,6 +553,10 @@ rn_status finish(rn_graph *g, Workspace &ws, const Prepared &p, int64_t cap, int
         RN_TRY(grow_recs(ws, c.npairs));
     }
     if (*regrow) return RN_OK;
+    if (c.resort) {
+        RN_TRY(enqueue_sort_fallback(ws, p, out, cap, s));
+        RN_HIP(hipStreamSynchronize(s), "waiting for the sort");
+    }
     if (timed) {
         rn_stats &st = g->stats;
         st = rn_stats{};
@@ -576,7 +605,7 @@ rn_status run_eager(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *out,
         RN_TRY(enqueue_call(g, ws, p, out, cap, s, timed));
         RN_TRY(read_back(ws, p, s));
         bool regrow = false;
-        const rn_status st = finish(g, ws, p, cap, offsets, status, timed, &regrow, s);
+        const rn_status st = finish(g, ws, p, out, cap, offsets, status, timed, &regrow, s);
         if (!regrow) return st;
     }
     return fail(RN_ERR_NOMEM, "record buffer did not settle");
@@ -1345,7 +1374,7 @@ rn_status rn_plan_run(rn_plan *pl, int64_t *offsets, int32_t *status, void *stre
     RN_HIP(hipGraphLaunch(pl->exec, s), "launching the graph");
     RN_TRY(read_back(pl->ws, p, s));
     bool regrow = false;
-    const rn_status st = finish(g, pl->ws, p, pl->cap, offsets, status, false, &regrow, s);
+    const rn_status st = finish(g, pl->ws, p, pl->out, pl->cap, offsets, status, false, &regrow, s);
     if (!regrow) return st;
     // the records outgrew the buffer (grown by finish): run eagerly, re-capture
     return plan_build(pl, p, s, offsets, status);

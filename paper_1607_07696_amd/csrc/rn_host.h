@@ -149,12 +149,13 @@ struct Prepared {
     uint64_t total_R = 0;
     unsigned long long total_elems = 0;
     // word offsets in the call block
-    size_t off_qs = 0, off_sbits = 0, off_rbits = 0, off_hists = 0, off_sort = 0, block_words = 0;
+    size_t off_qs = 0, off_sbits = 0, off_rbits = 0, off_hists = 0, off_work = 0, off_sort = 0, block_words = 0;
     size_t zero_words = 0;
     uint32_t sbits_words = 0, rbits_words = 0;
     size_t desc_bytes = 0, off_ebase = 0, off_rbase = 0, off_perm = 0;
     // bucket sort (theta-join calls with few bins); nbins = 0: radix sort
     uint32_t nbins = 0;
+    bool small_sort = false;        // k-closest-pairs calls with few candidates: launch_sort_small
     std::vector<uint32_t> binbase;
     size_t off_bins = 0, off_binbase = 0;
 };
@@ -182,6 +183,11 @@ void fill_host_desc(const Prepared &p, uint8_t *h);
 // source so that other streams' kernels interleave).
 rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *out, int64_t cap, hipStream_t s,
                        bool timed, bool shared = false);
+// After a call whose sort left the output to the radix sort (its state's
+// resort: a bucket-sort bin too large to rank, or too many candidates for the
+// small sort): enqueue on s the radix sort of the records in recs[1], which
+// writes the output.
+rn_status enqueue_sort_fallback(const Workspace &ws, const Prepared &p, rn_pair *out, int64_t cap, hipStream_t s);
 
 }  // namespace host
 }  // namespace rn

@@ -104,7 +104,8 @@ struct CallCtl {
     uint32_t sort_db;           // distance bits of the sort key
     uint32_t sort_passes;       // 8-bit digit passes the sort needs
     uint32_t nchunks;           // bucket sort: 64-record chunks over all bins
-    uint32_t pad;
+    uint32_t resort;            // the call's sort left the output to the radix sort (a bucket-sort bin
+                                //   above kBucketRankMax records, or more than kSmallSort candidates)
 };
 static_assert(sizeof(CallCtl) == 80, "CallCtl is 80 bytes");
 
@@ -156,16 +157,17 @@ struct JoinArgs {
     const int32_t *order;       // global vertex of the device copy -> local id in the caller's numbering
     const uint32_t *first;      // bit a: arc a is the first lightest of the arcs from its tail to its
                                 //   target (parallel arcs give one pair, at that arc's weight)
+    uint32_t *work;             // global tier: counter of sources claimed past the grid (zero at the start)
 };
 
 // State of the global-memory tier: n slots (one per concurrent block), V the
 // largest graph's vertex count, laid out array by array across the slots:
-// dist[n][V] | queue stamp[n][V] | far bitmap[n][ceil(V/32)] | frontier[n][V] |
-// next frontier[n][V] | touched[n][V] | far list[n][V].  Between searches dist
-// is all kInf, every stamp zero and every far bitmap clear (the first three
-// arrays, cleared once at allocation).
-__host__ __device__ inline size_t global_bitmap_words(int32_t V) { return (static_cast<size_t>(V) + 31) / 32; }
-inline size_t global_slot_words(int32_t V) { return 6 * static_cast<size_t>(V) + global_bitmap_words(V); }
+// word[n][V] (64-bit: distance and queue round) | frontier spill[n][V] |
+// second frontier spill[n][V] | touched[n][V] | far list[n][V] (32-bit).
+// Between searches every word is all ones (the first array, filled with ones
+// at allocation: global_clear_words words).
+inline size_t global_slot_words(int32_t V) { return 6 * static_cast<size_t>(V); }
+inline size_t global_clear_words(uint32_t nslots, int32_t V) { return 2 * static_cast<size_t>(nslots) * V; }
 
 // Host-side description of the call buffers the launch sequence uses.
 struct CallBuffers {
@@ -268,9 +270,25 @@ constexpr int32_t kMaxQueries = 65536;
 // to its place, then order each bin by (u, v) by counting the smaller
 // keys of its records, one wave per 64 of them, writing each query's output
 // segment as the radix sort's last pass does.  Work per bin grows with the
-// square of its size, so it is chosen only for graphs with varied weights.
+// square of its size, so it is chosen only for graphs with varied weights,
+// and the ranking is bounded: when some bin holds more than kBucketRankMax
+// records the layout launch sets ctl->resort, the ranking launch returns at
+// once, and the caller sorts the scattered records (grouped by bin in
+// recs[1]) with the radix sort instead (launch_sort_out, selected = 1).
 constexpr uint32_t kMaxBins = 65536;
+constexpr uint32_t kBucketRankMax = 4096;
 inline size_t bucket_words(uint32_t nbins) { return 4 * static_cast<size_t>(nbins) + 1; }
 hipError_t launch_bucket_sort(const CallBuffers &b, rn_pair *out, unsigned long long user_cap, hipStream_t s);
+
+// Small sort, for calls of k-closest-pairs queries only whose k add up to at
+// most kSmallSort / 2: one block sorts the selected records (recs[1]) in LDS
+// as 64-bit (query, dist, u, v) keys (query bits qb, vertex bits vb, distance
+// bits from the device) and writes the output as the radix sort's last pass
+// does; one launch instead of the radix sort's two per digit.  More than
+// kSmallSort records (ties at the bound) or a key wider than 63 bits set
+// ctl->resort, and the caller runs the radix sort.
+constexpr uint32_t kSmallSort = 4096;
+hipError_t launch_sort_small(const CallBuffers &b, uint32_t qb, uint32_t vb, rn_pair *out, unsigned long long user_cap,
+                             hipStream_t s);
 
 }  // namespace rn

@@ -1204,9 +1204,11 @@ __device__ __forceinline__ void launch_range(const JoinArgs &a, uint32_t &b, uin
 // One wavefront per block; the launch's sources split into 8 contiguous
 // chunks, chunk c taken by the blocks with blockIdx % 8 == c so that each XCD
 // (blocks are dealt to the 8 XCDs round-robin) sweeps one region of the
-// source order and keeps its part of the graph in its own L2.  GEN = false:
-// every source belongs to a theta-join, and the k-closest-pairs code is
-// compiled out.
+// source order and keeps its part of the graph in its own L2.  (Claiming
+// sources through atomic counters instead was measured 1.6 times slower:
+// thousands of blocks contend for the counters at a launch's start and end.)
+// GEN = false: every source belongs to a theta-join, and the k-closest-pairs
+// code is compiled out.
 template <int HB, bool GEN, bool CT>
 __global__ __launch_bounds__((64 * Tier<HB, CT>::NW)) void k_join(JoinArgs a) {
     __shared__ SearchLds<HB, CT> L;
@@ -1267,29 +1269,56 @@ __global__ __launch_bounds__((64 * Tier<HB, CT>::NW)) void k_join(JoinArgs a) {
 
 // ------------------------------------------------------------------ global-memory tier
 // A search that outgrows every on-chip table runs here: one 1024-thread block
-// per source, its state in a dense per-slot area indexed by the local id.
+// per source, its distances in a dense per-slot array indexed by the local id.
 // Distances are settled bucket by bucket (near-far delta-stepping with the
 // query's gdelta): a round expands the near frontier (tentative distance below
 // the bucket's end), improved vertices join the next near frontier or the far
 // list; when no near vertex is left, the bucket end moves past the smallest
 // far distance and the far list is split.  Without buckets, a frontier-
 // synchronous search on a large road graph improves each vertex dozens of
-// times; with them, close to once.  Each round's arcs are flattened into
-// windows of kGWin arcs, kGJ per thread, whose loads and atomics are all
-// issued before any result is used.  A vertex is queued for round r + 1 by
-// raising its stamp to r + 1, so one improved while it is being expanded is
-// queued again without a clearing pass.  Only rare, very large searches (huge
-// balls, expander graphs, unbounded k-closest-pairs searches) take this path.
+// times; with them, close to once.
+//
+// A whole-graph search takes hundreds of rounds (about the graph's diameter
+// in arcs), so a round's latency, not its work, sets the search's time, and
+// the round is built to wait on global memory twice: for the arcs, then for
+// one 64-bit atomicMin per arc.
+//  - Each vertex has one word, (distance << 32) | 1 + the round of its last
+//    improvement; round r's atomicMin with (nd << 32) | (r + 1) lowers the
+//    distance only when nd is strictly smaller (an equal distance leaves the
+//    word alone, since rounds only grow), and its old value tells whether the
+//    vertex was already queued for round r + 1: improved in round r to a
+//    distance below the bucket's end (an improvement in round r at or past the
+//    end went to the far list instead, and a later one below it queues).
+//  - The near frontier lives in LDS (kGF entries per round, the rest spills to
+//    global memory) and carries each vertex's arc range, which the relaxed
+//    arc's record holds, so no row pointer is read on the way.
+//  - A frontier vertex's distance is read while its arcs load, and the bound
+//    (k-closest pairs) while the round's scan runs.
+//  - Far-list membership needs no bitmap: every vertex with a finite distance
+//    at or past the bucket's end is on the far list once, except vertices a
+//    split dropped for lying beyond the bound (k-closest pairs: the bound
+//    falls), whose word the split marks with round 0; so an improvement at or
+//    past the bucket's end appends its vertex only if the vertex had no
+//    distance or carries that mark.  Entries whose vertex later fell below the
+//    bucket's end are dropped at the next split.
+// An empty word is all ones (no distance, no round); rounds count from 1 per
+// search and every word the search changed is reset at its end.
 constexpr uint32_t kGT = 1024;
 constexpr uint32_t kGJ = 4;
 constexpr uint32_t kGWin = kGT * kGJ;
+constexpr uint32_t kGF = 4096;                     // LDS frontier entries per round
+constexpr unsigned long long kGEmpty = ~0ull;
 
-__device__ __forceinline__ uint32_t gload(const uint32_t *p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// A slot's words are only touched by the block that owns the slot, so their
+// loads and atomics are workgroup-scoped (served by the XCD's L2, which
+// performs the atomics).
+__device__ __forceinline__ unsigned long long gload64(const unsigned long long *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ void gstore(uint32_t *p, uint32_t v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ unsigned long long gmin64(unsigned long long *p, unsigned long long v) {
+    return __hip_atomic_fetch_min(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
+__device__ __forceinline__ uint32_t word_dist(unsigned long long w) { return static_cast<uint32_t>(w >> 32); }
 
 // Slot of a block-wide list append: one LDS atomic per wave.
 __device__ __forceinline__ uint32_t block_append(bool want, uint32_t *counter) {
@@ -1318,66 +1347,99 @@ __device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t *ws, ui
     return off + incl - v;
 }
 
+// The LDS frontier of a global-tier search: two rounds' entries (vertex,
+// first arc, arc count), the expansion window of kGWin arcs and the block's
+// counters.
+struct GlobalLds {
+    uint32_t fy[2][kGF];
+    int32_t fb[2][kGF];
+    uint32_t fd[2][kGF];
+    int32_t widx[kGWin];      // window: arc index
+    uint16_t worig[kGWin];    //   and the thread whose vertex it leaves
+    uint32_t dx[kGT];         // distance of each thread's frontier vertex
+    uint32_t ws[kGT / 64];
+    uint32_t nf[2];           // frontier entries of each round parity
+    uint32_t ntouched, bound, probing, nfar, kept, dmin, dnext;
+};
+
+// Append vertex y (global id; arcs [beg, beg + deg)) to frontier parity p
+// when want: LDS entries first, then the spill array.
+__device__ __forceinline__ void frontier_push(GlobalLds &G, uint32_t p, uint32_t *spill, bool want, uint32_t y,
+                                              int32_t beg, uint32_t deg) {
+    const uint32_t i = block_append(want, &G.nf[p]);
+    if (!want) return;
+    if (i < kGF) {
+        G.fy[p][i] = y;
+        G.fb[p][i] = beg;
+        G.fd[p][i] = deg;
+    } else {
+        spill[i - kGF] = y;
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slots, uint32_t nslots,
                                                       int32_t Vmax) {
-    __shared__ int32_t s_widx[kGWin];
-    __shared__ uint32_t s_wd[kGWin];
-    __shared__ uint32_t s_ws[kGT / 64];
-    __shared__ uint32_t s_nf, s_nfn, s_ntouched, s_bound, s_probing, s_nfar, s_kept, s_dmin;
+    __shared__ GlobalLds G;
+    __shared__ uint32_t s_si;
     const uint32_t tid = threadIdx.x, lane = tid & 63u;
     uint32_t sb, n;
     launch_range(a, sb, n);
-    const size_t V = static_cast<size_t>(Vmax), NV = nslots * V, W = global_bitmap_words(Vmax);
+    const size_t V = static_cast<size_t>(Vmax), NV = nslots * V;
     const size_t k = blockIdx.x;
-    uint32_t *dist = slots + k * V;                                 // local ids
-    uint32_t *stamp = slots + NV + k * V;                           // local ids: round a vertex is queued for
-    uint32_t *farbits = slots + 2 * NV + k * W;                     // local ids
-    uint32_t *fa = slots + 2 * NV + nslots * W + k * V;             // global ids
-    uint32_t *fb = fa + NV;
-    uint32_t *touched = fb + NV;                                    // local ids
+    unsigned long long *word = reinterpret_cast<unsigned long long *>(slots) + k * V;   // local ids
+    uint32_t *spill0 = slots + 2 * NV + k * V;                      // global ids
+    uint32_t *spill1 = spill0 + NV;
+    uint32_t *touched = spill1 + NV;                                // local ids
     uint32_t *far = touched + NV;                                   // local ids
-    for (uint32_t i = blockIdx.x; i < n; i += gridDim.x) {
+    // sources: block b takes source b, then claims the next unclaimed one
+    // through the launch's counter (whole-graph searches differ widely in
+    // length, and the grid holds at most one block per slot)
+    for (uint32_t i = blockIdx.x; i < n;) {
         const int32_t u = a.src[sb + i];
         const SrcCtx c = load_ctx(a, a.srcq[sb + i]);
         const uint32_t voff = static_cast<uint32_t>(c.voff);
         if (tid == 0) {
-            gstore(&dist[u - c.voff], 0u);
-            gstore(&stamp[u - c.voff], 1u);
-            fa[0] = static_cast<uint32_t>(u);
+            word[u - c.voff] = 1ull;   // distance 0, queued for round 1
+            G.fy[1][0] = static_cast<uint32_t>(u);
+            G.fb[1][0] = a.row_ptr[c.rpo + u];
+            G.fd[1][0] = static_cast<uint32_t>(a.row_ptr[c.rpo + u + 1] - G.fb[1][0]);
             touched[0] = static_cast<uint32_t>(u - c.voff);
-            s_nf = 1;
-            s_ntouched = 1;
-            s_nfar = 0;
+            G.nf[1] = 1;
+            G.nf[0] = 0;
+            G.ntouched = 1;
+            G.nfar = 0;
+            G.bound = current_bound(c);
         }
         __syncthreads();
-        uint32_t *F = fa, *Fn = fb;
         uint32_t seen = 0, pnew = 0, round = 1;
         const uint32_t gdelta = a.qd[c.q].gdelta;
         uint32_t thr = gdelta;   // end of the current bucket (exclusive)
         bool probing = false;
         while (true) {
-            if (s_nf == 0) {
+            const uint32_t cur = round & 1u, nxt = cur ^ 1u;
+            uint32_t *spill_cur = cur ? spill1 : spill0, *spill_nxt = cur ? spill0 : spill1;
+            if (G.nf[cur] == 0) {
                 // no near vertex left: everything below thr is settled
-                const uint32_t nfar = s_nfar;
+                const uint32_t nfar = G.nfar;
                 if (nfar == 0) break;
                 if (tid == 0) {
-                    s_dmin = kInf;
-                    s_kept = 0;
-                    s_bound = current_bound(c);
+                    G.dmin = kInf;
+                    G.kept = 0;
+                    G.bound = current_bound(c);
                 }
                 __syncthreads();
-                const uint32_t bound = s_bound;
+                const uint32_t bound = G.bound;
                 uint32_t dmin = kInf;
                 for (uint32_t j = tid; j < nfar; j += kGT) {
-                    const uint32_t d = gload(&dist[far[j]]);
+                    const uint32_t d = word_dist(gload64(&word[far[j]]));
                     if (d >= thr && d <= bound) dmin = min(dmin, d);
                 }
                 dmin = wave_min(dmin);
-                if (lane == 0 && dmin != kInf) atomicMin(&s_dmin, dmin);
+                if (lane == 0 && dmin != kInf) atomicMin(&G.dmin, dmin);
                 __syncthreads();
                 const uint32_t told = thr;
-                if (s_dmin != kInf) {
-                    const uint64_t t = (static_cast<uint64_t>(s_dmin) / gdelta + 1ull) * gdelta;
+                if (G.dmin != kInf) {
+                    const uint64_t t = (static_cast<uint64_t>(G.dmin) / gdelta + 1ull) * gdelta;
                     thr = t > kInf ? kInf : static_cast<uint32_t>(t);
                 }
                 // split the far list in place: settled or out of bound -> dropped,
@@ -1386,78 +1448,100 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                     const uint32_t j = cb + tid;
                     const bool valid = j < nfar;
                     const uint32_t yl = valid ? far[j] : 0u;
-                    const uint32_t d = valid ? gload(&dist[yl]) : kInf;
+                    const uint32_t d = valid ? word_dist(gload64(&word[yl])) : kInf;
                     __syncthreads();   // the chunk is read before kept entries overwrite it
                     const bool near = valid && d >= told && d < thr && d <= bound;
                     const bool keep = valid && d >= thr && d <= bound;
-                    if (valid && !keep) atomicAnd(&farbits[yl >> 5], ~(1u << (yl & 31u)));
-                    const uint32_t fi = block_append(near, &s_nf);
-                    if (near) F[fi] = yl + voff;
-                    const uint32_t ki = block_append(keep, &s_kept);
+                    if (valid && d != kInf && d > bound)   // dropped: marked, so that it can join again
+                        word[yl] = static_cast<unsigned long long>(d) << 32;
+                    const uint32_t y = yl + voff;
+                    const int32_t beg = near ? a.row_ptr[c.rpo + y] : 0;
+                    const uint32_t deg = near ? static_cast<uint32_t>(a.row_ptr[c.rpo + y + 1] - beg) : 0u;
+                    frontier_push(G, cur, spill_cur, near, y, beg, deg);
+                    const uint32_t ki = block_append(keep, &G.kept);
                     if (keep) far[ki] = yl;
                     __syncthreads();
                 }
-                if (tid == 0) s_nfar = s_kept;
+                if (tid == 0) G.nfar = G.kept;
                 __syncthreads();
                 continue;
             }
-            // (s_nf is written again only after the round's last barrier; thread 0
-            // writes s_nfn here, which no other thread reads before the barrier below)
-            const uint32_t nf = s_nf;
-            if (tid < 64 && c.hist != nullptr) probe_phase(c, pnew, probing, seen);
+            const uint32_t nf = G.nf[cur];
+            uint32_t nb = 0;
             if (tid == 0) {
-                s_nfn = 0;
-                s_bound = current_bound(c);
-                s_probing = probing ? 1u : 0u;
+                G.nf[nxt] = 0;              // (no thread reads it before the barriers below)
+                nb = current_bound(c);      // used from the first window on
             }
-            __syncthreads();
-            const uint32_t bound = s_bound;
-            const bool probe_on = s_probing != 0;
             for (uint32_t cb = 0; cb < nf; cb += kGT) {
                 const uint32_t t = cb + tid;
                 const bool valid = t < nf;
-                const uint32_t x = valid ? F[t] : 0u;
-                const uint32_t dx = valid ? gload(&dist[x - voff]) : kInf;
-                const int32_t beg = valid ? a.row_ptr[c.rpo + x] : 0;
-                const uint32_t deg =
-                    (valid && dx <= bound) ? static_cast<uint32_t>(a.row_ptr[c.rpo + x + 1] - beg) : 0u;
+                uint32_t y = 0, deg = 0;
+                int32_t beg = 0;
+                if (valid) {
+                    if (t < kGF) {
+                        y = G.fy[cur][t];
+                        beg = G.fb[cur][t];
+                        deg = G.fd[cur][t];
+                    } else {
+                        y = spill_cur[t - kGF];
+                        beg = a.row_ptr[c.rpo + y];
+                        deg = static_cast<uint32_t>(a.row_ptr[c.rpo + y + 1] - beg);
+                    }
+                }
+                // the vertex's current distance, read while the scan and the arcs
+                // proceed (an entry queued earlier may have improved since)
+                const unsigned long long wx = valid ? gload64(&word[y - voff]) : kGEmpty;
                 uint32_t total;
-                const uint32_t excl = block_scan_1024(deg, s_ws, &total);
+                const uint32_t excl = block_scan_1024(deg, G.ws, &total);
                 for (uint32_t wb = 0; wb < total; wb += kGWin) {
                     const uint32_t lo = max(excl, wb), hi = min(excl + deg, wb + kGWin);
                     for (uint32_t p = lo; p < hi; ++p) {
-                        s_widx[p - wb] = beg + static_cast<int32_t>(p - excl);
-                        s_wd[p - wb] = dx;
+                        G.widx[p - wb] = beg + static_cast<int32_t>(p - excl);
+                        G.worig[p - wb] = static_cast<uint16_t>(tid);
                     }
-                    __syncthreads();
+                    __syncthreads();   // window map written
                     const uint32_t cnt = min(kGWin, total - wb);
                     ArcRec r[kGJ];
-                    uint32_t nd[kGJ], old[kGJ];
+                    uint32_t org[kGJ];
 #pragma unroll
                     for (uint32_t j = 0; j < kGJ; ++j) {
                         const uint32_t e = j * kGT + tid;
-                        r[j] = a.arcs[e < cnt ? s_widx[e] : 0];
-                        nd[j] = e < cnt ? sat_add(s_wd[e], r[j].w) : kInf;
+                        r[j] = a.arcs[e < cnt ? G.widx[e] : 0];
+                        org[j] = e < cnt ? G.worig[e] : kGT;
                     }
-                    __syncthreads();   // window map read before the next window rewrites it
+                    // while the arcs load: the frontier distances, the bound
+                    // and (k-closest pairs, every 8th round, wave 0) the
+                    // discovery count go to LDS
+                    if (wb == 0) G.dx[tid] = word_dist(wx);
+                    if (cb == 0 && wb == 0) {
+                        if (tid < 64 && c.hist != nullptr && (round & 7u) == 1u) probe_phase(c, pnew, probing, seen);
+                        if (tid == 0) {
+                            G.bound = nb;
+                            G.probing = probing ? 1u : 0u;
+                        }
+                    }
+                    __syncthreads();   // (the window map may be rewritten after this barrier)
+                    const uint32_t bound = G.bound;
+                    const bool probe_on = G.probing != 0;
+                    uint32_t nd[kGJ];
+#pragma unroll
+                    for (uint32_t j = 0; j < kGJ; ++j) nd[j] = org[j] < kGT ? sat_add(G.dx[org[j]], r[j].w) : kInf;
+                    unsigned long long old[kGJ];
+#pragma unroll
+                    for (uint32_t j = 0; j < kGJ; ++j) {
+                        // (nd < kInf: a word is changed only with a real distance,
+                        // so every changed word is on the touched list)
+                        const uint32_t yl = static_cast<uint32_t>(r[j].y) - voff;
+                        const bool go = nd[j] <= bound && nd[j] < kInf;
+                        old[j] = go ? gmin64(&word[yl], (static_cast<unsigned long long>(nd[j]) << 32) | (round + 1u)) : 0ull;
+                    }
 #pragma unroll
                     for (uint32_t j = 0; j < kGJ; ++j) {
                         const uint32_t yl = static_cast<uint32_t>(r[j].y) - voff;
-                        old[j] = nd[j] <= bound ? atomicMin(&dist[yl], nd[j]) : 0u;
-                    }
-                    uint32_t qs[kGJ], fo[kGJ];
-#pragma unroll
-                    for (uint32_t j = 0; j < kGJ; ++j) {
-                        const uint32_t yl = static_cast<uint32_t>(r[j].y) - voff;
-                        const bool imp = nd[j] < old[j];
-                        qs[j] = imp && nd[j] < thr ? atomicMax(&stamp[yl], round + 1u) : round + 1u;
-                        fo[j] = imp && nd[j] >= thr ? atomicOr(&farbits[yl >> 5], 1u << (yl & 31u)) : ~0u;
-                    }
-#pragma unroll
-                    for (uint32_t j = 0; j < kGJ; ++j) {
-                        const uint32_t yl = static_cast<uint32_t>(r[j].y) - voff;
-                        const bool fresh = nd[j] < old[j] && old[j] == kInf;
-                        const uint32_t ti = block_append(fresh, &s_ntouched);
+                        const uint32_t od = word_dist(old[j]);
+                        const bool imp = nd[j] < od;
+                        const bool fresh = imp && od == kInf;
+                        const uint32_t ti = block_append(fresh, &G.ntouched);
                         if (fresh) {
                             touched[ti] = yl;
                             if (probe_on && ((c.sbits[yl >> 5] >> (yl & 31u)) & 1u)) {
@@ -1465,28 +1549,24 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                                 atomicAdd(probe_count(c), 1u);
                             }
                         }
-                        const bool queue = qs[j] < round + 1u;
-                        const uint32_t fi = block_append(queue, &s_nfn);
-                        if (queue) Fn[fi] = static_cast<uint32_t>(r[j].y);
-                        const bool tofar = ((fo[j] >> (yl & 31u)) & 1u) == 0u;
-                        const uint32_t ri = block_append(tofar, &s_nfar);
+                        const bool queued = static_cast<uint32_t>(old[j]) == round + 1u && od < thr;
+                        const bool queue = imp && nd[j] < thr && !queued;
+                        frontier_push(G, nxt, spill_nxt, queue, static_cast<uint32_t>(r[j].y), r[j].ybeg,
+                                      static_cast<uint32_t>(r[j].yend - r[j].ybeg));
+                        const bool tofar = imp && nd[j] >= thr && (od == kInf || static_cast<uint32_t>(old[j]) == 0u);
+                        const uint32_t ri = block_append(tofar, &G.nfar);
                         if (tofar) far[ri] = yl;
                     }
                 }
             }
-            __syncthreads();
-            if (tid == 0) s_nf = s_nfn;
             ++round;
             __syncthreads();
-            uint32_t *tmp = F;
-            F = Fn;
-            Fn = tmp;
         }
         // emit S members, count work, reset the slot
-        if (tid == 0) s_bound = current_bound(c);
+        if (tid == 0) G.bound = current_bound(c);
         __syncthreads();
-        const uint32_t bound = s_bound;
-        const uint32_t nt = s_ntouched;
+        const uint32_t bound = G.bound;
+        const uint32_t nt = G.ntouched;
         unsigned long long warcs = 0;
         uint32_t wsettled = 0;
         for (uint32_t j0 = 0; j0 < nt; j0 += kGT) {
@@ -1495,9 +1575,8 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
             bool m = false;
             if (j < nt) {
                 yl = touched[j];
-                d = gload(&dist[yl]);
-                gstore(&dist[yl], kInf);
-                gstore(&stamp[yl], 0u);
+                d = word_dist(gload64(&word[yl]));
+                word[yl] = kGEmpty;
                 m = d <= bound && ((c.sbits[yl >> 5] >> (yl & 31u)) & 1u);
                 if (a.count_work && d <= bound) {
                     warcs += static_cast<unsigned long long>(a.row_ptr[c.rpo + yl + voff + 1] -
@@ -1545,7 +1624,10 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
         __syncthreads();
         unsigned long long tseen = 0;
         if (c.k && tid < 64) tighten_bound(c, tseen);
+        if (tid == 0) s_si = gridDim.x + atomicAdd(a.work, 1u);
         __syncthreads();   // the slot is clean before the next source starts
+        i = s_si;
+        __syncthreads();   // every thread has the claim before the next one is written
     }
 }
 
@@ -1795,37 +1877,54 @@ __global__ __launch_bounds__(256) void k_kcp_direct(JoinArgs a) {
 }
 
 // Keep the records within their query's final bound (order is restored by the
-// sort).  Counts are taken per wave: one atomic per run of equal queries.
-__global__ void k_select(CallBuffers b) {
+// sort).  Each block takes a contiguous tile: it counts the records it keeps,
+// reserves their places with one global atomic, then writes them; only
+// k-closest-pairs queries count their kept records (every record of a
+// theta-join is kept, so its count is its emitted count).
+__device__ __forceinline__ bool keep_rec(const CallBuffers &b, const Rec &r) {
+    return b.qd[r.q].k == 0 || r.d <= b.qs[r.q].bound;
+}
+
+__global__ __launch_bounds__(256) void k_select(CallBuffers b) {
+    __shared__ uint32_t s_cnt;
+    __shared__ unsigned long long s_base;
     const unsigned long long n = min(b.ctl->npairs, b.rec_cap);
     const Rec *in = b.recs[0];
     Rec *kept = b.recs[1];
-    const unsigned long long stride = static_cast<unsigned long long>(gridDim.x) * blockDim.x;
-    for (unsigned long long i0 = blockIdx.x * static_cast<unsigned long long>(blockDim.x);
-         i0 < n; i0 += stride) {
+    const unsigned long long per = ((n + gridDim.x - 1) / gridDim.x + 255ull) / 256ull * 256ull;
+    const unsigned long long beg = min(n, blockIdx.x * per), end = min(n, beg + per);
+    if (beg >= end) return;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    uint32_t mine = 0;
+    for (unsigned long long i = beg + threadIdx.x; i < end; i += 256) {
+        const Rec r = in[i];
+        if (!keep_rec(b, r)) continue;
+        ++mine;
+        if (b.qd[r.q].k != 0) atomicAdd(&b.qs[r.q].nsel, 1ull);
+    }
+    for (int o = 32; o > 0; o >>= 1) mine += static_cast<uint32_t>(__shfl_xor(static_cast<int>(mine), o));
+    if (lane_id() == 0 && mine) atomicAdd(&s_cnt, mine);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        s_base = s_cnt ? atomicAdd(&b.ctl->nsel, static_cast<unsigned long long>(s_cnt)) : 0ull;
+        s_cnt = 0;
+    }
+    __syncthreads();
+    for (unsigned long long i0 = beg; i0 < end; i0 += 256) {
         const unsigned long long i = i0 + threadIdx.x;
-        const bool valid = i < n;
         Rec r{0, 0, 0, 0};
         bool keep = false;
-        if (valid) {
+        if (i < end) {
             r = in[i];
-            keep = b.qd[r.q].k == 0 || r.d <= b.qs[r.q].bound;
+            keep = keep_rec(b, r);
         }
         const uint64_t mk = __ballot(keep);
         if (mk == 0) continue;
-        const uint32_t leader = static_cast<uint32_t>(__ffsll(static_cast<long long>(mk)) - 1);
-        const uint32_t q0 = readlane(r.q, static_cast<int>(leader));
-        unsigned long long base = 0;
-        if (lane_id() == leader) base = atomicAdd(&b.ctl->nsel, static_cast<unsigned long long>(popc(mk)));
-        base = (static_cast<unsigned long long>(readlane(static_cast<uint32_t>(base >> 32), static_cast<int>(leader))) << 32) |
-               readlane(static_cast<uint32_t>(base), static_cast<int>(leader));
-        if (keep) kept[base + mbcnt(mk)] = r;
-        const bool same = __ballot(keep && r.q != q0) == 0;
-        if (same) {
-            if (lane_id() == leader) atomicAdd(&b.qs[q0].nsel, static_cast<unsigned long long>(popc(mk)));
-        } else if (keep) {
-            atomicAdd(&b.qs[r.q].nsel, 1ull);
-        }
+        uint32_t base = 0;
+        if (lane_id() == 0) base = atomicAdd(&s_cnt, popc(mk));
+        base = readlane(base, 0);
+        if (keep) kept[s_base + base + mbcnt(mk)] = r;
     }
 }
 
@@ -1872,7 +1971,7 @@ __device__ __forceinline__ void layout_block(const CallBuffers &b, int selected,
         if (valid) {
             const QueryDesc &d = b.qd[q];
             const QueryState &st = b.qs[q];
-            nsel = selected ? st.nsel : st.npairs;
+            nsel = (selected && d.k) ? st.nsel : st.npairs;   // a theta-join keeps every record
             nout = st.err ? 0ull : (d.k ? min(nsel, static_cast<unsigned long long>(d.k)) : nsel);
             if (nsel) atomicMax(&s_dmax, d.k ? st.bound : d.theta);
         }
@@ -1956,6 +2055,19 @@ __device__ __forceinline__ uint32_t chunk_rank(bool act, uint32_t dg, uint32_t (
     return off + wrank;
 }
 
+// hist[key] += 1 for every active lane (key < 2^16), with one atomic per
+// distinct key of the wave: lanes find their peers by the key's bits.
+__device__ __forceinline__ void wave_count16(bool act, uint32_t key, uint32_t *hist) {
+    uint64_t peers = __ballot(act);
+#pragma unroll
+    for (int b = 0; b < 16; ++b) {
+        const bool set = (key >> b) & 1u;
+        const uint64_t m = __ballot(act && set);
+        peers &= set ? m : ~m;
+    }
+    if (act && mbcnt(peers) == 0) atomicAdd(&hist[key], popc(peers));
+}
+
 // Exclusive scan over 256 threads (4 waves) through LDS scratch ws[4].
 __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *ws) {
     const uint32_t tid = threadIdx.x;
@@ -2028,9 +2140,8 @@ __global__ __launch_bounds__(256) void k_sort_pass(const Rec *in, Rec *out, Call
         Rec r{0, 0, 0, 0};
         if (act) r = in[i];
         const uint32_t dg = act ? rec_digit(r, shift, vb, db) : 0u;
-        const uint32_t rk = chunk_rank(act, dg, wcnt);
+        const uint32_t pos = base[dg] + chunk_rank(act, dg, wcnt);
         if (act) {
-            const uint32_t pos = base[dg] + rk;
             if (last) {
                 const QueryState &st = b.qs[r.q];
                 const unsigned long long rel = pos - st.start;
@@ -2043,8 +2154,14 @@ __global__ __launch_bounds__(256) void k_sort_pass(const Rec *in, Rec *out, Call
                 }
             } else {
                 out[pos] = r;
-                atomicAdd(&hist_next[rec_digit(r, shift + 8u, vb, db) * nb + pos / static_cast<uint32_t>(tile)], 1u);
             }
+        }
+        if (!last) {
+            // the next digit's per-tile count: one atomic per distinct (digit,
+            // tile) of the wave (skewed digits would otherwise pile every
+            // lane's atomic onto a few words)
+            const uint32_t key = act ? rec_digit(r, shift + 8u, vb, db) * nb + pos / static_cast<uint32_t>(tile) : 0u;
+            wave_count16(act, key, hist_next);
         }
         __syncthreads();
         base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
@@ -2064,11 +2181,13 @@ __device__ __forceinline__ void bucket_scan_block(const CallBuffers &b, uint32_t
     const uint32_t *cnt = b.bins;
     uint32_t *start = b.bins + nb, *cursor = b.bins + 2 * nb, *cstart = b.bins + 3 * nb;
     const uint32_t per = (nb + 1023u) / 1024u, lo = min(nb, tid * per), hi = min(nb, lo + per);
-    uint32_t sr = 0, sc = 0;
+    uint32_t sr = 0, sc = 0, big = 0;
     for (uint32_t i = lo; i < hi; ++i) {
         sr += cnt[i];
         sc += (cnt[i] + 63u) / 64u;
+        big |= cnt[i] > kBucketRankMax ? 1u : 0u;
     }
+    if (big) b.ctl->resort = 1u;   // (the call block starts cleared)
     uint32_t tr, tc;
     uint32_t er = block_excl_scan_1024(sr, wsum, &tr);
     uint32_t ec = block_excl_scan_1024(sc, wsum, &tc);
@@ -2116,10 +2235,12 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(CallBuffers b) {
 
 // One wave per 64-record chunk of a bin: each record's place in the bin is the
 // number of the bin's records with a smaller (u, v) (keys are unique within a
-// query); the record goes to the caller's output at its query's offset.
+// query); the record goes to the caller's output at its query's offset.  A
+// wave's work is the size of its bin, at most kBucketRankMax (beyond it the
+// caller takes the radix sort).
 __global__ __launch_bounds__(256) void k_bucket_rank(CallBuffers b, rn_pair *out, unsigned long long user_cap) {
     const CallCtl *ctl = b.ctl;
-    if (ctl->npairs > b.rec_cap || ctl->nout > user_cap) return;
+    if (ctl->npairs > b.rec_cap || ctl->nout > user_cap || ctl->resort) return;
     const uint32_t nb = b.nbins, lane = lane_id();
     const uint32_t *cnt = b.bins, *start = b.bins + nb, *cstart = b.bins + 3 * nb;
     const uint32_t total = ctl->nchunks;
@@ -2152,6 +2273,69 @@ __global__ __launch_bounds__(256) void k_bucket_rank(CallBuffers b, rn_pair *out
                 pr.dist = r.d;
                 out[st.off + rel] = pr;
             }
+        }
+    }
+}
+
+// ---- small sort (k-closest-pairs calls with few candidates)
+// One block: the selected records (recs[1], at most kSmallSort) become 64-bit
+// keys (query, dist, u, v) packed as the radix sort orders them (when they fit
+// 63 bits), padded with all-ones keys to a power of two and bitonic-sorted in
+// LDS (one compare-exchange per thread and stage, a barrier per stage); the
+// key gives the record back, which goes to the caller's output at its query's
+// offset.  Too many records or too wide a key: ctl->resort.
+__global__ __launch_bounds__(1024) void k_sort_small(CallBuffers b, uint32_t qb, uint32_t vb, rn_pair *out,
+                                                     unsigned long long user_cap) {
+    __shared__ unsigned long long s_k[kSmallSort];
+    CallCtl *ctl = b.ctl;
+    if (ctl->npairs > b.rec_cap || ctl->nout > user_cap) return;
+    const uint32_t tid = threadIdx.x;
+    const unsigned long long n64 = ctl->nsel;
+    const uint32_t db = ctl->sort_db;
+    if (n64 > kSmallSort || qb + db + 2u * vb > 63u) {
+        if (tid == 0) ctl->resort = 1u;
+        return;
+    }
+    const uint32_t n = static_cast<uint32_t>(n64);
+    uint32_t P = 2;
+    while (P < n) P <<= 1;
+    const uint32_t sh_d = 2u * vb, sh_q = 2u * vb + db;
+    for (uint32_t i = tid; i < P; i += 1024) {
+        unsigned long long key = ~0ull;
+        if (i < n) {
+            const Rec r = b.recs[1][i];
+            key = (static_cast<unsigned long long>(r.q) << sh_q) | (static_cast<unsigned long long>(r.d) << sh_d) |
+                  (static_cast<unsigned long long>(static_cast<uint32_t>(r.u)) << vb) | static_cast<uint32_t>(r.v);
+        }
+        s_k[i] = key;
+    }
+    __syncthreads();
+    for (uint32_t k = 2; k <= P; k <<= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+            for (uint32_t i = tid; i < P / 2; i += 1024) {
+                const uint32_t lo = ((i & ~(j - 1u)) << 1) | (i & (j - 1u)), hi = lo + j;
+                const bool up = (lo & k) == 0u;
+                const unsigned long long x = s_k[lo], y = s_k[hi];
+                if ((x > y) == up) {
+                    s_k[lo] = y;
+                    s_k[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    const unsigned long long vm = (1ull << vb) - 1ull, dm = (1ull << db) - 1ull;
+    for (uint32_t i = tid; i < n; i += 1024) {
+        const unsigned long long key = s_k[i];
+        const uint32_t q = static_cast<uint32_t>(key >> sh_q);
+        const QueryState &st = b.qs[q];
+        const unsigned long long rel = static_cast<unsigned long long>(i) - st.start;
+        if (rel < st.nout) {
+            rn_pair p;
+            p.u = static_cast<int32_t>((key >> vb) & vm);
+            p.v = static_cast<int32_t>(key & vm);
+            p.dist = static_cast<uint32_t>((key >> sh_d) & dm);
+            out[st.off + rel] = p;
         }
     }
 }
@@ -2291,6 +2475,12 @@ hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_pass
         in = o;
         o = t;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_sort_small(const CallBuffers &b, uint32_t qb, uint32_t vb, rn_pair *out, unsigned long long user_cap,
+                             hipStream_t s) {
+    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, s, b, qb, vb, out, user_cap);
     return hipGetLastError();
 }
 

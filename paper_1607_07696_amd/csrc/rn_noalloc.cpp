@@ -135,11 +135,9 @@ rn_status rn_dist_join_noalloc(rn_graph *g, const int32_t *R, int32_t nR, const 
         size_t slot_words = 0;
         RN_TRY(carve(base, p, g->Vmax, nslots, ws, &slot_words));
         if (nslots) {
-            // global-tier slots start cleared: distances at kInf, stamps and far
-            // bits zero (the layout depends on the graph, so clear at every use)
-            const size_t V = static_cast<size_t>(g->Vmax);
-            RN_HIP(launch_fill_u32(ws.d_gslots, nslots * V, kInf, s), "clearing search slots");
-            RN_HIP(launch_fill_u32(ws.d_gslots + nslots * V, nslots * V + nslots * global_bitmap_words(g->Vmax), 0u, s),
+            // global-tier slots start cleared (every word all ones; the layout
+            // depends on the graph, so clear at every use)
+            RN_HIP(launch_fill_u32(ws.d_gslots, global_clear_words(nslots, g->Vmax), 0xFFFFFFFFu, s),
                    "clearing search slots");
         }
         fill_host_desc(p, h_desc);
@@ -164,6 +162,10 @@ rn_status rn_dist_join_noalloc(rn_graph *g, const int32_t *R, int32_t nR, const 
         if (c.npairs > ws.rec_cap)
             return fail(RN_ERR_NOMEM, "the call's records do not fit the scratch array (" + std::to_string(c.npairs) +
                                           " records, room for " + std::to_string(ws.rec_cap) + ")");
+        if (c.resort) {   // the call's sort left the output to the radix sort
+            RN_TRY(enqueue_sort_fallback(ws, p, out, cap, s));
+            RN_HIP(hipStreamSynchronize(s), "waiting for the sort");
+        }
         *n_out = static_cast<int64_t>(c.nout);
         if (qs.err) return fail(RN_ERR_ARG, "invalid node sets:" + describe_err(qs.err));
         if (c.nout > static_cast<unsigned long long>(cap)) return fail(RN_ERR_CAPACITY, "output buffer too small");

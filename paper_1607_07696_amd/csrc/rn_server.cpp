@@ -41,6 +41,8 @@ struct Request {
     uint32_t theta = 0;
     int32_t k = 0;
     double footprint = 0;           // estimated device bytes while in flight
+    bool heavy = false;             // estimated search work above kHeavyWork
+    bool held = false;              // was once held back by the HBM budget
     Clock::time_point t_submit, t_done;
     std::vector<rn_pair> result;
     rn_status status = RN_OK;
@@ -123,6 +125,29 @@ double footprint(const rn_server *s, const Request &r) {
     }
     return 4.0 * (nR + nS) + pairs * (2.0 * sizeof(Rec) + sizeof(rn_pair));
 }
+
+// Estimated search work of a request, in vertices visited: its searches run
+// from the smaller side; a theta-join's balls hold about c_ball theta^2
+// vertices; a k-closest-pairs search reaches the ball holding about k of the
+// |R| |S| pairs (the whole graph when k is a large share of them).
+double work_estimate(const rn_server *s, const Request &r) {
+    const double nR = static_cast<double>(r.R.size()), nS = static_cast<double>(r.S.size());
+    const double V = static_cast<double>(std::max(1, s->V));
+    double ball;
+    if (r.k == 0) {
+        const double th = static_cast<double>(r.theta);
+        ball = std::min(V, s->c_ball * th * th);
+    } else {
+        ball = std::min(V, std::max(64.0, 4.0 * static_cast<double>(r.k) * V / (nR * nS)));
+        if (r.theta < kMaxDist) ball = std::min(ball, s->c_ball * double(r.theta) * r.theta);
+    }
+    return std::min(nR, nS) * ball;
+}
+
+// Requests above this estimated work (vertices visited; about 2-5 ms of
+// device time on road graphs) are heavy: with heavy_lane set they run one at
+// a time on the last lane, so that light requests never queue behind them.
+constexpr double kHeavyWork = 2.0e7;
 
 void finish_request(rn_server *s, Request *r, rn_status st, const std::string &msg) {
     r->status = st;
@@ -240,6 +265,15 @@ bool progress_lane(rn_server *s, Lane &L) {
             fail_batch(s, L, st == RN_OK ? RN_ERR_NOMEM : st, st == RN_OK ? "buffers did not settle" : last_error());
             return true;
         }
+        if (c.resort) {
+            // the call's sort left the output to the radix sort, which
+            // writes it before the copy below on the same stream
+            st = enqueue_sort_fallback(L.ws, L.prep, L.d_out, static_cast<int64_t>(L.out_cap), L.stream);
+            if (st != RN_OK) {
+                fail_batch(s, L, st, last_error());
+                return true;
+            }
+        }
         L.nout = c.nout;
         if (L.h_out_cap < L.nout) {
             host_free(L.h_out);
@@ -309,22 +343,63 @@ void server_loop(rn_server *s) {
         std::vector<Lane *> to_launch;
         {
             std::unique_lock<std::mutex> lk(s->mu);
-            for (Lane &L : s->lanes) {
+            const int32_t nl = static_cast<int32_t>(s->lanes.size());
+            const bool split = s->cfg.heavy_lane && nl >= 2;
+            for (int32_t li = 0; li < nl; ++li) {
+                Lane &L = s->lanes[static_cast<size_t>(li)];
                 if (L.state != Lane::IDLE || !L.batch.empty() || s->pending.empty()) continue;
-                // admit the longest FIFO prefix within the budget and the batch
-                // limit (one request always goes when nothing is in flight)
+                // admit waiting requests in arrival order, within the budget and
+                // the batch limit (one request always goes when nothing is in
+                // flight).  heavy_lane: the last lane takes heavy requests, one
+                // per batch, first, and light ones when no heavy one waits; the
+                // other lanes take light requests, and the first heavy one
+                // while the heavy lane is busy and no light request waits
                 const bool alone = s->in_flight_requests == 0;
-                while (!s->pending.empty() && static_cast<int32_t>(L.batch.size()) < s->cfg.max_batch) {
-                    Request *r = s->pending.front();
+                const bool heavy_lane = split && li == nl - 1;
+                const bool heavy_busy = split && s->lanes[static_cast<size_t>(nl - 1)].state != Lane::IDLE;
+                auto take_first_heavy = [&]() {
+                    for (auto it = s->pending.begin(); it != s->pending.end(); ++it) {
+                        Request *r = *it;
+                        if (!r->heavy) continue;
+                        const bool fits = s->budget_used + r->footprint <= static_cast<double>(s->cfg.hbm_budget);
+                        if (!fits && !alone && !r->held) {
+                            r->held = true;
+                            s->stats.budget_waits += 1;
+                        }
+                        if (!fits && !alone) return false;
+                        s->pending.erase(it);
+                        L.batch.push_back(r);
+                        L.reserved += r->footprint;
+                        s->budget_used += r->footprint;
+                        s->in_flight_requests += 1;
+                        return true;   // heavy requests go in arrival order, one per batch
+                    }
+                    return false;
+                };
+                bool took_heavy = heavy_lane && take_first_heavy();
+                for (auto it = s->pending.begin();
+                     !took_heavy && it != s->pending.end() && static_cast<int32_t>(L.batch.size()) < s->cfg.max_batch;) {
+                    Request *r = *it;
+                    if (split && r->heavy) {   // left for the heavy lane
+                        ++it;
+                        continue;
+                    }
                     const bool fits = s->budget_used + r->footprint <= static_cast<double>(s->cfg.hbm_budget);
-                    if (!fits && !(alone && L.batch.empty())) break;
-                    s->pending.pop_front();
+                    if (!fits && !(alone && L.batch.empty())) {
+                        if (!r->held) {
+                            r->held = true;
+                            s->stats.budget_waits += 1;
+                        }
+                        break;
+                    }
+                    it = s->pending.erase(it);
                     L.batch.push_back(r);
                     L.reserved += r->footprint;
                     s->budget_used += r->footprint;
                     s->in_flight_requests += 1;
                 }
-                if (L.batch.empty()) break;   // the budget is full: wait for a lane to finish
+                if (L.batch.empty() && split && !heavy_lane && heavy_busy) take_first_heavy();
+                if (L.batch.empty()) continue;   // nothing this lane may take now
                 to_launch.push_back(&L);
                 s->stats.batches += 1;
                 s->stats.peak_budget = std::max(s->stats.peak_budget, static_cast<int64_t>(s->budget_used));
@@ -400,6 +475,11 @@ rn_status rn_server_create(rn_graph *g, const rn_server_config *cfg, rn_server *
             (e = hipEventCreateWithFlags(&L.ev_copy, hipEventDisableTiming)) != hipSuccess)
             st = hip_fail(e, "creating lane streams");
         L.ws.gslot_cap = static_cast<uint32_t>(cfg->global_slots);
+        // a lane's global-tier slots are allocated here, when the server
+        // starts, and not when a search first needs them: an allocation on
+        // the request path would stall every lane (the bytes count in
+        // rn_server_stats.device_bytes, outside the HBM budget)
+        if (st == RN_OK) st = ensure_gslots(L.ws, g->Vmax, static_cast<uint32_t>(cfg->global_slots), L.stream);
     }
     if (st == RN_OK) {
         try {
@@ -447,6 +527,7 @@ rn_status rn_server_submit(rn_server *s, const int32_t *R, int32_t nR, const int
             return fail(RN_ERR_ARG, "the server is shutting down");
         }
         r->footprint = footprint(s, *r);
+        r->heavy = work_estimate(s, *r) > kHeavyWork;
         r->id = s->next_id++;
         s->reqs[r->id] = r;
         s->pending.push_back(r);

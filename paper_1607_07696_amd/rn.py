@@ -50,7 +50,8 @@ class Query(C.Structure):
 class ServerConfig(C.Structure):
     """struct rn_server_config (include/rn.h)."""
     _fields_ = [("graph", C.c_int32), ("lanes", C.c_int32), ("max_batch", C.c_int32),
-                ("global_slots", C.c_int32), ("hbm_budget", C.c_int64)]
+                ("global_slots", C.c_int32), ("hbm_budget", C.c_int64), ("heavy_lane", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class ServerStats(C.Structure):
@@ -58,10 +59,10 @@ class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("batches", C.c_int64),
                 ("reruns", C.c_int64), ("peak_budget", C.c_int64), ("device_bytes", C.c_int64),
                 ("max_in_flight", C.c_int32), ("max_lanes_busy", C.c_int32), ("max_batch_seen", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("budget_waits", C.c_int32)]
 
     def as_dict(self) -> dict:
-        return {f: getattr(self, f) for f, _ in self._fields_ if f != "reserved"}
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Stats(C.Structure):
@@ -443,9 +444,10 @@ class Server:
     node sets, wait for host results; batching and overlap happen inside."""
 
     def __init__(self, net: RoadNetwork, graph: int = 0, lanes: int = 2, max_batch: int = 8,
-                 global_slots: int = 128, hbm_budget: int = 8 << 30):
+                 global_slots: int = 128, hbm_budget: int = 8 << 30, heavy_lane: bool = True):
         self.net = net
-        cfg = ServerConfig(int(graph), int(lanes), int(max_batch), int(global_slots), int(hbm_budget))
+        cfg = ServerConfig(int(graph), int(lanes), int(max_batch), int(global_slots), int(hbm_budget),
+                           1 if heavy_lane else 0, 0)
         h = C.c_void_p()
         self._h = None
         _check(load_library().rn_server_create(net._h, C.byref(cfg), C.byref(h)))

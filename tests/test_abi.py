@@ -138,4 +138,4 @@ def test_server_calls_reject_bad_arguments_before_device(rn):
     assert lib.rn_server_wait(None, 1, None, 0, C.byref(n), None) == rn.RN_ERR_ARG and n.value == 0
     assert lib.rn_server_get_stats(None, None) == rn.RN_ERR_ARG
     lib.rn_server_free(None)
-    assert C.sizeof(rn.ServerConfig) == 24 and C.sizeof(rn.ServerStats) == 64
+    assert C.sizeof(rn.ServerConfig) == 32 and C.sizeof(rn.ServerStats) == 64

@@ -157,6 +157,58 @@ def test_one_distance_bin_beyond_2_16_records(rnmod, orc, rg):
         assert_same(gpu_join(rnmod, net, R, S, theta), want)
 
 
+def test_oversized_bins_take_the_radix_sort_everywhere(rnmod, orc, rg):
+    # bins past the bucket ranking's bound (4096 records) send the call's
+    # scattered records to the radix sort: in a batch beside queries whose
+    # bins are small, in a captured plan, in the request server and in the
+    # allocation-free call, every result equals the oracle's; so do
+    # k-closest-pairs calls with more tied candidates than the small sort holds
+    import ctypes as C
+    import torch
+    R = np.arange(300, dtype=np.int32)
+    S = np.arange(300, 600, dtype=np.int32)
+    chain = np.arange(600, 619)
+    g = rg.from_edges(620, np.concatenate([np.repeat(R, 300), chain]),
+                      np.concatenate([np.tile(S, 300), chain + 1]),
+                      np.concatenate([np.full(90000, 5), np.arange(1, 20)]), symmetric=False)
+    net = rnmod.RoadNetwork.from_graph(g)
+    specs = [{"R": R, "S": S, "theta": 12}, {"R": R[:50], "S": S[:60], "theta": 5},
+             {"R": chain[:5].astype(np.int32), "S": chain[5:].astype(np.int32) + 1, "theta": 100},
+             {"R": R[:70], "S": S[:40], "theta": 4}]
+    wants = [orc.dist_join(g, sp["R"], sp["S"], sp["theta"]).pairs for sp in specs]
+    assert [len(w) for w in wants][:2] == [90000, 3000]
+
+    def check_batch(pairs, off):
+        got = rnmod.pairs_to_numpy(pairs)
+        for i, w in enumerate(wants):
+            assert_same(got[off[i]:off[i + 1]], w)
+    check_batch(*net.join_batch(specs)[:2])
+    q, keep = net.make_queries(specs)
+    plan = net.plan(q)
+    for _ in range(2):
+        check_batch(*plan.run()[:2])
+    plan.close()
+    srv = rnmod.Server(net, lanes=2, max_batch=4)
+    ids = [srv.submit(sp["R"], sp["S"], sp["theta"], 0) for sp in specs]
+    for i, w in zip(ids, wants):
+        got, _ = srv.wait(i, guess=len(w) + 1)
+        assert_same(got, w)
+    srv.close()
+    lib = rnmod.load_library()
+    Rd, Sd = torch.as_tensor(R, device="cuda"), torch.as_tensor(S, device="cuda")
+    out = torch.zeros((90001, 3), dtype=torch.int32, device="cuda")
+    n = C.c_int64()
+    st = lib.rn_dist_join_noalloc(net._h, C.c_void_p(Rd.data_ptr()), 300, C.c_void_p(Sd.data_ptr()), 300,
+                                  C.c_uint32(12), C.c_void_p(out.data_ptr()), 90001, C.byref(n),
+                                  C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    assert st == rnmod.RN_OK and n.value == 90000
+    assert_same(rnmod.pairs_to_numpy(out[:90000]), wants[0])
+    # k-closest pairs whose ties at the bound give more candidates than the
+    # one-block sort holds (90 000 pairs at distance 5): the radix sort runs
+    for k in (10, 2048):
+        assert_same(rnmod.pairs_to_numpy(net.kcp_join(R, S, k)), orc.kcp_join(g, R, S, k))
+
+
 def test_lattice_closed_form_at_scale(rnmod, rg):
     side, c = 1024, 100
     g = rg.full_lattice(side, c)

@@ -100,6 +100,31 @@ def test_requests_arriving_later_overtake_a_long_one(rnmod, orc, graph, rg):
     assert st["max_lanes_busy"] == 2
 
 
+def test_heavy_requests_run_on_their_own_lane(rnmod, orc, graph, rg):
+    # three whole-graph requests (every pair of 1000 x 1000) and then ten light
+    # ones: with a lane set aside for heavy requests the light ones run on the
+    # other lane at once, so all of them are answered before the last heavy
+    # one, which waits for the two before it
+    net = rnmod.RoadNetwork.from_graph(graph)
+    srv = rnmod.Server(net, lanes=2, max_batch=8, heavy_lane=True)
+    heavy = [rg.sample_disjoint(graph.V, 1000, 1000, 170 + i) for i in range(3)]
+    hid = [srv.submit(R, S, MAX_DIST, 0) for R, S in heavy]
+    light = [rg.sample_disjoint(graph.V, 40, 40, 180 + i) for i in range(10)]
+    lid = [srv.submit(R, S, 900, 0) for R, S in light]
+    lat_light = []
+    for (R, S), i in zip(light, lid):
+        got, lat = srv.wait(i)
+        lat_light.append(lat)
+        assert_same(got, orc.dist_join(graph, R, S, 900).pairs)
+    lat_heavy = []
+    for (R, S), i in zip(heavy, hid):
+        got, lat = srv.wait(i, guess=len(R) * len(S))
+        lat_heavy.append(lat)
+        assert got.shape[0] == len(R) * len(S)
+    srv.close()
+    assert max(lat_light) < max(lat_heavy)
+
+
 def test_budget_limits_admission(rnmod, orc, graph):
     reqs = make_requests(graph, 12, 74)
     net = rnmod.RoadNetwork.from_graph(graph)
