@@ -247,10 +247,18 @@ rn_status rn_graph_size(const rn_graph *g, int32_t i, int32_t *V, int64_t *A);
  *             queries as "k results within theta")
  *   theta     distance bound, inclusive, <= 2^32 - 2
  *   delta     bucket width for this query's searches, or RN_DELTA_DEFAULT
- *   hash_log2 first on-chip table size for its searches (8..14), or 0 for the
- *             default (the handle's setting for a theta-join, 8 for k > 0)
+ *   hash_log2 first on-chip table size for its searches (8..14),
+ *             RN_TABLE_GLOBAL to run them in the global-memory tier from the
+ *             start, or 0 for the default: the handle's setting for a
+ *             theta-join, 8 for k > 0, and the global tier where the searches
+ *             are sure to outgrow every on-chip table (a theta-join whose
+ *             expected ball, about 2 (theta / mean arc weight)^2 vertices, is
+ *             more than twice the largest table's capacity; a k-closest-pairs
+ *             query that asks for at least half of its |R| |S| pairs on a
+ *             graph of 2^16 vertices or more)
  * delta and hash_log2 never change results.
  */
+#define RN_TABLE_GLOBAL 15
 typedef struct rn_query {
     const int32_t *R;
     const int32_t *S;
@@ -289,9 +297,11 @@ rn_status rn_join_batch(rn_graph *g, const rn_query *q, int32_t nq, rn_pair *out
 /*
  * rn_autotune -- choose delta and hash_log2 for each query by timing a few
  * candidate settings on a sample of its sources (the first min(nR, sample)
- * entries of R) and keeping the one with the least relaxation time.  Writes
- * q[i].delta and q[i].hash_log2; results never depend on them.  The device
- * work runs on `stream`.
+ * entries of R) and keeping the one with the least relaxation time: delta in
+ * {0, w_min, 4 w_min} times first table sizes (2^9..2^12 for theta-joins,
+ * 2^8..2^10 for k > 0), plus the global tier from the start (RN_TABLE_GLOBAL)
+ * with the default delta.  Writes q[i].delta and q[i].hash_log2; results
+ * never depend on them.  The device work runs on `stream`.
  */
 rn_status rn_autotune(rn_graph *g, rn_query *q, int32_t nq, int32_t sample, void *stream);
 

@@ -67,7 +67,8 @@ rn_status check_queries(const rn_graph *g, const rn_query *q, int32_t nq, int32_
             m = "R and S together exceed the vertex count (they must be disjoint)";
         else if (x.k < 0 || x.k > (1 << 24)) m = "k must be 0 (theta-join) or in [1, 2^24]";
         else if (x.theta > kMaxDist) m = "theta must be <= 2^32 - 2";
-        else if (x.hash_log2 != 0 && !join_tier_supported(x.hash_log2)) m = "hash_log2 must be 0 or in [8, 14]";
+        else if (x.hash_log2 != 0 && x.hash_log2 != kGlobalHB && !join_tier_supported(x.hash_log2))
+            m = "hash_log2 must be 0, in [8, 14] or RN_TABLE_GLOBAL";
         else if (x.flags & ~RN_QUERY_FORWARD) m = "unknown query flags";
         if (status) status[i] = m ? RN_ERR_ARG : RN_OK;
         if (m && bad < 0) {
@@ -92,6 +93,24 @@ int first_table(const rn_graph *g, int32_t graph, uint32_t theta) {
     int hb = g->hash_log2;
     while (hb < kMaxHB && static_cast<double>(1u << hb) < need) ++hb;
     return hb;
+}
+
+// Queries whose searches are sure to outgrow the largest on-chip table go to
+// the global tier from the start instead of failing through every tier: a
+// theta-join whose expected ball (as first_table estimates it, capped at the
+// graph) needs more than twice the largest table, and a k-closest-pairs query
+// asking for at least half of its pairs on a graph of 2^16 vertices or more
+// (its searches then reach past the median R-S distance, a large share of
+// the graph).
+bool sure_global(const rn_graph *g, const rn_query &x) {
+    if (!g->hash_auto) return false;
+    const double V = static_cast<double>(g->voff[x.graph + 1] - g->voff[x.graph]);
+    const double r = static_cast<double>(x.theta) / std::max(1.0, g->wmean[x.graph]);
+    const double ball = std::min(V, 2.0 * r * r);
+    const double cap = 0.75 * static_cast<double>(1u << kMaxHB);
+    if (x.k == 0) return 1.3 * ball > 2.0 * cap;
+    const double pairs = static_cast<double>(x.nR) * static_cast<double>(x.nS);
+    return 2.0 * static_cast<double>(x.k) >= pairs && V >= 65536.0 && ball > 2.0 * cap;
 }
 
 // The on-chip search with delta = 0 takes the oldest pending vertices in
@@ -131,14 +150,18 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
     uint32_t dmax = 0;
     for (int32_t i = 0; i < nq; ++i) {
         const rn_query &x = q[i];
-        hb[i] = x.hash_log2 ? x.hash_log2 : (x.k ? kMinHB : first_table(g, x.graph, x.theta));
+        hb[i] = x.hash_log2 ? x.hash_log2
+                            : (sure_global(g, x) ? kGlobalHB : (x.k ? kMinHB : first_table(g, x.graph, x.theta)));
         p.any_kcp |= x.k > 0;
         dmax = std::max(dmax, x.theta);
         p.total_R += static_cast<uint64_t>(std::max(x.nR, 0));
     }
     // staging order: grouped by first table size and kind, query order within a group
     for (int32_t i = 0; i < nq; ++i) p.perm[i] = static_cast<uint32_t>(i);
-    auto key = [&](uint32_t i) { return 2 * hb[i] + (q[i].k > 0 ? 1 : 0); };
+    // (every query searched in the global tier from the start forms one group:
+    // a launch of that tier uses every slot, so two could not run side by side)
+    auto kcp_part = [&](uint32_t i) { return hb[i] != kGlobalHB && q[i].k > 0; };
+    auto key = [&](uint32_t i) { return 2 * hb[i] + (kcp_part(i) ? 1 : 0); };
     std::stable_sort(p.perm.begin(), p.perm.end(), [&](uint32_t a, uint32_t b) { return key(a) < key(b); });
     uint64_t sw = 0, rw = 0;
     uint32_t nkcp = 0;
@@ -174,15 +197,17 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         sw += round_up(words, 4);
         rw += words;
         if (sw >= 0xFFFFFFFFull || rw >= 0xFFFFFFFFull) return fail(RN_ERR_ARG, "too many vertices in one call");
-        if (p.groups.empty() || p.groups.back().hb != hb[i] || p.groups.back().kcp != (x.k > 0))
+        if (p.groups.empty() || p.groups.back().hb != hb[i] ||
+            (hb[i] != kGlobalHB && p.groups.back().kcp != (x.k > 0)))
             p.groups.push_back(Group{hb[i], x.k > 0, true, s, s + 1, 0});
         Group &gr = p.groups.back();
+        gr.kcp = gr.kcp || x.k > 0;
         gr.end = s + 1;
         gr.sources += static_cast<uint64_t>(d.nR);
         // compact tables: local ids below 2^24, and (theta-joins) every
         // distance within theta fits the compact word; a k-closest-pairs
         // search whose bound is larger moves on if it meets such a distance
-        gr.compact = gr.compact && hb[i] >= kCompactMinHB && g->Vmax < kCompactVertices &&
+        gr.compact = gr.compact && hb[i] >= kCompactMinHB && hb[i] <= kMaxHB && g->Vmax < kCompactVertices &&
                      (x.k > 0 || x.theta <= compact_max_dist(hb[i]));
     }
     p.rbase[nq] = static_cast<uint32_t>(rw);
@@ -192,6 +217,7 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
     for (const Group &gr : p.groups) {
         p.need_list0 |= gr.hb < kRetryHB1;
         p.need_list1 |= gr.hb < kMaxHB;
+        p.any_global |= gr.hb == kGlobalHB;
     }
     // the bucket sort: theta-joins only, on graphs with varied weights, with
     // at most kMaxBins (query, dist) bins in all
@@ -424,34 +450,58 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         k.send = &b.ctl->nsrc;
         RN_HIP(launch_kcp_seed(k, b, static_cast<uint32_t>(p.total_R), s), "seeding the k-closest-pairs bounds");
     }
-    // first tiers, one launch per table size; several run side by side
+    // first tiers, one launch per table size; several run side by side.  The
+    // device gives a process few hardware queues (four), so the on-chip groups
+    // share at most three streams (this one and two side streams, in turn),
+    // and a group searched in the global tier from the start gets a side
+    // stream of its own that the re-run tiers do not wait for: only the later
+    // global launch, which takes the same slots, waits for it.
     const size_t ng = p.groups.size();
     if (ng > static_cast<size_t>(kSide) + 1) return fail(RN_ERR_DEVICE, "too many first-tier groups");
-    const bool fork = !shared && ng > 1;
+    const bool early_global = ng > 0 && p.groups[ng - 1].hb == kGlobalHB && ws.d_gslots != nullptr;
+    const size_t non = ng - (early_global ? 1 : 0);                  // on-chip groups
+    const size_t ons = shared ? 1 : std::max<size_t>(1, std::min<size_t>(non, 3));   // their streams
+    const size_t gside = early_global && !shared ? 1 : 0;             // side stream 0: the global group
+    const bool fork = ons > 1 || gside > 0;
     if (fork) {
-        RN_TRY(ensure_side_streams(ws, ng - 1));
+        RN_TRY(ensure_side_streams(ws, gside + ons - 1));
         RN_HIP(hipEventRecord(ws.fork, s), "forking streams");
+        for (size_t i = 0; i < gside + ons - 1; ++i) RN_HIP(hipStreamWaitEvent(ws.side[i], ws.fork, 0), "forking streams");
     }
+    auto on_chip_stream = [&](size_t gi) { return gi % ons == 0 ? s : ws.side[gside + gi % ons - 1]; };
     for (size_t gi = 0; gi < ng; ++gi) {
         const Group &gr = p.groups[gi];
-        hipStream_t st = gi == 0 || !fork ? s : ws.side[gi - 1];
-        if (gi > 0 && fork) RN_HIP(hipStreamWaitEvent(st, ws.fork, 0), "forking streams");
         JoinArgs t = a;
         t.src = b.src;
         t.srcq = b.srcq;
         t.sbeg = &b.qs[p.perm[gr.first]].src_start;
         t.send = gr.end < p.nq ? &b.qs[p.perm[gr.end]].src_start : &b.ctl->nsrc;
-        const int li = retry_list_after(gr.hb);
-        t.ovf = b.list[li];
-        t.ovfq = b.listq[li];
-        t.novf = &b.ctl->nlist[li];
-        t.first_tier = 1;
-        t.tier = 0;
-        RN_HIP(launch_join(t, gr.hb, gr.kcp, gr.compact, static_cast<uint32_t>(gr.sources), !shared, st),
-               "launching the relaxation");
-        if (gi > 0 && fork) RN_HIP(hipEventRecord(ws.join[gi - 1], st), "joining streams");
+        if (early_global && gi == ng - 1) {
+            // searches sure to outgrow every table: the global tier at once
+            hipStream_t st = gside ? ws.side[0] : s;
+            t.tier = 3;
+            t.work = ws.d_block + p.off_work + 32;
+            RN_HIP(launch_join_global(t, ws.d_gslots, ws.n_gslots, g->Vmax, static_cast<uint32_t>(gr.sources), st),
+                   "launching the global relaxation");
+        } else {
+            // (without global-tier slots yet, a global group takes the largest
+            // table, whose overflows get the slots and a re-run of the call)
+            const int hbt = std::min(gr.hb, kMaxHB);
+            const int li = retry_list_after(hbt);
+            t.ovf = b.list[li];
+            t.ovfq = b.listq[li];
+            t.novf = &b.ctl->nlist[li];
+            t.first_tier = 1;
+            t.tier = 0;
+            RN_HIP(launch_join(t, hbt, gr.kcp, gr.compact, static_cast<uint32_t>(gr.sources), !shared,
+                               on_chip_stream(gi)),
+                   "launching the relaxation");
+        }
     }
-    for (size_t gi = 1; fork && gi < ng; ++gi) RN_HIP(hipStreamWaitEvent(s, ws.join[gi - 1], 0), "joining streams");
+    if (fork) {
+        for (size_t i = 0; i < gside + ons - 1; ++i) RN_HIP(hipEventRecord(ws.join[i], ws.side[i]), "joining streams");
+        for (size_t i = gside; i < gside + ons - 1; ++i) RN_HIP(hipStreamWaitEvent(s, ws.join[i], 0), "joining streams");
+    }
     record(g, ws, timed, EV_TIER0, s);
     // re-runs: 2^11-slot tables, 2^14-slot tables, then the global tier
     const uint32_t maxs = static_cast<uint32_t>(p.total_R);
@@ -474,6 +524,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         RN_HIP(launch_join(t, li == 0 ? kRetryHB1 : kMaxHB, true, false, maxs, !shared, s),
                "launching the relaxation");
     }
+    if (gside) RN_HIP(hipStreamWaitEvent(s, ws.join[0], 0), "joining streams");   // the early global launch
     if (ws.d_gslots) {   // (without slots the call is run again once they exist)
         JoinArgs t = a;
         t.src = b.list[2];
@@ -1251,10 +1302,12 @@ rn_status rn_autotune(rn_graph *g, rn_query *q, int32_t nq, int32_t sample, void
         float best = 3.4e38f;
         uint32_t best_delta = g->delta;
         int best_hb = t.k ? kMinHB : g->hash_log2;
-        for (int di = 0; di < 3 && result == RN_OK; ++di) {
-            for (int hi = 0; hi < nh && result == RN_OK; ++hi) {
-                t.delta = deltas[di];
-                t.hash_log2 = hbs[hi];
+        for (int di = 0; di < 4 && result == RN_OK; ++di) {
+            for (int hi = 0; hi < (di < 3 ? nh : 1) && result == RN_OK; ++hi) {
+                // the fourth setting: the global tier from the start (its
+                // buckets have their own width, so delta does not apply)
+                t.delta = di < 3 ? deltas[di] : g->delta;
+                t.hash_log2 = di < 3 ? hbs[hi] : kGlobalHB;
                 Prepared p;
                 result = prepare(g, &t, 1, p);
                 if (result != RN_OK) break;

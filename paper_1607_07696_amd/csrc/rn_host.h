@@ -145,6 +145,7 @@ struct Prepared {
     bool any_kcp = false;
     bool need_list0 = false;
     bool need_list1 = false;
+    bool any_global = false;        // a first-tier group runs in the global tier
     uint32_t qb = 0, vb = 1, max_passes = 1;
     uint64_t total_R = 0;
     unsigned long long total_elems = 0;

@@ -27,6 +27,9 @@ enum : uint32_t {
 constexpr int kMinHB = 8;
 constexpr int kMaxHB = 14;
 constexpr int kRetryHB1 = 11;
+// First-tier "table size" of queries whose searches run in the global tier
+// from the start (RN_TABLE_GLOBAL).
+constexpr int kGlobalHB = kMaxHB + 1;
 constexpr int kLists = 3;
 inline int retry_list_after(int hb) { return hb < kRetryHB1 ? 0 : (hb < kMaxHB ? 1 : 2); }
 

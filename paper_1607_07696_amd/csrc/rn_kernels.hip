@@ -1398,6 +1398,14 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
         const int32_t u = a.src[sb + i];
         const SrcCtx c = load_ctx(a, a.srcq[sb + i]);
         const uint32_t voff = static_cast<uint32_t>(c.voff);
+        // a k-query answered by k_kcp_direct has nothing to search
+        if (c.k != 0 && a.qs[c.q].direct) {
+            __syncthreads();   // every thread has read the query before the claim is rewritten
+            if (tid == 0) s_si = gridDim.x + atomicAdd(a.work, 1u);
+            __syncthreads();
+            i = s_si;
+            continue;
+        }
         if (tid == 0) {
             word[u - c.voff] = 1ull;   // distance 0, queued for round 1
             G.fy[1][0] = static_cast<uint32_t>(u);

@@ -31,6 +31,7 @@ EXPORTS = (
 )
 RN_DELTA_DEFAULT = 0xFFFFFFFF
 RN_QUERY_FORWARD = 1
+RN_TABLE_GLOBAL = 15
 MAX_DIST = 0xFFFFFFFE
 
 

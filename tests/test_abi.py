@@ -139,3 +139,10 @@ def test_server_calls_reject_bad_arguments_before_device(rn):
     assert lib.rn_server_get_stats(None, None) == rn.RN_ERR_ARG
     lib.rn_server_free(None)
     assert C.sizeof(rn.ServerConfig) == 32 and C.sizeof(rn.ServerStats) == 64
+
+
+def test_header_constants_match_binding(rn):
+    text = open(HEADER).read()
+    for name in ("RN_TABLE_GLOBAL", "RN_QUERY_FORWARD"):
+        m = re.search(r"#define\s+" + name + r"\s+(\w+)", text)
+        assert m and int(m.group(1), 0) == getattr(rn, name), name

@@ -75,7 +75,7 @@ def test_batch_with_partition_and_autotune(rnmod, orc, instances):
     net.partition(1.0, 128)
     q, keep = net.make_queries([spec(x, i) for i, x in enumerate(sub)])
     net.autotune(q, sample=64)
-    assert all(8 <= q[i].hash_log2 <= 14 for i in range(len(sub)))
+    assert all(8 <= q[i].hash_log2 <= 14 or q[i].hash_log2 == rnmod.RN_TABLE_GLOBAL for i in range(len(sub)))
     out, off, status = net.join_batch(q)
     cases = [(x.graph, x.R, x.S, x.theta if x.k == 0 else MAX_DIST, x.k) for x in sub]
     check_batch(rnmod, orc, out, off, status, cases)
@@ -112,8 +112,20 @@ def test_per_query_tuning_and_tiers(rnmod, orc, rg):
         k = 0 if i < 5 else 50
         specs.append({"R": R, "S": S, "theta": theta, "k": k, "hash_log2": hb, "delta": delta})
         cases.append((g, R, S, theta, k))
+    # searches in the global tier from the start, beside the on-chip groups
+    # (theta-joins and k-closest pairs together: they share the tier's slots)
+    for theta, k in ((6000, 0), (2500, 50), (MAX_DIST, 300), (4000, 0)):
+        specs.append({"R": R, "S": S, "theta": theta, "k": k, "hash_log2": rnmod.RN_TABLE_GLOBAL})
+        cases.append((g, R, S, theta, k))
     out, off, status = net.join_batch(specs)
     check_batch(rnmod, orc, out, off, status, cases)
+    # and in a captured plan, replayed
+    q, keep = net.make_queries(specs)
+    plan = net.plan(q)
+    for _ in range(2):
+        out, off, status = plan.run()
+        check_batch(rnmod, orc, out, off, status, cases)
+    plan.close()
 
 
 def test_invalid_query_gets_empty_segment(rnmod, orc, rg):

@@ -174,3 +174,20 @@ def test_one_hop_answers_with_parallel_arcs(rnmod, orc, rg):
             want = orc.kcp_join(g, R, S, k)
             assert _one_hop(want, g) == (k < 60), (nR, nS, k)
             assert_same(gpu_kcp(rnmod, net, R, S, k), want)
+
+
+def test_one_hop_answers_are_not_searched_again(rnmod, orc, rg):
+    # clustered sets on a mid-size graph: the seeded bound is below two
+    # lightest arcs, so the one-hop kernel answers the query; with its
+    # searches sent to any tier -- the global tier from the start included --
+    # no source is searched again (a repeated search would count its pairs
+    # twice and lower the bound below the k-th distance)
+    g = rg.road_graph(256, 1)
+    R, S = rg.sample_clustered(g, 4096, 4096, 5)
+    net = rnmod.RoadNetwork.from_graph(g)
+    for k in (16, 256):
+        want = orc.kcp_join(g, R, S, k)
+        for hb in (0, 8, 14, rnmod.RN_TABLE_GLOBAL):
+            out, off, status = net.join_batch([{"R": R, "S": S, "k": k, "hash_log2": hb}])
+            assert not status.any()
+            assert_same(rnmod.pairs_to_numpy(out[off[0]:off[1]]), want)
