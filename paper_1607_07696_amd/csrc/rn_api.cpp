@@ -255,12 +255,11 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
     p.off_bins = p.off_work + 64;
     p.off_sort = round_up(p.off_bins + (p.nbins ? bucket_words(p.nbins) : 0), 64);
     p.block_words = p.off_sort + sort_hist_words();
-    // the pass-0 histogram is written whole and the digit totals before use;
-    // the histograms later passes accumulate start at zero; the bucket sort
-    // needs only its bin counts cleared (either way the clearing covers the
-    // call state, histograms and the global tier's counter before them)
-    p.zero_words = p.nbins ? p.off_bins + p.nbins
-                           : p.off_sort + static_cast<size_t>(p.max_passes + 1) * 256u * 256u;
+    // the sort's histograms and digit totals are written whole before use;
+    // the bucket sort needs its bin counts cleared (either way the clearing
+    // covers the call state, histograms and the global tier's counter before
+    // them)
+    p.zero_words = p.nbins ? p.off_bins + p.nbins : p.off_bins;
     p.off_ebase = round_up(static_cast<size_t>(nq) * sizeof(QueryDesc), 16);
     p.off_rbase = round_up(p.off_ebase + static_cast<size_t>(nq + 1) * sizeof(unsigned long long), 16);
     p.off_perm = round_up(p.off_rbase + static_cast<size_t>(nq + 1) * sizeof(uint32_t), 16);
@@ -556,10 +555,6 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
 
 rn_status enqueue_sort_fallback(const Workspace &ws, const Prepared &p, rn_pair *out, int64_t cap, hipStream_t s) {
     const CallBuffers b = call_buffers(ws, p);
-    // the radix sort's histograms start cleared (the bucket scan kept its
-    // chunk map there)
-    RN_HIP(launch_fill_u32(b.sort_hist, static_cast<uint64_t>(p.max_passes + 1) * 256u * 256u, 0u, s),
-           "clearing the sort histograms");
     RN_HIP(launch_sort_out(b, 1, p.max_passes, p.vb, out, static_cast<unsigned long long>(cap), s), "sorting pairs");
     return RN_OK;
 }

@@ -1543,27 +1543,59 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                         const bool go = nd[j] <= bound && nd[j] < kInf;
                         old[j] = go ? gmin64(&word[yl], (static_cast<unsigned long long>(nd[j]) << 32) | (round + 1u)) : 0ull;
                     }
+                    // what each relaxation appends: its vertex to the touched list
+                    // (first distance), the next round's frontier (below the
+                    // bucket's end, not queued yet) or the far list; the wave's
+                    // places on the three lists come from one LDS atomic each, issued
+                    // together
+                    uint64_t mt[kGJ], mq[kGJ], mf[kGJ];
+                    uint32_t nt = 0, nq = 0, nfr = 0;
+#pragma unroll
+                    for (uint32_t j = 0; j < kGJ; ++j) {
+                        const uint32_t od = word_dist(old[j]);
+                        const bool imp = nd[j] < od;
+                        const bool queued = static_cast<uint32_t>(old[j]) == round + 1u && od < thr;
+                        mt[j] = __ballot(imp && od == kInf);
+                        mq[j] = __ballot(imp && nd[j] < thr && !queued);
+                        mf[j] = __ballot(imp && nd[j] >= thr && (od == kInf || static_cast<uint32_t>(old[j]) == 0u));
+                        nt += popc(mt[j]);
+                        nq += popc(mq[j]);
+                        nfr += popc(mf[j]);
+                    }
+                    uint32_t bt = 0, bq = 0, bf = 0;
+                    if (lane == 0) {
+                        if (nt) bt = atomicAdd(&G.ntouched, nt);
+                        if (nq) bq = atomicAdd(&G.nf[nxt], nq);
+                        if (nfr) bf = atomicAdd(&G.nfar, nfr);
+                    }
+                    bt = readlane(bt, 0);
+                    bq = readlane(bq, 0);
+                    bf = readlane(bf, 0);
 #pragma unroll
                     for (uint32_t j = 0; j < kGJ; ++j) {
                         const uint32_t yl = static_cast<uint32_t>(r[j].y) - voff;
-                        const uint32_t od = word_dist(old[j]);
-                        const bool imp = nd[j] < od;
-                        const bool fresh = imp && od == kInf;
-                        const uint32_t ti = block_append(fresh, &G.ntouched);
-                        if (fresh) {
-                            touched[ti] = yl;
+                        const uint64_t bit = 1ull << lane;
+                        if (mt[j] & bit) {
+                            touched[bt + mbcnt(mt[j])] = yl;
                             if (probe_on && ((c.sbits[yl >> 5] >> (yl & 31u)) & 1u)) {
                                 atomicAdd(&probe_hist(c)[dist_bin(nd[j])], 1u);
                                 atomicAdd(probe_count(c), 1u);
                             }
                         }
-                        const bool queued = static_cast<uint32_t>(old[j]) == round + 1u && od < thr;
-                        const bool queue = imp && nd[j] < thr && !queued;
-                        frontier_push(G, nxt, spill_nxt, queue, static_cast<uint32_t>(r[j].y), r[j].ybeg,
-                                      static_cast<uint32_t>(r[j].yend - r[j].ybeg));
-                        const bool tofar = imp && nd[j] >= thr && (od == kInf || static_cast<uint32_t>(old[j]) == 0u);
-                        const uint32_t ri = block_append(tofar, &G.nfar);
-                        if (tofar) far[ri] = yl;
+                        if (mq[j] & bit) {
+                            const uint32_t fi = bq + mbcnt(mq[j]);
+                            if (fi < kGF) {
+                                G.fy[nxt][fi] = static_cast<uint32_t>(r[j].y);
+                                G.fb[nxt][fi] = r[j].ybeg;
+                                G.fd[nxt][fi] = static_cast<uint32_t>(r[j].yend - r[j].ybeg);
+                            } else {
+                                spill_nxt[fi - kGF] = static_cast<uint32_t>(r[j].y);
+                            }
+                        }
+                        if (mf[j] & bit) far[bf + mbcnt(mf[j])] = yl;
+                        bt += popc(mt[j]);
+                        bq += popc(mq[j]);
+                        bf += popc(mf[j]);
                     }
                 }
             }
@@ -2015,9 +2047,8 @@ __global__ __launch_bounds__(1024) void k_layout(CallBuffers b, int selected, ui
 // ------------------------------------------------------------------ radix sort
 // Records are ordered by the key (q, d, u, v): v in bits [0, vb), u in
 // [vb, 2vb), d in [2vb, 2vb + db), q above, sorted by 8-bit digits from the
-// least significant, two launches per digit: a scan of the per-tile digit
-// histogram (which the previous pass accumulated for the tiles its items
-// landed in) and the stable scatter.  db and the number of digits come from
+// least significant, three launches per digit: the per-tile digit histogram,
+// its scan, and the stable scatter.  db and the number of digits come from
 // the device (k_layout); launches for digits beyond it return at once.
 constexpr uint32_t kSortBlocks = 256;
 // words of the radix sort's scratch region (per pass a [256 digits][kSortBlocks
@@ -2063,19 +2094,6 @@ __device__ __forceinline__ uint32_t chunk_rank(bool act, uint32_t dg, uint32_t (
     return off + wrank;
 }
 
-// hist[key] += 1 for every active lane (key < 2^16), with one atomic per
-// distinct key of the wave: lanes find their peers by the key's bits.
-__device__ __forceinline__ void wave_count16(bool act, uint32_t key, uint32_t *hist) {
-    uint64_t peers = __ballot(act);
-#pragma unroll
-    for (int b = 0; b < 16; ++b) {
-        const bool set = (key >> b) & 1u;
-        const uint64_t m = __ballot(act && set);
-        peers &= set ? m : ~m;
-    }
-    if (act && mbcnt(peers) == 0) atomicAdd(&hist[key], popc(peers));
-}
-
 // Exclusive scan over 256 threads (4 waves) through LDS scratch ws[4].
 __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *ws) {
     const uint32_t tid = threadIdx.x;
@@ -2088,16 +2106,20 @@ __device__ __forceinline__ uint32_t block_excl_scan_256(uint32_t v, uint32_t *ws
     return off + incl - v;
 }
 
-// Pass-0 digit histogram per tile, laid out [digit][tile].
-__global__ __launch_bounds__(256) void k_sort_hist0(const Rec *in, const CallCtl *ctl, unsigned long long cap,
-                                                    uint32_t vb, uint32_t *hist) {
+// One pass's digit histogram per tile, laid out [digit][tile], counted in
+// LDS over the tile the pass's scatter will read (plain stores: no global
+// atomics, whose hot words made passes with a skewed digit up to 15 times
+// slower).  Launches beyond ctl->sort_passes return at once.
+__global__ __launch_bounds__(256) void k_sort_hist(const Rec *in, const CallCtl *ctl, unsigned long long cap,
+                                                   uint32_t vb, uint32_t pass, uint32_t *hist) {
     __shared__ uint32_t h[256];
+    if (pass >= ctl->sort_passes) return;
     h[threadIdx.x] = 0;
     __syncthreads();
     uint64_t beg, end, tile;
     sort_tile(&ctl->nsel, cap, beg, end, tile);
     const uint32_t db = ctl->sort_db;
-    for (uint64_t i = beg + threadIdx.x; i < end; i += 256) atomicAdd(&h[rec_digit(in[i], 0u, vb, db)], 1u);
+    for (uint64_t i = beg + threadIdx.x; i < end; i += 256) atomicAdd(&h[rec_digit(in[i], 8u * pass, vb, db)], 1u);
     __syncthreads();
     hist[threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
@@ -2114,18 +2136,17 @@ __global__ __launch_bounds__(256) void k_sort_scan(uint32_t *hist, uint32_t *tot
     if (tid == kSortBlocks - 1) tot[d] = e + v;
 }
 
-// One digit pass.  hist: this pass's scanned [256][tiles] histogram; the
-// pass accumulates the next digit per output tile into hist_next.  The last
-// pass writes each query's first nout records to the caller's buffer at the
-// query's offset, when the records all fit and the output fits user_cap.
+// One digit pass.  hist: this pass's scanned [256][tiles] histogram.  The
+// last pass writes each query's first nout records to the caller's buffer at
+// the query's offset, when the records all fit and the output fits user_cap.
 __global__ __launch_bounds__(256) void k_sort_pass(const Rec *in, Rec *out, CallBuffers b, uint32_t pass,
                                                    uint32_t vb, const uint32_t *hist, const uint32_t *tot,
-                                                   uint32_t *hist_next, rn_pair *user_out,
+                                                   rn_pair *user_out,
                                                    unsigned long long user_cap) {
     __shared__ uint32_t base[256];
     __shared__ uint32_t wcnt[4][256];
     __shared__ uint32_t ws[4];
-    const uint32_t tid = threadIdx.x, nb = gridDim.x;
+    const uint32_t tid = threadIdx.x;
     const CallCtl *ctl = b.ctl;
     const uint32_t passes = ctl->sort_passes;
     if (pass >= passes) return;
@@ -2163,13 +2184,6 @@ __global__ __launch_bounds__(256) void k_sort_pass(const Rec *in, Rec *out, Call
             } else {
                 out[pos] = r;
             }
-        }
-        if (!last) {
-            // the next digit's per-tile count: one atomic per distinct (digit,
-            // tile) of the wave (skewed digits would otherwise pile every
-            // lane's atomic onto a few words)
-            const uint32_t key = act ? rec_digit(r, shift + 8u, vb, db) * nb + pos / static_cast<uint32_t>(tile) : 0u;
-            wave_count16(act, key, hist_next);
         }
         __syncthreads();
         base[tid] += wcnt[0][tid] + wcnt[1][tid] + wcnt[2][tid] + wcnt[3][tid];
@@ -2474,11 +2488,11 @@ hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_pass
     uint32_t *tot = hist + (kSortPassesMax + 1) * hw;
     Rec *in = selected ? b.recs[1] : b.recs[0];
     Rec *o = selected ? b.recs[0] : b.recs[1];
-    hipLaunchKernelGGL(k_sort_hist0, dim3(kSortBlocks), dim3(256), 0, s, in, b.ctl, b.rec_cap, vb, hist);
     for (uint32_t p = 0; p < max_passes; ++p) {
+        hipLaunchKernelGGL(k_sort_hist, dim3(kSortBlocks), dim3(256), 0, s, in, b.ctl, b.rec_cap, vb, p, hist + p * hw);
         hipLaunchKernelGGL(k_sort_scan, dim3(256), dim3(256), 0, s, hist + p * hw, tot + p * 256u, b.ctl, p);
         hipLaunchKernelGGL(k_sort_pass, dim3(kSortBlocks), dim3(256), 0, s, in, o, b, p, vb, hist + p * hw,
-                           tot + p * 256u, hist + (p + 1) * hw, out, user_cap);
+                           tot + p * 256u, out, user_cap);
         Rec *t = in;
         in = o;
         o = t;
