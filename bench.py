@@ -443,7 +443,7 @@ def partition_study(torch, rn, g, R, S, theta, arcs, steps):
     Rs = torch.as_tensor(perm[R], device="cuda")
     Ss = torch.as_tensor(perm[S], device="cuda")
     for name, a, leaf in (("shuffled ids, none", None, None), ("shuffled ids, 1,256", 1.0, 256),
-                          ("shuffled ids, 0.5,256", 0.5, 256)):
+                          ("shuffled ids, 0.5,256", 0.5, 256), ("shuffled ids, 0,256", 0.0, 256)):
         net = rn.RoadNetwork.from_graph(gs)
         part_s = None
         if a is not None:
