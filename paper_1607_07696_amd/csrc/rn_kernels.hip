@@ -2358,38 +2358,8 @@ __global__ __launch_bounds__(1024) void k_sort_small(CallBuffers b, uint32_t qb,
         s_k[i] = key;
     }
     __syncthreads();
-    // Stages whose partners lie within the same 64-key segment (j < 64) run
-    // in registers: wave w holds segments w, w + 16, ... (lane l the key 64 s
-    // + l of each), and a lane trades with lane l ^ j by a shuffle, without a
-    // barrier; only stages with j >= 64 go through LDS.
-    constexpr uint32_t kSeg = kSmallSort / 1024;   // segments per wave
-    const uint32_t lane = tid & 63u, wave = tid >> 6;
-    auto reg_stages = [&](uint32_t k, uint32_t jtop) {
-        unsigned long long v[kSeg];
-#pragma unroll
-        for (uint32_t g = 0; g < kSeg; ++g) {
-            const uint32_t e = (wave + 16u * g) * 64u + lane;
-            v[g] = e < P ? s_k[e] : ~0ull;
-        }
-        for (uint32_t j = jtop; j > 0; j >>= 1) {
-#pragma unroll
-            for (uint32_t g = 0; g < kSeg; ++g) {
-                const uint32_t e = (wave + 16u * g) * 64u + lane;
-                const unsigned long long o = __shfl_xor(v[g], static_cast<int>(j));
-                const bool up = (e & k) == 0u, low = (e & j) == 0u;
-                v[g] = (low == up) ? (v[g] < o ? v[g] : o) : (v[g] < o ? o : v[g]);
-            }
-        }
-#pragma unroll
-        for (uint32_t g = 0; g < kSeg; ++g) {
-            const uint32_t e = (wave + 16u * g) * 64u + lane;
-            if (e < P) s_k[e] = v[g];
-        }
-        __syncthreads();
-    };
     for (uint32_t k = 2; k <= P; k <<= 1) {
-        uint32_t j = k >> 1;
-        for (; j >= 64u; j >>= 1) {
+        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
             for (uint32_t i = tid; i < P / 2; i += 1024) {
                 const uint32_t lo = ((i & ~(j - 1u)) << 1) | (i & (j - 1u)), hi = lo + j;
                 const bool up = (lo & k) == 0u;
@@ -2401,7 +2371,6 @@ __global__ __launch_bounds__(1024) void k_sort_small(CallBuffers b, uint32_t qb,
             }
             __syncthreads();
         }
-        reg_stages(k, j);
     }
     const unsigned long long vm = (1ull << vb) - 1ull, dm = (1ull << db) - 1ull;
     for (uint32_t i = tid; i < n; i += 1024) {
