@@ -227,10 +227,12 @@ constexpr uint32_t compact_disp_bits(int hash_log2) { return hash_log2 >= 14 ? 5
 constexpr uint32_t compact_max_dist(int hash_log2) {
     return (1u << (7u + static_cast<uint32_t>(hash_log2) - compact_disp_bits(hash_log2))) - 2u;
 }
-// Compact tables are used from this size on: below it the one-wave searches
-// are bound by instruction issue, not by residency, and the wide table's
-// simpler arithmetic is faster (2^11 at theta = 3000: 0.266 against 0.285 ms).
-constexpr int kCompactMinHB = 12;
+// Compact tables are used from this size on.  Their 12 KiB (2^11) and 8 KiB
+// (2^10) per search hold 12 and 18 searches per CU against the wide tables' 8
+// and 12, which outweighs their longer arithmetic (2^11 at theta = 3000:
+// 0.224 against 0.268 ms); at 2^9 both hold 18 or more, and the wide table's
+// simpler arithmetic is faster.
+constexpr int kCompactMinHB = 10;
 hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, bool compact, uint32_t max_sources,
                        bool persistent, hipStream_t s);
 int join_tier_supported(int hash_log2);

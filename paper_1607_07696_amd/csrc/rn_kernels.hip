@@ -2388,6 +2388,20 @@ __global__ __launch_bounds__(1024) void k_sort_small(CallBuffers b, uint32_t qb,
     }
 }
 
+// Blocks of `lds` bytes of LDS that one CU holds at once.  A CU's LDS is
+// handed out in 128 equal granules (1 280 bytes of the 160 KiB on gfx950), a
+// block taking whole granules, while the occupancy query counts bytes: it
+// answers 13 for blocks of 12 KiB, of which 12 fit (10 granules each), and a
+// persistent grid sized by it leaves the 13th block of every CU waiting for a
+// whole block's lifetime.  (Measured with blocks that hold LDS and spin:
+// 6 144, 8 192, 12 288 and 16 384 bytes give 25, 18, 12 and 9 blocks; 10 240,
+// 11 264, 20 480, 24 576 and 28 672 give what the query says.)
+int lds_resident_blocks(size_t lds, size_t lds_per_cu) {
+    if (lds == 0 || lds_per_cu < 128) return 1 << 20;
+    const size_t gran = lds_per_cu / 128;
+    return static_cast<int>(lds_per_cu / ((lds + gran - 1) / gran * gran));
+}
+
 template <int HB, bool GEN, bool CT>
 hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, bool persistent, hipStream_t s) {
     static int resident = 0;  // blocks per CU, per device this process uses first
@@ -2402,8 +2416,13 @@ hipError_t launch_join_tier(const JoinArgs &a, uint32_t max_sources, bool persis
         int occ = 0;
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_join<HB, GEN, CT>, 64 * Tier<HB, CT>::NW, 0);
         if (e != hipSuccess) return e;
+        hipFuncAttributes fa;
+        e = hipFuncGetAttributes(&fa, reinterpret_cast<const void *>(&k_join<HB, GEN, CT>));
+        if (e != hipSuccess) return e;
         cus = prop.multiProcessorCount;
-        resident = occ > 0 ? occ : 1;
+        const int fit = lds_resident_blocks(fa.sharedSizeBytes, prop.maxSharedMemoryPerMultiProcessor);
+        resident = occ < fit ? occ : fit;
+        if (resident < 1) resident = 1;
     }
     // persistent: as many blocks as fit on the device at once, each looping
     // over sources; otherwise one block per source, so that the kernel's

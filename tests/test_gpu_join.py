@@ -105,6 +105,23 @@ def test_table_tiers_and_reruns(rnmod, orc, rg, g64, hash_log2):
         assert st["retried"] > 0          # the small first table overflowed and was re-run
 
 
+@pytest.mark.parametrize("hash_log2", [10, 11])
+def test_wide_tables_for_distances_beyond_the_compact_word(rnmod, orc, rg, hash_log2):
+    # theta above the largest distance a compact table of this size holds, so
+    # the first tier is the wide table; the whole 20x20 graph fits it
+    g = rg.road_graph(20, 3)
+    g.w = (g.w * 64).astype(np.uint32)
+    net = rnmod.RoadNetwork.from_graph(g)
+    net.set_tuning(hash_log2=hash_log2)
+    net.set_profiling(times=True, work=False)
+    R, S = rg.sample_disjoint(g.V, 48, 200, 12)
+    theta = 90000
+    want = orc.dist_join(g, R, S, theta).pairs
+    assert len(want) > 3000 and int(want["dist"].max()) > 16382
+    assert_same(gpu_join(rnmod, net, R, S, theta), want)
+    assert net.stats()["retried"] == 0
+
+
 def test_whole_graph_ball(rnmod, orc, rg, g64):
     net = rnmod.RoadNetwork.from_graph(g64)
     R, S = rg.sample_disjoint(g64.V, 16, 2000, 10)
