@@ -208,6 +208,7 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         // distance within theta fits the compact word; a k-closest-pairs
         // search whose bound is larger moves on if it meets such a distance
         gr.compact = gr.compact && hb[i] >= kCompactMinHB && hb[i] <= kMaxHB && g->Vmax < kCompactVertices &&
+                     g->A * (g->rev_rpo ? 2 : 1) < static_cast<int64_t>(kCompactArcs) &&
                      (x.k > 0 || x.theta <= compact_max_dist(hb[i]));
     }
     p.rbase[nq] = static_cast<uint32_t>(rw);

@@ -221,6 +221,9 @@ size_t stage_scratch_words(size_t rwords);
 // one that outgrows its table).  persistent: a device-filling grid of blocks
 // that loop over the sources; else one block per source.
 constexpr int32_t kCompactVertices = 1 << 24;
+// ... and the handle's arc records (forward and reversed) number fewer than
+// kCompactArcs: a compact search's window map names an arc in 26 bits
+constexpr uint32_t kCompactArcs = 1u << 26;
 // bits of a compact word that hold a slot's probe distance (longer probe
 // sequences send the search on), and the largest distance the word holds
 constexpr uint32_t compact_disp_bits(int hash_log2) { return hash_log2 >= 14 ? 5u : 4u; }

@@ -24,6 +24,8 @@
 // needed and the result is exact.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "rn_internal.h"
 
 namespace rn {
@@ -167,6 +169,12 @@ struct Tier {
     static constexpr int NW = HB >= 14 ? (CT ? 3 : 8) : (HB == 13 ? 4 : (HB == 12 ? 2 : 1));
     static constexpr int G = 1;
     static constexpr uint32_t W = kWin * G;
+    // window map entries of 4 bytes (the lane expanding the arc's tail, and the
+    // arc's index) instead of 8 (the arc's index and the tail's distance): the
+    // compact 2^11 search then needs 11 KiB of LDS and 14 fit a CU instead of 12
+    // (5% faster at theta = 3000); at 2^10 the 8-byte form is faster (18
+    // searches per CU already), and the larger tables gain no residency
+    static constexpr bool LW = CT && HB >= 11;
 };
 
 // Ring bookkeeping shared by the waves of a block that runs one search
@@ -261,12 +269,15 @@ struct SearchLds<HB, true> {
     static constexpr int PC = Tier<HB, true>::PC;
     uint32_t t[H];              // compact word, kWordNone when empty
     uint2 lst[2][PC];           // as in the wide table
-    uint2 win[Tier<HB, true>::W * Tier<HB, true>::NW];
-    __device__ uint2 *wwin() {
+    using WinEntry = std::conditional_t<Tier<HB, true>::LW, uint32_t, uint2>;
+    WinEntry win[Tier<HB, true>::W * Tier<HB, true>::NW];   // per wave: as in the wide table, or
+                                //   (Tier::LW) window arc -> (lane holding its tail << 26) | arc
+                                //   index (below 2^26), the tail's distance coming over the lanes
+    __device__ WinEntry *wwin() {
         if constexpr (Tier<HB, true>::NW == 1) return win;
         else return win + wave_in_block() * Tier<HB, true>::W;
     }
-    __device__ uint2 *sink() { return wwin() + lane_id(); }
+    __device__ uint2 *sink() { return reinterpret_cast<uint2 *>(wwin()) + lane_id(); }
 };
 
 // ---- table access shared by both layouts
@@ -658,10 +669,12 @@ __device__ __forceinline__ void relax_window(SearchLds<HB, CT> &L, WaveState &st
 
 // Load window arcs j*64 + lane (j < NJ) and relax them.  Every load is issued
 // before any is used; lanes past the window's end load arc 0 and stay idle.
+// 4-byte window entries (Tier::LW) name the lane expanding the arc's tail,
+// whose distance d0 comes over the lanes (ds_bpermute) while the arc loads run.
 template <int HB, bool CT, int NJ>
 __device__ __forceinline__ void window_step(SearchLds<HB, CT> &L, WaveState &st, const SrcCtx &c,
                                             const ArcRec *__restrict__ arcs, uint32_t cnt,
-                                            uint32_t bound) {
+                                            uint32_t bound, uint32_t d0) {
     const uint32_t lane = lane_id();
     int32_t idx[NJ];
     uint32_t od[NJ];
@@ -669,9 +682,16 @@ __device__ __forceinline__ void window_step(SearchLds<HB, CT> &L, WaveState &st,
     for (int j = 0; j < NJ; ++j) {
         const uint32_t t = j * 64 + lane;
         const uint32_t tc = t < cnt ? t : 0u;
-        const uint2 w = L.wwin()[tc];
-        idx[j] = t < cnt ? static_cast<int32_t>(w.x) : 0;
-        od[j] = w.y;
+        if constexpr (Tier<HB, CT>::LW) {
+            const uint32_t e = L.wwin()[tc];
+            idx[j] = t < cnt ? static_cast<int32_t>(e & (kCompactArcs - 1)) : 0;
+            od[j] = static_cast<uint32_t>(__builtin_amdgcn_ds_bpermute(static_cast<int>((e >> 26) << 2),
+                                                                       static_cast<int>(d0)));
+        } else {
+            const uint2 w = L.wwin()[tc];
+            idx[j] = t < cnt ? static_cast<int32_t>(w.x) : 0;
+            od[j] = w.y;
+        }
     }
     ArcRec r[NJ];
     uint32_t nd[NJ];
@@ -753,6 +773,8 @@ __device__ __forceinline__ void expand_chunk(SearchLds<HB, CT> &L, WaveState &st
                                              const uint2 *eb, const bool *valid, const uint32_t *d,
                                              uint32_t bound) {
     constexpr uint32_t W = kWin * G;
+    static_assert(!Tier<HB, CT>::LW || G == 1, "4-byte window entries name the expanding lane, one vertex per lane");
+    static_assert(W * sizeof(uint32_t) >= 64 * sizeof(uint2), "the window area holds the wave's sink");
     uint32_t deg[G];
     int32_t b[G];
     uint32_t sum = 0;
@@ -772,24 +794,26 @@ __device__ __forceinline__ void expand_chunk(SearchLds<HB, CT> &L, WaveState &st
 #pragma unroll
         for (int g = 0; g < G; ++g) {
             const uint32_t lo = max(first, wb), hi = min(first + deg[g], wb + W);
-            for (uint32_t p = lo; p < hi; ++p)
-                L.wwin()[p - wb] = make_uint2(static_cast<uint32_t>(b[g]) + (p - first), d[g]);
+            for (uint32_t p = lo; p < hi; ++p) {
+                if constexpr (Tier<HB, CT>::LW) L.wwin()[p - wb] = (lane_id() << 26) | (static_cast<uint32_t>(b[g]) + (p - first));
+                else L.wwin()[p - wb] = make_uint2(static_cast<uint32_t>(b[g]) + (p - first), d[g]);
+            }
             first += deg[g];
         }
         wave_sync();
         const uint32_t cnt = min(W, total - wb);
         switch ((cnt + 63u) / 64u) {
-            case 1: window_step<HB, CT, 1>(L, st, c, a.arcs, cnt, bound); break;
-            case 2: window_step<HB, CT, 2>(L, st, c, a.arcs, cnt, bound); break;
-            case 3: window_step<HB, CT, 3>(L, st, c, a.arcs, cnt, bound); break;
-            case 4: window_step<HB, CT, 4>(L, st, c, a.arcs, cnt, bound); break;
+            case 1: window_step<HB, CT, 1>(L, st, c, a.arcs, cnt, bound, d[0]); break;
+            case 2: window_step<HB, CT, 2>(L, st, c, a.arcs, cnt, bound, d[0]); break;
+            case 3: window_step<HB, CT, 3>(L, st, c, a.arcs, cnt, bound, d[0]); break;
+            case 4: window_step<HB, CT, 4>(L, st, c, a.arcs, cnt, bound, d[0]); break;
             default:
                 if constexpr (G > 1) {
                     switch ((cnt + 63u) / 64u) {
-                        case 5: window_step<HB, CT, 5>(L, st, c, a.arcs, cnt, bound); break;
-                        case 6: window_step<HB, CT, 6>(L, st, c, a.arcs, cnt, bound); break;
-                        case 7: window_step<HB, CT, 7>(L, st, c, a.arcs, cnt, bound); break;
-                        default: window_step<HB, CT, 8>(L, st, c, a.arcs, cnt, bound); break;
+                        case 5: window_step<HB, CT, 5>(L, st, c, a.arcs, cnt, bound, d[0]); break;
+                        case 6: window_step<HB, CT, 6>(L, st, c, a.arcs, cnt, bound, d[0]); break;
+                        case 7: window_step<HB, CT, 7>(L, st, c, a.arcs, cnt, bound, d[0]); break;
+                        default: window_step<HB, CT, 8>(L, st, c, a.arcs, cnt, bound, d[0]); break;
                     }
                 }
                 break;
