@@ -114,6 +114,22 @@ def kcp_leg(torch, rn, steps):
         net.kcp_join(Rd, Sd, 1024)
         lat.append(time.perf_counter() - a)
         dev.append(net.stats()["total_ms"])
+    eager_pairs = rn.pairs_to_numpy(net.kcp_join(Rd, Sd, 1024)).copy()
+    # the same query captured once into a HIP graph (as the theta-join's timed
+    # steps): each replay runs the whole query and reads its status back
+    net.set_profiling(times=False, work=False)
+    q, keep = net.make_queries([{"R": Rd, "S": Sd, "k": 1024}])
+    plan = net.plan(q, cap=4096)
+    for _ in range(3):
+        plan.run()
+    torch.cuda.synchronize()
+    plat = []
+    for _ in range(steps):
+        a = time.perf_counter()
+        pout, poff, _ = plan.run()
+        plat.append(time.perf_counter() - a)
+    plan_same = int(poff[-1]) == len(eager_pairs) and bool(np.array_equal(rn.pairs_to_numpy(pout), eager_pairs))
+    plan.close()
     # work: arcs out of every vertex within d_k of each source (theta-join at d_k)
     net.set_profiling(times=False, work=True)
     net.dist_join(Rd, Sd, dk)
@@ -125,6 +141,9 @@ def kcp_leg(torch, rn, steps):
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)) * 1e3, 4),
                            "p99": round(float(np.percentile(lat, 99)) * 1e3, 4)},
             "device_ms": round(float(np.median(dev)), 4),
+            "plan_latency_ms": {"p50": round(float(np.percentile(plat, 50)) * 1e3, 4),
+                                "p99": round(float(np.percentile(plat, 99)) * 1e3, 4)},
+            "plan_matches_eager": plan_same,
             "gteps_at_dk": round(arcs_dk / (ms / 1e3) / 1e9, 3),
             "candidates": int(st["pairs"]), "arcs_scanned": int(st["arcs"])}
 

@@ -1904,46 +1904,108 @@ __global__ __launch_bounds__(64) void k_kcp_seed_bound(const QueryDesc *qd, Quer
 // path of two or more arcs is longer, so the pairs within the bound are the
 // direct arcs from a source into S no heavier than it, each at the weight of
 // the pair's lightest arc (parallel arcs: the first lightest).  One thread
-// per source (a source has a few arcs, so a wave per source would idle):
-// count, reserve, then write.  The query's searches are skipped.
-__device__ __forceinline__ bool direct_pair(const JoinArgs &a, const SrcCtx &c, int32_t b, int32_t e, int32_t x,
-                                            uint32_t bound, ArcRec &r) {
-    (void)b;
-    (void)e;
-    r = a.arcs[x];
-    return r.w <= bound && first_of_pair(a, x) && in_s(c, static_cast<uint32_t>(r.y));
+// per source (a source has a few arcs, so a wave per source would idle): its
+// arcs are read kDirectBatch at a time with every load of a batch issued
+// before any is used, the records of a wave's sources of one query are
+// reserved with one pair of atomics, then written.  The query's searches are
+// skipped.
+constexpr int kDirectBatch = 8;
+
+// Bit k: arc x0 + k (below e) gives a pair.  Arcs past e read arc x0 (x0 < e)
+// and fail.
+__device__ __forceinline__ uint32_t direct_batch(const JoinArgs &a, const SrcCtx &c, int32_t x0, int32_t e,
+                                                 uint32_t bound, ArcRec *r) {
+    uint32_t fb[kDirectBatch], sb[kDirectBatch];
+#pragma unroll
+    for (int k = 0; k < kDirectBatch; ++k) r[k] = a.arcs[x0 + k < e ? x0 + k : x0];
+#pragma unroll
+    for (int k = 0; k < kDirectBatch; ++k) {
+        const int32_t x = x0 + k < e ? x0 + k : x0;
+        const uint32_t yl = static_cast<uint32_t>(r[k].y) - static_cast<uint32_t>(c.voff);
+        fb[k] = a.first[static_cast<uint32_t>(x) >> 5] >> (x & 31);
+        sb[k] = c.sbits[yl >> 5] >> (yl & 31u);
+    }
+    uint32_t m = 0;
+#pragma unroll
+    for (int k = 0; k < kDirectBatch; ++k)
+        m |= (x0 + k < e && r[k].w <= bound && (fb[k] & sb[k] & 1u) != 0u) ? (1u << k) : 0u;
+    return m;
 }
 
 __global__ __launch_bounds__(256) void k_kcp_direct(JoinArgs a) {
     const uint32_t n = *a.send;
     const uint32_t i = blockIdx.x * 256u + threadIdx.x;
-    if (i >= n) return;
-    const uint32_t q = a.srcq[i];
-    if (!a.qs[q].direct) return;
-    const SrcCtx c = load_ctx(a, q);
-    const uint32_t bound = c.qs->bound;
-    const int32_t u = a.src[i];
-    const int32_t b = a.row_ptr[c.rpo + u], e = a.row_ptr[c.rpo + u + 1];
-    ArcRec r;
-    uint32_t cnt = 0;
-    for (int32_t x = b; x < e; ++x) cnt += direct_pair(a, c, b, e, x, bound, r) ? 1u : 0u;
-    if (cnt == 0) return;
-    const unsigned long long base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(cnt));
-    atomicAdd(&c.qs->npairs, static_cast<unsigned long long>(cnt));
-    unsigned long long idx = base;
-    for (int32_t x = b; x < e; ++x) {
-        if (!direct_pair(a, c, b, e, x, bound, r)) continue;
-        atomicAdd(&c.hist[kHistEmit + dist_bin(r.w)], 1u);
-        if (idx < a.rec_cap) {
-            const int32_t from = caller_id(a, u, c.voff), to = caller_id(a, r.y, c.voff);
-            Rec o;
-            o.u = c.swapped ? to : from;
-            o.v = c.swapped ? from : to;
-            o.d = r.w;
-            o.q = q;
-            a.recs[idx] = o;
+    const uint32_t lane = lane_id();
+    uint32_t q = 0;
+    bool act = false;
+    if (i < n) {
+        q = a.srcq[i];
+        act = a.qs[q].direct != 0;
+    }
+    const uint64_t mact = __ballot(act);
+    if (mact == 0) return;   // wave-uniform
+    SrcCtx c{};
+    uint32_t bound = 0, cnt = 0, m0 = 0;
+    int32_t u = 0, b = 0, e = 0;
+    ArcRec r[kDirectBatch];
+    if (act) {
+        c = load_ctx(a, q);
+        bound = c.qs->bound;
+        u = a.src[i];
+        b = a.row_ptr[c.rpo + u];
+        e = a.row_ptr[c.rpo + u + 1];
+        m0 = b < e ? direct_batch(a, c, b, e, bound, r) : 0u;   // (a batch reads arc x0 < e)
+        cnt = popc(m0);
+        for (int32_t x0 = b + kDirectBatch; x0 < e; x0 += kDirectBatch) {   // sources of many arcs
+            ArcRec t[kDirectBatch];
+            cnt += popc(direct_batch(a, c, x0, e, bound, t));
         }
-        ++idx;
+    }
+    // reserve: the lanes of the first active lane's query together, the rest alone
+    const int first = __ffsll(static_cast<unsigned long long>(mact)) - 1;
+    const uint32_t q0 = static_cast<uint32_t>(__shfl(static_cast<int>(q), first));
+    const bool same = act && q == q0;
+    const uint32_t cs = same ? cnt : 0u;
+    const uint32_t incl = wave_incl_scan(cs);
+    const uint32_t tot = readlane(incl, 63);
+    unsigned long long base = 0;
+    if (tot != 0) {
+        uint32_t lo = 0, hi = 0;
+        if (static_cast<int>(lane) == first) {
+            const unsigned long long w = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(tot));
+            atomicAdd(&a.qs[q0].npairs, static_cast<unsigned long long>(tot));
+            lo = static_cast<uint32_t>(w);
+            hi = static_cast<uint32_t>(w >> 32);
+        }
+        base = (static_cast<unsigned long long>(static_cast<uint32_t>(__shfl(static_cast<int>(hi), first))) << 32) |
+               static_cast<uint32_t>(__shfl(static_cast<int>(lo), first));
+        base += incl - cs;
+    }
+    if (act && !same && cnt != 0) {
+        base = atomicAdd(&a.ctl->npairs, static_cast<unsigned long long>(cnt));
+        atomicAdd(&c.qs->npairs, static_cast<unsigned long long>(cnt));
+    }
+    if (!act || cnt == 0) return;
+    unsigned long long idx = base;
+    const int32_t from = caller_id(a, u, c.voff);
+    for (int32_t x0 = b; x0 < e; x0 += kDirectBatch) {
+        uint32_t m = m0;
+        if (x0 != b) m = direct_batch(a, c, x0, e, bound, r);
+#pragma unroll
+        for (int k = 0; k < kDirectBatch; ++k) {
+            if (!((m >> k) & 1u)) continue;
+            atomicAdd(&c.hist[kHistEmit + dist_bin(r[k].w)], 1u);
+            if (idx < a.rec_cap) {
+                const int32_t to = caller_id(a, r[k].y, c.voff);
+                Rec o;
+                o.u = c.swapped ? to : from;
+                o.v = c.swapped ? from : to;
+                o.d = r[k].w;
+                o.q = q;
+                a.recs[idx] = o;
+            }
+            ++idx;
+        }
     }
 }
 
