@@ -207,7 +207,10 @@ rn_status prepare(const rn_graph *g, const rn_query *q, int32_t nq, Prepared &p)
         // compact tables: local ids below 2^24, and (theta-joins) every
         // distance within theta fits the compact word; a k-closest-pairs
         // search whose bound is larger moves on if it meets such a distance
+        // (the compact 2^11 search's lists hold 64 entries: with buckets, delta
+        // > 0, too few for its pending sets, so such groups keep wide tables)
         gr.compact = gr.compact && hb[i] >= kCompactMinHB && hb[i] <= kMaxHB && g->Vmax < kCompactVertices &&
+                     (hb[i] != kCompactSmallRingHB || d.delta == 0) &&
                      g->A * (g->rev_rpo ? 2 : 1) < static_cast<int64_t>(kCompactArcs) &&
                      (x.k > 0 || x.theta <= compact_max_dist(hb[i]));
     }

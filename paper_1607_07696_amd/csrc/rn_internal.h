@@ -236,6 +236,8 @@ constexpr uint32_t compact_max_dist(int hash_log2) {
 // 0.224 against 0.268 ms); at 2^9 both hold 18 or more, and the wide table's
 // simpler arithmetic is faster.
 constexpr int kCompactMinHB = 10;
+// The compact table size whose search takes a 128-entry ring (lists of 64).
+constexpr int kCompactSmallRingHB = 11;
 hipError_t launch_join(const JoinArgs &a, int hash_log2, bool generic, bool compact, uint32_t max_sources,
                        bool persistent, hipStream_t s);
 int join_tier_supported(int hash_log2);

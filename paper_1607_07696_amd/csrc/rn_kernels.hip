@@ -156,8 +156,12 @@ struct Tier {
     // list capacity: the ring (2 PC entries) holds a search's pending set (at
     // most about 120 vertices for searches that fit 2^11 entries on road
     // graphs, 250 for 2^13 and 370 for 2^14); sized so that every wide table
-    // from 2^11 on fits 8 waves per CU
-    static constexpr int PC = HB <= 12 ? 128 : (HB == 13 ? 256 : 512);
+    // from 2^11 on fits 8 waves per CU.  The compact 2^11 search takes a ring
+    // of 128 entries: 10 KiB in all, so 16 fit a CU instead of 14 (8% faster at
+    // theta = 3000, and none of the benchmark's 8192 searches outgrew it); a
+    // search that does goes on to the next tier.  Calls with delta > 0 take
+    // the wide 2^11 table instead, whose lists of 128 entries their buckets need
+    static constexpr int PC = (CT && HB == kCompactSmallRingHB) ? 64 : (HB <= 12 ? 128 : (HB == 13 ? 256 : 512));
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
     // waves per search: a large table leaves room for few searches per CU, so
     // several waves share each one (a block): two for 2^12, four for 2^13,
@@ -834,6 +838,7 @@ __device__ __forceinline__ void direct_pairs(SearchLds<HB, CT> &L, const JoinArg
     const uint32_t lane = lane_id();
     const uint32_t bound = current_bound(c);
     const int32_t ub = a.row_ptr[c.rpo + u], ue = a.row_ptr[c.rpo + u + 1];
+    uint2 *const stg = &L.lst[0][0];   // both lists, 2 PC entries: free, no search runs
     uint32_t nst = 0, emitted = 0;
     for (int32_t x0 = ub; x0 < ue; x0 += 64) {
         const int32_t x = x0 + static_cast<int32_t>(lane);
@@ -846,15 +851,15 @@ __device__ __forceinline__ void direct_pairs(SearchLds<HB, CT> &L, const JoinArg
         const uint64_t mM = __ballot(m);
         if (m) atomicAdd(&c.hist[kHistEmit + dist_bin(r.w)], 1u);
         emitted += popc(mM);
-        *(m ? &L.lst[0][nst + mbcnt(mM)] : L.sink()) = make_uint2(r.w, static_cast<uint32_t>(r.y));
+        *(m ? stg + nst + mbcnt(mM) : L.sink()) = make_uint2(r.w, static_cast<uint32_t>(r.y));
         nst += popc(mM);
-        if (nst + 64 > PC) {
+        if (nst + 64 > 2u * PC) {
             wave_sync();
-            flush_pairs<HB, CT>(L, a, c, u, nst, &L.lst[0][0]);
+            flush_pairs<HB, CT>(L, a, c, u, nst, stg);
         }
     }
     wave_sync();
-    flush_pairs<HB, CT>(L, a, c, u, nst, &L.lst[0][0]);
+    flush_pairs<HB, CT>(L, a, c, u, nst, stg);
     if (emitted != 0) tighten_bound(c, tseen);
     wave_sync();
 }
@@ -996,6 +1001,7 @@ __device__ void search_source(SearchLds<HB, CT> &L, const JoinArgs &a, const Src
 
     // ---- emit table entries in S, and clear the table for the next source
     bound = current_bound(c);
+    uint2 *const stg = &L.lst[0][0];   // both lists, 2 PC entries: the search has ended
     uint32_t nst = 0, emitted = 0;
     unsigned long long warcs = 0;
     uint32_t wsettled = 0;
@@ -1024,16 +1030,16 @@ __device__ void search_source(SearchLds<HB, CT> &L, const JoinArgs &a, const Src
             const uint64_t mM = __ballot(m);
             if (c.k && m) atomicAdd(&c.hist[kHistEmit + dist_bin(d[j])], 1u);
             emitted += popc(mM);
-            *(m ? &L.lst[0][nst + mbcnt(mM)] : L.sink()) = make_uint2(d[j], k[j]);
+            *(m ? stg + nst + mbcnt(mM) : L.sink()) = make_uint2(d[j], k[j]);
             nst += popc(mM);
-            if (nst + 64 > static_cast<uint32_t>(PC)) {
+            if (nst + 64 > 2u * PC) {
                 wave_sync();
-                flush_pairs<HB, CT>(L, a, c, u, nst, &L.lst[0][0]);
+                flush_pairs<HB, CT>(L, a, c, u, nst, stg);
             }
         }
     }
     wave_sync();
-    flush_pairs<HB, CT>(L, a, c, u, nst, &L.lst[0][0]);
+    flush_pairs<HB, CT>(L, a, c, u, nst, stg);
     if (c.k && emitted != 0) tighten_bound(c, tseen);
     if (a.count_work && !st.ovf) {
         for (int o = 32; o > 0; o >>= 1) {
