@@ -129,6 +129,27 @@ def test_whole_graph_ball(rnmod, orc, rg, g64):
     assert_same(gpu_join(rnmod, net, R, S, theta), orc.dist_join(g64, R, S, theta).pairs)
 
 
+def test_pending_sets_beyond_the_ring_go_to_the_next_tier(rnmod, orc, rg):
+    # a hub of 300 spokes: the first step from the hub leaves 300 vertices
+    # pending, more than the compact 2^11 search's ring holds, while the
+    # 301 vertices fit its table; the search goes on to the next tier
+    n = 300
+    rng = np.random.default_rng(21)
+    src = np.concatenate([np.zeros(n, dtype=np.int64), np.arange(1, n + 1)])
+    dst = np.concatenate([np.arange(1, n + 1), np.roll(np.arange(1, n + 1), 1)])
+    w = rng.integers(5, 40, size=2 * n)
+    g = rg.from_edges(n + 1, src, dst, w, symmetric=True)
+    net = rnmod.RoadNetwork.from_graph(g)
+    net.set_tuning(hash_log2=11)
+    net.set_profiling(times=True, work=False)
+    R = np.array([0, 7, 150], dtype=np.int32)
+    S = np.setdiff1d(np.arange(n + 1, dtype=np.int32), R)
+    want = orc.dist_join(g, R, S, 200).pairs
+    assert len(want) > 600
+    assert_same(gpu_join(rnmod, net, R, S, 200), want)
+    assert net.stats()["retried"] >= 1
+
+
 def test_global_tier_for_searches_beyond_lds(rnmod, orc, rg):
     g = rg.road_graph(128, 0)                    # ~16k vertices: a whole-graph ball
     net = rnmod.RoadNetwork.from_graph(g)        # outgrows every on-chip table
