@@ -1338,8 +1338,8 @@ __global__ __launch_bounds__((64 * Tier<HB, CT>::NW)) void k_join(JoinArgs a) {
 // An empty word is all ones (no distance, no round); rounds count from 1 per
 // search and every word the search changed is reset at its end.
 constexpr uint32_t kGT = 1024;
-constexpr uint32_t kGJ = 4;
-constexpr uint32_t kGWin = kGT * kGJ;
+constexpr uint32_t kGJ = 4;                         // window arcs per lane
+constexpr uint32_t kGWW = 64 * kGJ;                 // window arcs per wave
 constexpr uint32_t kGF = 4096;                     // LDS frontier entries per round
 constexpr unsigned long long kGEmpty = ~0ull;
 
@@ -1364,43 +1364,27 @@ __device__ __forceinline__ uint32_t block_append(bool want, uint32_t *counter) {
     return readlane(base, leader) + mbcnt(m);
 }
 
-// Exclusive scan over a 1024-thread block (ws: 16 words of LDS); *total gets the sum.
-__device__ __forceinline__ uint32_t block_scan_1024(uint32_t v, uint32_t *ws, uint32_t *total) {
-    const uint32_t tid = threadIdx.x;
-    const uint32_t incl = wave_incl_scan(v);
-    if ((tid & 63u) == 63u) ws[tid >> 6] = incl;
-    __syncthreads();
-    uint32_t off = 0, all = 0;
-    for (uint32_t w = 0; w < kGT / 64; ++w) {
-        const uint32_t x = ws[w];
-        off += w < (tid >> 6) ? x : 0u;
-        all += x;
-    }
-    __syncthreads();
-    *total = all;
-    return off + incl - v;
-}
-
 // The LDS frontier of a global-tier search: two rounds' entries (vertex,
-// first arc, arc count), the expansion window of kGWin arcs and the block's
-// counters.
+// first arc, arc count; by round parity), each wave's expansion window of
+// kGWW arcs and the block's counters.  Frontier counts are kept by round
+// modulo 3: round r reads count r, appends to count r + 1 and clears count
+// r + 2 (round r - 1's, read by then), so that no barrier inside a round is
+// needed before its appends.
 struct GlobalLds {
     uint32_t fy[2][kGF];
     int32_t fb[2][kGF];
     uint32_t fd[2][kGF];
-    int32_t widx[kGWin];      // window: arc index
-    uint16_t worig[kGWin];    //   and the thread whose vertex it leaves
-    uint32_t dx[kGT];         // distance of each thread's frontier vertex
-    uint32_t ws[kGT / 64];
-    uint32_t nf[2];           // frontier entries of each round parity
+    int32_t widx[kGT / 64][kGWW];    // per wave: window arc index
+    uint8_t worig[kGT / 64][kGWW];   //   and the lane whose vertex it leaves
+    uint32_t nf[3];                  // frontier entries, by round modulo 3
     uint32_t ntouched, bound, probing, nfar, kept, dmin, dnext;
 };
 
-// Append vertex y (global id; arcs [beg, beg + deg)) to frontier parity p
-// when want: LDS entries first, then the spill array.
-__device__ __forceinline__ void frontier_push(GlobalLds &G, uint32_t p, uint32_t *spill, bool want, uint32_t y,
-                                              int32_t beg, uint32_t deg) {
-    const uint32_t i = block_append(want, &G.nf[p]);
+// Append vertex y (global id; arcs [beg, beg + deg)) to the frontier of
+// parity p (count ci) when want: LDS entries first, then the spill array.
+__device__ __forceinline__ void frontier_push(GlobalLds &G, uint32_t p, uint32_t ci, uint32_t *spill, bool want,
+                                              uint32_t y, int32_t beg, uint32_t deg) {
+    const uint32_t i = block_append(want, &G.nf[ci]);
     if (!want) return;
     if (i < kGF) {
         G.fy[p][i] = y;
@@ -1446,8 +1430,10 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
             G.fb[1][0] = a.row_ptr[c.rpo + u];
             G.fd[1][0] = static_cast<uint32_t>(a.row_ptr[c.rpo + u + 1] - G.fb[1][0]);
             touched[0] = static_cast<uint32_t>(u - c.voff);
-            G.nf[1] = 1;
+            G.nf[1] = 1;   // round 1
+            G.nf[2] = 0;
             G.nf[0] = 0;
+            G.probing = 0;
             G.ntouched = 1;
             G.nfar = 0;
             G.bound = current_bound(c);
@@ -1459,8 +1445,9 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
         bool probing = false;
         while (true) {
             const uint32_t cur = round & 1u, nxt = cur ^ 1u;
+            const uint32_t cf = round % 3u, af = (round + 1u) % 3u, zf = (round + 2u) % 3u;
             uint32_t *spill_cur = cur ? spill1 : spill0, *spill_nxt = cur ? spill0 : spill1;
-            if (G.nf[cur] == 0) {
+            if (G.nf[cf] == 0) {
                 // no near vertex left: everything below thr is settled
                 const uint32_t nfar = G.nfar;
                 if (nfar == 0) break;
@@ -1499,7 +1486,7 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                     const uint32_t y = yl + voff;
                     const int32_t beg = near ? a.row_ptr[c.rpo + y] : 0;
                     const uint32_t deg = near ? static_cast<uint32_t>(a.row_ptr[c.rpo + y + 1] - beg) : 0u;
-                    frontier_push(G, cur, spill_cur, near, y, beg, deg);
+                    frontier_push(G, cur, cf, spill_cur, near, y, beg, deg);
                     const uint32_t ki = block_append(keep, &G.kept);
                     if (keep) far[ki] = yl;
                     __syncthreads();
@@ -1508,14 +1495,15 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                 __syncthreads();
                 continue;
             }
-            const uint32_t nf = G.nf[cur];
-            uint32_t nb = 0;
-            if (tid == 0) {
-                G.nf[nxt] = 0;              // (no thread reads it before the barriers below)
-                nb = current_bound(c);      // used from the first window on
-            }
-            for (uint32_t cb = 0; cb < nf; cb += kGT) {
-                const uint32_t t = cb + tid;
+            const uint32_t nf = G.nf[cf];
+            if (tid == 0) G.nf[zf] = 0;   // (read in round - 1; appended to from round + 1 on)
+            // each wave expands 64 frontier entries at a time with a window of
+            // its own: no block barrier until the round's end
+            const uint32_t bound = current_bound(c);
+            const bool probe_on = G.probing != 0;
+            const uint32_t wv = tid >> 6;
+            for (uint32_t cb = wv * 64u; cb < nf; cb += kGT) {
+                const uint32_t t = cb + lane;
                 const bool valid = t < nf;
                 uint32_t y = 0, deg = 0;
                 int32_t beg = 0;
@@ -1532,42 +1520,34 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                 }
                 // the vertex's current distance, read while the scan and the arcs
                 // proceed (an entry queued earlier may have improved since)
-                const unsigned long long wx = valid ? gload64(&word[y - voff]) : kGEmpty;
-                uint32_t total;
-                const uint32_t excl = block_scan_1024(deg, G.ws, &total);
-                for (uint32_t wb = 0; wb < total; wb += kGWin) {
-                    const uint32_t lo = max(excl, wb), hi = min(excl + deg, wb + kGWin);
+                const uint32_t dl = valid ? word_dist(gload64(&word[y - voff])) : kInf;
+                const uint32_t incl = wave_incl_scan(deg);
+                const uint32_t excl = incl - deg;
+                const uint32_t total = readlane(incl, 63);
+                for (uint32_t wb = 0; wb < total; wb += kGWW) {
+                    const uint32_t lo = max(excl, wb), hi = min(excl + deg, wb + kGWW);
                     for (uint32_t p = lo; p < hi; ++p) {
-                        G.widx[p - wb] = beg + static_cast<int32_t>(p - excl);
-                        G.worig[p - wb] = static_cast<uint16_t>(tid);
+                        G.widx[wv][p - wb] = beg + static_cast<int32_t>(p - excl);
+                        G.worig[wv][p - wb] = static_cast<uint8_t>(lane);
                     }
-                    __syncthreads();   // window map written
-                    const uint32_t cnt = min(kGWin, total - wb);
+                    const uint32_t cnt = min(kGWW, total - wb);
                     ArcRec r[kGJ];
                     uint32_t org[kGJ];
 #pragma unroll
                     for (uint32_t j = 0; j < kGJ; ++j) {
-                        const uint32_t e = j * kGT + tid;
-                        r[j] = a.arcs[e < cnt ? G.widx[e] : 0];
-                        org[j] = e < cnt ? G.worig[e] : kGT;
+                        const uint32_t e = j * 64u + lane;
+                        r[j] = a.arcs[e < cnt ? G.widx[wv][e] : 0];
+                        org[j] = e < cnt ? G.worig[wv][e] : 64u;
                     }
-                    // while the arcs load: the frontier distances, the bound
-                    // and (k-closest pairs, every 8th round, wave 0) the
-                    // discovery count go to LDS
-                    if (wb == 0) G.dx[tid] = word_dist(wx);
-                    if (cb == 0 && wb == 0) {
-                        if (tid < 64 && c.hist != nullptr && (round & 7u) == 1u) probe_phase(c, pnew, probing, seen);
-                        if (tid == 0) {
-                            G.bound = nb;
-                            G.probing = probing ? 1u : 0u;
-                        }
-                    }
-                    __syncthreads();   // (the window map may be rewritten after this barrier)
-                    const uint32_t bound = G.bound;
-                    const bool probe_on = G.probing != 0;
+                    wave_sync();   // the window map is read before the next window rewrites it
                     uint32_t nd[kGJ];
 #pragma unroll
-                    for (uint32_t j = 0; j < kGJ; ++j) nd[j] = org[j] < kGT ? sat_add(G.dx[org[j]], r[j].w) : kInf;
+                    for (uint32_t j = 0; j < kGJ; ++j) {
+                        // the tail's distance, from the lane expanding it
+                        const uint32_t od = static_cast<uint32_t>(
+                            __builtin_amdgcn_ds_bpermute(static_cast<int>((org[j] & 63u) << 2), static_cast<int>(dl)));
+                        nd[j] = org[j] < 64u ? sat_add(od, r[j].w) : kInf;
+                    }
                     unsigned long long old[kGJ];
                     uint32_t sw[kGJ];   // (k-closest pairs, counting: the S-bitmap word of the target)
 #pragma unroll
@@ -1602,7 +1582,7 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                     uint32_t bt = 0, bq = 0, bf = 0;
                     if (lane == 0) {
                         if (nt) bt = atomicAdd(&G.ntouched, nt);
-                        if (nq) bq = atomicAdd(&G.nf[nxt], nq);
+                        if (nq) bq = atomicAdd(&G.nf[af], nq);
                         if (nfr) bf = atomicAdd(&G.nfar, nfr);
                     }
                     bt = readlane(bt, 0);
@@ -1635,6 +1615,12 @@ __global__ __launch_bounds__(1024) void k_join_global(JoinArgs a, uint32_t *slot
                         bf += popc(mf[j]);
                     }
                 }
+            }
+            // (k-closest pairs, every 8th round, wave 0) the discovery count
+            // lowers the bound; whether to keep counting is read next round
+            if (tid < 64 && c.hist != nullptr && (round & 7u) == 1u) {
+                probe_phase(c, pnew, probing, seen);
+                if (tid == 0) G.probing = probing ? 1u : 0u;
             }
             ++round;
             __syncthreads();
