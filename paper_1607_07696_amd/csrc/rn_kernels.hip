@@ -468,10 +468,12 @@ __device__ __forceinline__ void relax_window(SearchLds<HB, CT> &L, WaveState &st
                                              const ArcRec *r, const uint32_t *nd, uint32_t bound) {
     constexpr uint32_t H = Tier<HB, CT>::H;
     // slot states: 0 idle, 1 slot holds y, 2 slot claimed for y, 3 keep probing;
-    // after the min: 4 improved a pending vertex, 5 improved an idle or new
-    // one, which this lane appends
+    // after the min, flags: the distance improved (imp), and the vertex was
+    // idle or new, so this lane appends it (app)
     uint32_t h[NJ], stt[NJ], old[NJ];
     bool fresh[NJ];   // the slot was empty before this window: a new table entry
+    bool app[NJ];     // this lane appends the vertex (it was idle or new, and improved)
+    bool imp[NJ];     // the vertex's distance improved
     // a distance the table's word cannot hold (possible only when the bound
     // itself is that large) sends the search on to the next tier
     constexpr uint32_t kMaxWord = CT ? Compact<HB>::MAXD : kPackMax;
@@ -539,8 +541,9 @@ __device__ __forceinline__ void relax_window(SearchLds<HB, CT> &L, WaveState &st
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             fresh[j] = stt[j] == 2u;
-            if (stt[j] == 1u && nw[j] < old[j]) stt[j] = (old[j] & K::PEND) == 0u ? 5u : 4u;
-            else if (stt[j] == 2u) stt[j] = 5u;
+            const bool better = stt[j] == 1u && nw[j] < old[j];
+            imp[j] = fresh[j] || better;
+            app[j] = fresh[j] || (better && (old[j] & K::PEND) == 0u);
         }
     } else {
 #pragma unroll
@@ -596,22 +599,22 @@ __device__ __forceinline__ void relax_window(SearchLds<HB, CT> &L, WaveState &st
         __builtin_amdgcn_sched_barrier(0);   // every min is issued before the first result is used
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            stt[j] = (v[j] < old[j]) ? ((old[j] == kWordNone || (old[j] & 1u) == 0u) ? 5u : 4u) : stt[j];
-            fresh[j] = old[j] == kWordNone && stt[j] >= 4u;
+            imp[j] = v[j] < old[j];
+            app[j] = imp[j] && (old[j] == kWordNone || (old[j] & 1u) == 0u);
+            fresh[j] = imp[j] && old[j] == kWordNone;
         }
     }
     uint64_t mA[NJ];
     uint32_t nadd = 0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const bool imp = stt[j] >= 4u;
-        st.imin = min(st.imin, imp ? nd[j] : kInf);
-        mA[j] = __ballot(stt[j] == 5u);
+        st.imin = min(st.imin, imp[j] ? nd[j] : kInf);
+        mA[j] = __ballot(app[j]);
         nadd += popc(mA[j]);
     }
     if (c.big_deg) {   // list entries hold arc counts below 2^16
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) lost |= stt[j] == 5u && (r[j].yend - r[j].ybeg) > 0xFFFF;
+        for (int j = 0; j < NJ; ++j) lost |= app[j] && (r[j].yend - r[j].ybeg) > 0xFFFF;
     }
     uint32_t ins = 0;
 #pragma unroll
@@ -646,8 +649,7 @@ __device__ __forceinline__ void relax_window(SearchLds<HB, CT> &L, WaveState &st
         }
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
-            const bool app = stt[j] == 5u;
-            uint2 *dst = app ? q + ((base + mbcnt(mA[j])) & st.amask) : L.sink();
+            uint2 *dst = app[j] ? q + ((base + mbcnt(mA[j])) & st.amask) : L.sink();
             *dst = make_uint2(h[j] | (static_cast<uint32_t>(r[j].yend - r[j].ybeg) << 16),
                               static_cast<uint32_t>(r[j].ybeg));
             base += popc(mA[j]);
@@ -661,8 +663,7 @@ __device__ __forceinline__ void relax_window(SearchLds<HB, CT> &L, WaveState &st
     uint32_t base = st.tail;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-        const bool app = stt[j] == 5u;
-        uint2 *dst = app ? q + ((base + mbcnt(mA[j])) & st.amask) : L.sink();
+        uint2 *dst = app[j] ? q + ((base + mbcnt(mA[j])) & st.amask) : L.sink();
         *dst = make_uint2(h[j] | (static_cast<uint32_t>(r[j].yend - r[j].ybeg) << 16),
                           static_cast<uint32_t>(r[j].ybeg));
         base += popc(mA[j]);
@@ -942,9 +943,11 @@ __device__ void search_source(SearchLds<HB, CT> &L, const JoinArgs &a, const Src
                 for (int g = 0; g < G; ++g) {
                     const bool later = valid[g] && dd[g] > lim && dd[g] <= bound;
                     const uint64_t mL = __ballot(later);
-                    *(later ? q + ((base + mbcnt(mL)) & (RC - 1u)) : L.sink()) = eb[g];
-                    base += popc(mL);
-                    valid[g] = valid[g] && !later;
+                    if (mL != 0) {   // (wave-uniform)
+                        *(later ? q + ((base + mbcnt(mL)) & (RC - 1u)) : L.sink()) = eb[g];
+                        base += popc(mL);
+                        valid[g] = valid[g] && !later;
+                    }
                 }
                 st.np += base - st.tail;
                 st.tail = base;
