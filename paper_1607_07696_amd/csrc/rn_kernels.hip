@@ -157,9 +157,9 @@ struct Tier {
     // most about 120 vertices for searches that fit 2^11 entries on road
     // graphs, 250 for 2^13 and 370 for 2^14); sized so that every wide table
     // from 2^11 on fits 8 waves per CU.  The compact 2^11 search takes a ring
-    // of 128 entries: 10 KiB in all, so 16 fit a CU instead of 14 (8% faster at
-    // theta = 3000, and none of the benchmark's 8192 searches outgrew it); a
-    // search that does goes on to the next tier.  Calls with delta > 0 take
+    // of 128 entries: 10 KiB in all, so 16 fit a CU instead of 14 (8% faster
+    // on the 1024x1024 road graph at theta = 3000, where none of 8192 searches
+    // outgrew it); a search that does goes on to the next tier.  Calls with delta > 0 take
     // the wide 2^11 table instead, whose lists of 128 entries their buckets need
     static constexpr int PC = (CT && HB == kCompactSmallRingHB) ? 64 : (HB <= 12 ? 128 : (HB == 13 ? 256 : 512));
     static constexpr int U = (H / 64) < 8 ? (H / 64) : 8;   // table rows scanned per batch
@@ -175,9 +175,10 @@ struct Tier {
     static constexpr uint32_t W = kWin * G;
     // window map entries of 4 bytes (the lane expanding the arc's tail, and the
     // arc's index) instead of 8 (the arc's index and the tail's distance): the
-    // compact 2^11 search then needs 11 KiB of LDS and 14 fit a CU instead of 12
-    // (5% faster at theta = 3000); at 2^10 the 8-byte form is faster (18
-    // searches per CU already), and the larger tables gain no residency
+    // compact 2^11 search then needs 11 KiB of LDS with a 256-entry ring (14
+    // fit a CU instead of 12, 5% faster at theta = 3000) and 10 KiB with the
+    // 128-entry ring it takes; at 2^10 the 8-byte form is faster (18 searches
+    // per CU already), and the larger tables gain no residency
     static constexpr bool LW = CT && HB >= 11;
 };
 
