@@ -530,7 +530,10 @@ __device__ __forceinline__ void relax_window(SearchLds<HB, CT> &L, WaveState &st
                 if (round >= K::MAXP) {   // the probe distance field is full
                     lost = lost || more;
 #pragma unroll
-                    for (int j = 0; j < NJ; ++j) stt[j] = stt[j] == 3u ? 0u : stt[j];
+                    for (int j = 0; j < NJ; ++j) {
+                        nw[j] = stt[j] == 3u ? kWordNone : nw[j];
+                        stt[j] = stt[j] == 3u ? 0u : stt[j];
+                    }
                     break;
                 }
             }
@@ -539,12 +542,21 @@ __device__ __forceinline__ void relax_window(SearchLds<HB, CT> &L, WaveState &st
 #pragma unroll
         for (int j = 0; j < NJ; ++j) old[j] = atomicMin(&L.t[stt[j] == 1u ? h[j] : lane_id()], stt[j] == 1u ? nw[j] : kWordNone);
         __builtin_amdgcn_sched_barrier(0);   // every min is issued before the first result is used
+        // a claimed slot compares as a word above every word a vertex can
+        // hold, and not pending: the vertex counts as improved and is
+        // appended by the claiming lane.  Idle lanes carry kWordNone, which
+        // compares above nothing.
+        constexpr uint32_t kClaimed = ~K::PEND;
+        static_assert(((((K::MAXD << 1) | 1u) << K::SH) | K::IDM) < kClaimed, "a claimed slot compares above every word");
 #pragma unroll
         for (int j = 0; j < NJ; ++j) {
             fresh[j] = stt[j] == 2u;
-            const bool better = stt[j] == 1u && nw[j] < old[j];
-            imp[j] = fresh[j] || better;
-            app[j] = fresh[j] || (better && (old[j] & K::PEND) == 0u);
+            const uint32_t o = fresh[j] ? kClaimed : old[j];
+            imp[j] = nw[j] < o;
+            // the vertex is appended if it improved and was idle: a pending
+            // old word is cut to the bits below its pending bit, which every
+            // word exceeds, so that one comparison decides
+            app[j] = nw[j] < (o & ((o & K::PEND) - 1u));
         }
     } else {
 #pragma unroll
@@ -606,20 +618,18 @@ __device__ __forceinline__ void relax_window(SearchLds<HB, CT> &L, WaveState &st
         }
     }
     uint64_t mA[NJ];
-    uint32_t nadd = 0;
+    uint32_t nadd = 0, ins = 0;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         st.imin = min(st.imin, imp[j] ? nd[j] : kInf);
         mA[j] = __ballot(app[j]);
         nadd += popc(mA[j]);
+        ins += popc(__ballot(fresh[j]));
     }
     if (c.big_deg) {   // list entries hold arc counts below 2^16
 #pragma unroll
         for (int j = 0; j < NJ; ++j) lost |= app[j] && (r[j].yend - r[j].ybeg) > 0xFFFF;
     }
-    uint32_t ins = 0;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) ins += popc(__ballot(fresh[j]));
     if constexpr (Tier<HB, CT>::NW == 1) st.nins += ins;
     if (st.probing && ins != 0) {
         // k-closest pairs: a first discovery of an S member is a pair with a
