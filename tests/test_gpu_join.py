@@ -150,6 +150,44 @@ def test_pending_sets_beyond_the_ring_go_to_the_next_tier(rnmod, orc, rg):
     assert net.stats()["retried"] >= 1
 
 
+def _colliding_ids(hb, V, count):
+    """Vertex ids below V whose 24-bit Fibonacci hashes (the compact tables'
+    bijection y -> y * 10368889 mod 2^24) share their top hb bits, so that all
+    of them have the same home slot in a compact table of 2^hb slots."""
+    inv = pow(10368889, -1, 1 << 24)
+    shift = 24 - hb
+    for home in range(1 << hb):
+        z = np.arange(home << shift, (home + 1) << shift, dtype=np.int64)
+        y = (z * inv) & 0xFFFFFF
+        y = np.sort(y[y < V])
+        if len(y) >= count:
+            return y[:count]
+    raise AssertionError("no home slot has enough ids below V")
+
+
+@pytest.mark.parametrize("hb", [10, 11])
+def test_probe_sequences_beyond_the_compact_field_go_to_the_next_tier(rnmod, orc, rg, hb):
+    # a star whose 24 leaves all hash to one home slot of the first (compact)
+    # table: a slot's probe-distance field counts at most 15 slots on, so the
+    # search from the centre gives up on that tier and is re-run on the next;
+    # the pairs are still exact
+    V = 1 << 16
+    leaves = _colliding_ids(hb, V, 24)
+    centre = int(np.setdiff1d(np.arange(V), leaves)[0])
+    rng = np.random.default_rng(31)
+    w = rng.integers(3, 50, size=len(leaves))
+    g = rg.from_edges(V, np.full(len(leaves), centre), leaves, w, symmetric=True)
+    net = rnmod.RoadNetwork.from_graph(g)
+    net.set_tuning(hash_log2=hb)
+    net.set_profiling(times=True, work=False)
+    R = np.array([centre, leaves[0]], dtype=np.int32)
+    S = np.setdiff1d(np.concatenate([[centre], leaves]).astype(np.int32), R)
+    want = orc.dist_join(g, R, S, 120).pairs
+    assert len(want) > 30
+    assert_same(gpu_join(rnmod, net, R, S, 120), want)
+    assert net.stats()["retried"] >= 1
+
+
 def test_global_tier_for_searches_beyond_lds(rnmod, orc, rg):
     g = rg.road_graph(128, 0)                    # ~16k vertices: a whole-graph ball
     net = rnmod.RoadNetwork.from_graph(g)        # outgrows every on-chip table
