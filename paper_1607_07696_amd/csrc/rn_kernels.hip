@@ -2421,9 +2421,42 @@ __global__ __launch_bounds__(256) void k_bucket_rank(CallBuffers b, rn_pair *out
 // One block: the selected records (recs[1], at most kSmallSort) become 64-bit
 // keys (query, dist, u, v) packed as the radix sort orders them (when they fit
 // 63 bits), padded with all-ones keys to a power of two and bitonic-sorted in
-// LDS (one compare-exchange per thread and stage, a barrier per stage); the
-// key gives the record back, which goes to the caller's output at its query's
+// LDS (up to three consecutive stages of a merge per barrier, below); the key
+// gives the record back, which goes to the caller's output at its query's
 // offset.  Too many records or too wide a key: ctl->resort.
+
+// G consecutive stages of bitonic merge k, at compare distances j, j/2, ...,
+// j/2^(G-1) = h, over P keys in LDS: the keys at base + m h (m < 2^G, base
+// with zero bits where m h sits) meet only each other in those stages, so one
+// thread loads the 2^G of them, runs the stages in registers and stores them.
+// Whole block; the caller's barrier follows.
+template <int G>
+__device__ __forceinline__ void bitonic_stages(unsigned long long *s, uint32_t P, uint32_t k, uint32_t j,
+                                               uint32_t tid) {
+    constexpr uint32_t E = 1u << G;
+    const uint32_t h = j >> (G - 1);
+    for (uint32_t i = tid; i < P / E; i += 1024) {
+        const uint32_t base = ((i & ~(h - 1u)) << G) | (i & (h - 1u));
+        const bool up = (base & k) == 0u;   // (the same for the whole group: h * E <= k)
+        unsigned long long x[E];
+#pragma unroll
+        for (uint32_t m = 0; m < E; ++m) x[m] = s[base + m * h];
+#pragma unroll
+        for (uint32_t d = E / 2; d > 0; d >>= 1) {
+#pragma unroll
+            for (uint32_t m = 0; m < E; ++m) {
+                if ((m & d) != 0u) continue;
+                const unsigned long long lo = x[m], hi = x[m + d];
+                const bool swap = (lo > hi) == up;
+                x[m] = swap ? hi : lo;
+                x[m + d] = swap ? lo : hi;
+            }
+        }
+#pragma unroll
+        for (uint32_t m = 0; m < E; ++m) s[base + m * h] = x[m];
+    }
+}
+
 __global__ __launch_bounds__(1024) void k_sort_small(CallBuffers b, uint32_t qb, uint32_t vb, rn_pair *out,
                                                      unsigned long long user_cap) {
     __shared__ unsigned long long s_k[kSmallSort];
@@ -2451,15 +2484,16 @@ __global__ __launch_bounds__(1024) void k_sort_small(CallBuffers b, uint32_t qb,
     }
     __syncthreads();
     for (uint32_t k = 2; k <= P; k <<= 1) {
-        for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-            for (uint32_t i = tid; i < P / 2; i += 1024) {
-                const uint32_t lo = ((i & ~(j - 1u)) << 1) | (i & (j - 1u)), hi = lo + j;
-                const bool up = (lo & k) == 0u;
-                const unsigned long long x = s_k[lo], y = s_k[hi];
-                if ((x > y) == up) {
-                    s_k[lo] = y;
-                    s_k[hi] = x;
-                }
+        for (uint32_t j = k >> 1; j > 0;) {
+            if (j >= 4) {
+                bitonic_stages<3>(s_k, P, k, j, tid);
+                j >>= 3;
+            } else if (j == 2) {
+                bitonic_stages<2>(s_k, P, k, j, tid);
+                j >>= 2;
+            } else {
+                bitonic_stages<1>(s_k, P, k, j, tid);
+                j >>= 1;
             }
             __syncthreads();
         }
