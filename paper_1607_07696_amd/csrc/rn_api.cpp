@@ -542,18 +542,23 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     if (p.any_kcp) RN_HIP(launch_select(b, s), "selecting candidates");
     RN_HIP(launch_layout(b, p.any_kcp ? 1 : 0, p.qb, p.vb, p.nbins != 0, s), "laying out the output");
     record(g, ws, timed, EV_SELECTED, s);
-    if (p.nbins)
+    const size_t state_bytes = sizeof(CallCtl) + static_cast<size_t>(p.nq) * sizeof(QueryState);
+    const uint32_t *state = reinterpret_cast<const uint32_t *>(ws.d_block);
+    const uint32_t state_words = static_cast<uint32_t>(state_bytes / 4);
+    bool published = false;   // the sort's kernel published the call state itself
+    if (p.nbins) {
         RN_HIP(launch_bucket_sort(b, out, static_cast<unsigned long long>(cap), s), "sorting pairs");
-    else if (p.small_sort)
-        RN_HIP(launch_sort_small(b, p.qb, p.vb, out, static_cast<unsigned long long>(cap), s), "sorting pairs");
-    else
+    } else if (p.small_sort) {
+        RN_HIP(launch_sort_small(b, p.qb, p.vb, out, static_cast<unsigned long long>(cap), state, ws.d_state_map,
+                                 state_words, s),
+               "sorting pairs");
+        published = true;
+    } else {
         RN_HIP(launch_sort_out(b, p.any_kcp ? 1 : 0, p.max_passes, p.vb, out, static_cast<unsigned long long>(cap), s),
                "sorting pairs");
+    }
     record(g, ws, timed, EV_DONE, s);
-    const size_t state_bytes = sizeof(CallCtl) + static_cast<size_t>(p.nq) * sizeof(QueryState);
-    RN_HIP(launch_publish(reinterpret_cast<const uint32_t *>(ws.d_block), ws.d_state_map,
-                          static_cast<uint32_t>(state_bytes / 4), s),
-           "publishing the call state");
+    if (!published) RN_HIP(launch_publish(state, ws.d_state_map, state_words, s), "publishing the call state");
     return RN_OK;
 }
 

@@ -2457,9 +2457,8 @@ __device__ __forceinline__ void bitonic_stages(unsigned long long *s, uint32_t P
     }
 }
 
-__global__ __launch_bounds__(1024) void k_sort_small(CallBuffers b, uint32_t qb, uint32_t vb, rn_pair *out,
-                                                     unsigned long long user_cap) {
-    __shared__ unsigned long long s_k[kSmallSort];
+__device__ __forceinline__ void sort_small(const CallBuffers &b, uint32_t qb, uint32_t vb, rn_pair *out,
+                                           unsigned long long user_cap, unsigned long long *s_k) {
     CallCtl *ctl = b.ctl;
     if (ctl->npairs > b.rec_cap || ctl->nout > user_cap) return;
     const uint32_t tid = threadIdx.x;
@@ -2512,6 +2511,17 @@ __global__ __launch_bounds__(1024) void k_sort_small(CallBuffers b, uint32_t qb,
             out[st.off + rel] = p;
         }
     }
+}
+
+// The small sort, then (every exit of it is block-uniform) the call state's
+// copy into mapped host memory, as k_publish does.
+__global__ __launch_bounds__(1024) void k_sort_small(CallBuffers b, uint32_t qb, uint32_t vb, rn_pair *out,
+                                                     unsigned long long user_cap, const uint32_t *state,
+                                                     uint32_t *state_map, uint32_t state_words) {
+    __shared__ unsigned long long s_k[kSmallSort];
+    sort_small(b, qb, vb, out, user_cap, s_k);
+    __syncthreads();   // the state's last writes (ctl->resort) are seen by the whole block
+    for (uint32_t i = threadIdx.x; i < state_words; i += 1024) state_map[i] = state[i];
 }
 
 // Blocks of `lds` bytes of LDS that one CU holds at once.  A CU's LDS is
@@ -2672,8 +2682,9 @@ hipError_t launch_sort_out(const CallBuffers &b, int selected, uint32_t max_pass
 }
 
 hipError_t launch_sort_small(const CallBuffers &b, uint32_t qb, uint32_t vb, rn_pair *out, unsigned long long user_cap,
-                             hipStream_t s) {
-    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, s, b, qb, vb, out, user_cap);
+                             const uint32_t *state, uint32_t *state_map, uint32_t state_words, hipStream_t s) {
+    hipLaunchKernelGGL(k_sort_small, dim3(1), dim3(1024), 0, s, b, qb, vb, out, user_cap, state, state_map,
+                       state_words);
     return hipGetLastError();
 }
 
