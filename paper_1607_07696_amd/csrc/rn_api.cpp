@@ -547,7 +547,9 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     const uint32_t state_words = static_cast<uint32_t>(state_bytes / 4);
     bool published = false;   // the sort's kernel published the call state itself
     if (p.nbins) {
-        RN_HIP(launch_bucket_sort(b, out, static_cast<unsigned long long>(cap), s), "sorting pairs");
+        RN_HIP(launch_bucket_sort(b, out, static_cast<unsigned long long>(cap), state, ws.d_state_map, state_words, s),
+               "sorting pairs");
+        published = true;
     } else if (p.small_sort) {
         RN_HIP(launch_sort_small(b, p.qb, p.vb, out, static_cast<unsigned long long>(cap), state, ws.d_state_map,
                                  state_words, s),

@@ -288,7 +288,10 @@ constexpr int32_t kMaxQueries = 65536;
 constexpr uint32_t kMaxBins = 65536;
 constexpr uint32_t kBucketRankMax = 4096;
 inline size_t bucket_words(uint32_t nbins) { return 4 * static_cast<size_t>(nbins) + 1; }
-hipError_t launch_bucket_sort(const CallBuffers &b, rn_pair *out, unsigned long long user_cap, hipStream_t s);
+// The ranking launch also publishes the call state (state_words words from
+// state to state_map, as launch_publish does), which is final by then.
+hipError_t launch_bucket_sort(const CallBuffers &b, rn_pair *out, unsigned long long user_cap, const uint32_t *state,
+                              uint32_t *state_map, uint32_t state_words, hipStream_t s);
 
 // Small sort, for calls of k-closest-pairs queries only whose k add up to at
 // most kSmallSort / 2: one block sorts the selected records (recs[1]) in LDS

@@ -2378,8 +2378,13 @@ __global__ __launch_bounds__(256) void k_bucket_scatter(CallBuffers b) {
 // query); the record goes to the caller's output at its query's offset.  A
 // wave's work is the size of its bin, at most kBucketRankMax (beyond it the
 // caller takes the radix sort).
-__global__ __launch_bounds__(256) void k_bucket_rank(CallBuffers b, rn_pair *out, unsigned long long user_cap) {
+__global__ __launch_bounds__(256) void k_bucket_rank(CallBuffers b, rn_pair *out, unsigned long long user_cap,
+                                                      const uint32_t *state, uint32_t *state_map, uint32_t state_words) {
     const CallCtl *ctl = b.ctl;
+    // the call state is final once the layout has run (the scatter and this
+    // ranking only read it): block 0 publishes it, as k_publish does
+    if (blockIdx.x == 0)
+        for (uint32_t i = threadIdx.x; i < state_words; i += 256) state_map[i] = state[i];
     if (ctl->npairs > b.rec_cap || ctl->nout > user_cap || ctl->resort) return;
     const uint32_t nb = b.nbins, lane = lane_id();
     const uint32_t *cnt = b.bins, *start = b.bins + nb, *cstart = b.bins + 3 * nb;
@@ -2688,9 +2693,10 @@ hipError_t launch_sort_small(const CallBuffers &b, uint32_t qb, uint32_t vb, rn_
     return hipGetLastError();
 }
 
-hipError_t launch_bucket_sort(const CallBuffers &b, rn_pair *out, unsigned long long user_cap, hipStream_t s) {
+hipError_t launch_bucket_sort(const CallBuffers &b, rn_pair *out, unsigned long long user_cap, const uint32_t *state,
+                              uint32_t *state_map, uint32_t state_words, hipStream_t s) {
     hipLaunchKernelGGL(k_bucket_scatter, dim3(1024), dim3(256), 0, s, b);
-    hipLaunchKernelGGL(k_bucket_rank, dim3(1024), dim3(256), 0, s, b, out, user_cap);
+    hipLaunchKernelGGL(k_bucket_rank, dim3(1024), dim3(256), 0, s, b, out, user_cap, state, state_map, state_words);
     return hipGetLastError();
 }
 
