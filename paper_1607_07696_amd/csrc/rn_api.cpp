@@ -540,7 +540,8 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
     }
     record(g, ws, timed, EV_RELAXED, s);
     if (p.any_kcp) RN_HIP(launch_select(b, s), "selecting candidates");
-    RN_HIP(launch_layout(b, p.any_kcp ? 1 : 0, p.qb, p.vb, p.nbins != 0, s), "laying out the output");
+    const bool small = p.small_sort && p.nbins == 0;   // the small sort lays out the output itself
+    if (!small) RN_HIP(launch_layout(b, p.any_kcp ? 1 : 0, p.qb, p.vb, p.nbins != 0, s), "laying out the output");
     record(g, ws, timed, EV_SELECTED, s);
     const size_t state_bytes = sizeof(CallCtl) + static_cast<size_t>(p.nq) * sizeof(QueryState);
     const uint32_t *state = reinterpret_cast<const uint32_t *>(ws.d_block);
@@ -550,7 +551,7 @@ rn_status enqueue_call(rn_graph *g, Workspace &ws, const Prepared &p, rn_pair *o
         RN_HIP(launch_bucket_sort(b, out, static_cast<unsigned long long>(cap), state, ws.d_state_map, state_words, s),
                "sorting pairs");
         published = true;
-    } else if (p.small_sort) {
+    } else if (small) {
         RN_HIP(launch_sort_small(b, p.qb, p.vb, out, static_cast<unsigned long long>(cap), state, ws.d_state_map,
                                  state_words, s),
                "sorting pairs");

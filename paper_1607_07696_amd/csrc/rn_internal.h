@@ -299,9 +299,10 @@ hipError_t launch_bucket_sort(const CallBuffers &b, rn_pair *out, unsigned long 
 // bits from the device) and writes the output as the radix sort's last pass
 // does; one launch instead of the radix sort's two per digit.  More than
 // kSmallSort records (ties at the bound) or a key wider than 63 bits set
-// ctl->resort, and the caller runs the radix sort.  As the call's last kernel
-// it then publishes the call state as launch_publish does (state_words words
-// from state to state_map), which saves that launch.
+// ctl->resort, and the caller runs the radix sort.  The same block first lays
+// out the output (as launch_layout with selected = 1, which the caller then
+// skips), and, as the call's last kernel, publishes the call state as
+// launch_publish does (state_words words from state to state_map).
 constexpr uint32_t kSmallSort = 4096;
 hipError_t launch_sort_small(const CallBuffers &b, uint32_t qb, uint32_t vb, rn_pair *out, unsigned long long user_cap,
                              const uint32_t *state, uint32_t *state_map, uint32_t state_words, hipStream_t s);

@@ -2121,6 +2121,7 @@ __device__ __forceinline__ void layout_block(const CallBuffers &b, int selected,
                                              unsigned long long *s, uint32_t &s_dmax) {
     const uint32_t tid = threadIdx.x;
     if (tid == 0) s_dmax = 0;
+    __syncthreads();   // cleared before any thread raises it
     unsigned long long cs = 0, co = 0;
     for (uint32_t q0 = 0; q0 < static_cast<uint32_t>(b.nq); q0 += 1024) {
         const uint32_t q = q0 + tid;
@@ -2518,12 +2519,17 @@ __device__ __forceinline__ void sort_small(const CallBuffers &b, uint32_t qb, ui
     }
 }
 
-// The small sort, then (every exit of it is block-uniform) the call state's
-// copy into mapped host memory, as k_publish does.
+// The output layout of the selected records (as k_layout), the small sort,
+// then (every exit of it is block-uniform) the call state's copy into mapped
+// host memory, as k_publish does: one launch for what took three.
 __global__ __launch_bounds__(1024) void k_sort_small(CallBuffers b, uint32_t qb, uint32_t vb, rn_pair *out,
                                                      unsigned long long user_cap, const uint32_t *state,
                                                      uint32_t *state_map, uint32_t state_words) {
     __shared__ unsigned long long s_k[kSmallSort];
+    __shared__ uint32_t s_dmax;
+    static_assert(kSmallSort >= 1024, "the layout's scan uses the sort's keys as scratch");
+    layout_block(b, 1, qb, vb, s_k, s_dmax);
+    __syncthreads();   // the layout's call state (ctl written by thread 0) is seen by the whole block
     sort_small(b, qb, vb, out, user_cap, s_k);
     __syncthreads();   // the state's last writes (ctl->resort) are seen by the whole block
     for (uint32_t i = threadIdx.x; i < state_words; i += 1024) state_map[i] = state[i];
